@@ -1,0 +1,226 @@
+/*
+ * fetdpic.h — C-ABI of the MI355X charge-conserving relativistic FETD-PIC
+ * particle step (2-D, unstructured triangles, Whitney forms).
+ *
+ * Method: Na, Moon, Omelchenko, Teixeira, "Relativistic extension of a
+ * charge-conservative finite element solver for time-dependent
+ * Maxwell-Vlasov equations", arXiv:1707.04333.  One call of
+ * fetd_pic_step advances every particle and the fields by the four PIC
+ * procedures of Sec. II: field update (Sec. II.A, eqs. semi.dis.curl.1/2),
+ * gather through Whitney 1- and 2-forms (Sec. II.B), relativistic push with
+ * the Boris, Boris-with-tan-correction, Vay or Higuera-Cary pusher
+ * (Sec. II.C), and the exactly charge-conserving scatter of the W1 line
+ * integral along each particle's path (Sec. II.D, eq. I.assign).
+ *
+ * Conventions fixed by this interface:
+ *   - SI units.  2-D quantities are per metre of depth: a macro particle of
+ *     a species with charge q and weight w carries Q = q w [C/m].
+ *   - Triangles are given counter-clockwise.  Local edge k of a triangle is
+ *     opposite local node k and runs from local node (k+1)%3 to (k+2)%3.
+ *   - Edges are node pairs oriented from the lower to the higher node id
+ *     and numbered in lexicographic (low, high) order; e, d and the current
+ *     are indexed by that numbering, b and bz by triangle.
+ *   - e_i is the line integral of E along edge i [V]; b_f is the flux of
+ *     Bz through triangle f [T m^2]; d = [*eps]_eff e is the FP64 primary
+ *     electric state (e = M~ d, M~ the sparse approximate inverse of
+ *     [*eps]; Gauss's law S~ d = q holds to rounding).
+ *   - A particle position is (triangle, derived slot r, barycentric pair):
+ *     the pair holds lambda of local nodes (r+1)%3 and (r+2)%3; lambda_r is
+ *     (1 - pair0) - pair1.  Momentum u = gamma v [m/s], in-plane.
+ *   - Walls: an edge with one adjacent triangle is a PEC wall (not a free
+ *     DoF); particles reaching it are removed after depositing their
+ *     current up to the wall.  Periodic meshes identify nodes (tri_shift
+ *     gives each triangle vertex's image shift).
+ *
+ * Ownership: input arrays belong to the caller and are copied during the
+ * call.  The simulation owns all device memory, obtained through the
+ * optional alloc/free callbacks of fetd_opts (else hipMalloc/hipFree), and
+ * releases it in fetd_destroy.  Outputs are written to caller buffers whose
+ * capacity is checked.
+ *
+ * Errors: every entry point returns fetd_status.  Argument and state errors
+ * are reported at once; device-side errors (crossing cap exceeded,
+ * non-finite momentum) are raised by the kernels into a device flag and
+ * returned as FETD_E_TRACK by the next synchronising call (fields_get,
+ * particles_get, diagnostics, sync).  fetd_last_error gives a message.
+ * No entry point aborts or throws across the ABI.
+ *
+ * Streams: all device work is enqueued on opts.stream (NULL = default
+ * stream); fetd_pic_step returns without waiting.
+ */
+#ifndef FETDPIC_H
+#define FETDPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FETD_OK = 0,
+    FETD_E_ARG = -1,   /* invalid argument */
+    FETD_E_MESH = -2,  /* invalid or unsupported mesh */
+    FETD_E_OOM = -3,   /* allocation failed */
+    FETD_E_HIP = -4,   /* HIP runtime error */
+    FETD_E_TRACK = -5, /* crossing cap exceeded or non-finite momentum */
+    FETD_E_STATE = -6  /* call not valid in the current state */
+} fetd_status;
+
+/* Pushers of Sec. II.C. */
+typedef enum { FETD_BORIS = 0, FETD_BORIS_TAN = 1, FETD_VAY = 2, FETD_HC = 3 } fetd_pusher;
+
+/* FETD_FP64: every stage in FP64.  FETD_MIXED: particle positions
+ * (barycentric pair) and momenta stored in FP32, gather/push/track in FP32;
+ * the current deposit, its accumulation, the field update and the Gauss
+ * accounting stay FP64 (charge is conserved to FP64 rounding). */
+typedef enum { FETD_FP64 = 0, FETD_MIXED = 1 } fetd_precision;
+
+typedef struct fetd_sim fetd_sim;
+typedef void *(*fetd_alloc_fn)(size_t bytes, void *user);
+typedef void (*fetd_free_fn)(void *ptr, void *user);
+
+typedef struct {
+    int32_t n_nodes;
+    const double *node_xy;   /* [2*n_nodes] x, y [m] */
+    int32_t n_tris;
+    const int32_t *tri_nodes; /* [3*n_tris] counter-clockwise node ids */
+    const int8_t *tri_shift;  /* [6*n_tris] (sx, sy) per vertex in periods, or NULL */
+    const double *period;     /* [2] period per axis (0 = bounded), or NULL */
+} fetd_mesh_desc;
+
+typedef struct {
+    int32_t precision;    /* fetd_precision */
+    double dt;            /* time step [s] */
+    double eps0, mu0, c;  /* vacuum constants [SI]; c enters the pushers */
+    int32_t spai_level;   /* >= 0: SPAI of [*eps] on the level-th power of its
+                             sparsity graph (0 = diagonal); -1: exact inverse
+                             (meshes with at most 4096 edges) */
+    int32_t device;       /* HIP device ordinal */
+    void *stream;         /* hipStream_t, or NULL for the default stream */
+    fetd_alloc_fn alloc;  /* optional device allocator (e.g. a caching allocator) */
+    fetd_free_fn free;
+    void *alloc_user;
+    int32_t crossing_cap; /* maximum edge crossings per particle per step; 0 = 64 */
+    int32_t resort_every; /* re-sort particles by triangle every k steps; 0 = 20 */
+} fetd_opts;
+
+/* Field / table selectors for fetd_fields_get. */
+typedef enum {
+    FETD_FIELD_E = 0,       /* double[n_edges]: e^n */
+    FETD_FIELD_D = 1,       /* double[n_edges]: d^n */
+    FETD_FIELD_B = 2,       /* double[n_tris]: b^{n-1/2} (after a step: the b used next) */
+    FETD_FIELD_J = 3,       /* double[n_edges]: current i^{n+1/2} of the last step */
+    FETD_FIELD_Q = 4,       /* double[n_nodes]: nodal charge q^n (Sec. II.D) */
+    FETD_FIELD_SPAI_PTR = 5, /* int32[n_edges+1]: CSR row pointers of M~ */
+    FETD_FIELD_SPAI_COL = 6, /* int32[nnz] */
+    FETD_FIELD_SPAI_VAL = 7, /* double[nnz] */
+    FETD_FIELD_EDGES = 8,   /* int32[2*n_edges]: (low, high) node of every edge */
+    FETD_FIELD_TRI_EDGE = 9, /* int32[3*n_tris]: edge of local edge k */
+    FETD_FIELD_DIVD = 10    /* double[n_nodes]: S~ d^n */
+} fetd_field;
+
+typedef struct {
+    int32_t n_nodes, n_tris, n_edges, n_free_edges, n_free_nodes;
+    int64_t spai_nnz;
+    double spai_frobenius;  /* ||I - [*eps] M~||_F / sqrt(n_free_edges) */
+    int32_t n_species;
+    int64_t device_bytes;   /* device memory held */
+} fetd_info;
+
+typedef struct {
+    int64_t step;           /* steps taken */
+    int64_t n_alive, n_lost;
+    int64_t n_segments;     /* path pieces deposited since creation */
+    double gauss_abs;       /* max over free nodes |S~(d^n - d^0) - (q^n - q^0)| [C/m] */
+    double gauss_rel;       /* gauss_abs / max(|q^n|, |q^0|) */
+    double dce_abs;         /* max over free nodes |q^n - q^{n-1} + dt S~ i^{n-1/2}|,
+                               when the previous diagnostics call was one step ago; else -1 */
+    double dce_rel;
+    double W_E;             /* (1/2) e . d  [J/m] */
+    double W_B;             /* (1/2) sum_f b_f^2 / (mu0 A_f) */
+    double W_kin;           /* sum w m c^2 (gamma - 1) */
+    int32_t error_code;     /* 0, or 1 = crossing cap, 2 = non-finite momentum */
+    int64_t error_particle; /* load-order index of the first offending particle */
+} fetd_diag;
+
+/* Build the mesh tables, [*eps], its approximate inverse and all device
+ * state (Sec. II.A).  Fields start at zero.  *out receives the handle. */
+fetd_status fetd_mesh_create(const fetd_mesh_desc *mesh, const fetd_opts *opts,
+                             fetd_sim **out);
+
+/* Static external fields added at the gather (not evolved): bz_ext per
+ * triangle [T], e_ext per edge [V] (line-integral DoFs), and an affine
+ * field E(r) = (a0 + a2 x + a3 y, a1 + a4 x + a5 y) [V/m] evaluated at the
+ * particle's Cartesian position in its triangle's frame.  NULL clears. */
+fetd_status fetd_fields_set(fetd_sim *sim, const double *bz_ext, const double *e_ext,
+                            const double *e_affine);
+
+/* Append a species of n macro particles given in barycentric form
+ * (tri[n], slot[n] or NULL for slot 0, lam[2n], u[2n]).  Load order
+ * defines particle ids 0..n-1 within the species.  *species_out gets the
+ * species index. */
+fetd_status fetd_particles_load_bary(fetd_sim *sim, double q, double m, double w, int64_t n,
+                                     const int32_t *tri, const int8_t *slot,
+                                     const double *lam, const double *u,
+                                     int32_t *species_out);
+
+/* Same, from Cartesian positions xy[2n]: each point is located in the
+ * lowest-id triangle that contains it (periodic images included). */
+fetd_status fetd_particles_load(fetd_sim *sim, double q, double m, double w, int64_t n,
+                                const double *xy, const double *u, int32_t *species_out);
+
+/* Advance n_steps PIC steps with the given pusher (fetd_pusher).
+ * Asynchronous on the simulation's stream. */
+fetd_status fetd_pic_step(fetd_sim *sim, int32_t n_steps, int32_t pusher);
+
+/* Re-sort every species by triangle now (also drops lost particles). */
+fetd_status fetd_sort(fetd_sim *sim);
+
+/* Wait for the stream and report device-side errors. */
+fetd_status fetd_sync(fetd_sim *sim);
+
+/* Copy a field or mesh table (fetd_field) to host memory.  *written gets
+ * the byte size; FETD_E_ARG if capacity_bytes is too small. */
+fetd_status fetd_fields_get(fetd_sim *sim, int32_t which, void *host_dst,
+                            int64_t capacity_bytes, int64_t *written);
+
+/* Copy the alive particles of a species, in load-id order of the alive
+ * ones: tri[n], slot[n], lam[2n], u[2n], id[n] (any may be NULL).
+ * *n_out gets the count; FETD_E_ARG if capacity < count. */
+fetd_status fetd_particles_get(fetd_sim *sim, int32_t species, int64_t capacity,
+                               int32_t *tri, int8_t *slot, double *lam, double *u,
+                               int64_t *id, int64_t *n_out);
+
+/* Charge, Gauss and continuity residuals, energies and counters
+ * (Sec. II.A eq. semi.dis.div.2, Sec. II.D eq. full.dis.cont).
+ * Synchronises the stream. */
+fetd_status fetd_diagnostics(fetd_sim *sim, fetd_diag *out);
+
+/* Stage timing with HIP events recorded on the simulation's stream around
+ * every kernel launch of the step: stage 0 = Faraday and gather record,
+ * 1 = particle stage (one launch per species), 2 = Ampere, 3 = SpMV,
+ * 4 = re-sort (all of its kernels).  enable != 0 starts (and resets) timing,
+ * 0 stops it. */
+fetd_status fetd_profile(fetd_sim *sim, int32_t enable);
+
+/* Device milliseconds summed per stage since timing started, and the number
+ * of timed launches per stage (arrays of FETD_N_STAGES).  Synchronises. */
+#define FETD_N_STAGES 5
+fetd_status fetd_stage_times(fetd_sim *sim, double *ms, int64_t *launches);
+
+/* Sizes and SPAI quality. */
+fetd_status fetd_info_get(fetd_sim *sim, fetd_info *out);
+
+/* Message of the last failed call on sim (thread-local one if sim is NULL). */
+const char *fetd_last_error(const fetd_sim *sim);
+
+/* Release all device memory and the handle.  NULL is a no-op. */
+void fetd_destroy(fetd_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FETDPIC_H */

@@ -1,0 +1,1404 @@
+// Host runtime of the FETD-PIC library: mesh tables, Hodge operators, the
+// sparse approximate inverse, device state and the C-ABI entry points
+// declared in include/fetdpic.h.
+//
+// Method: arXiv:1707.04333 (Na, Moon, Omelchenko, Teixeira), Sec. II.
+#include "../../include/fetdpic.h"
+#include "fetd_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+using namespace fetd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Species {
+    double q = 0, m = 0, w = 0;
+    int64_t n_loaded = 0;  // ids 0..n_loaded-1
+    int64_t n = 0;         // slots in use (alive + lost-but-not-yet-dropped)
+    int64_t offset = 0;    // first slot in the particle arrays
+};
+
+struct Csr {
+    std::vector<int32_t> ptr, col;
+    std::vector<double> val;
+};
+
+}  // namespace
+
+struct fetd_sim {
+    // options
+    int precision = FETD_FP64;
+    double dt = 0, eps0 = 0, mu0 = 0, c = 0;
+    int spai_level = 1;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    fetd_alloc_fn alloc_cb = nullptr;
+    fetd_free_fn free_cb = nullptr;
+    void *alloc_user = nullptr;
+    int cap = 64;
+    int resort_every = 20;
+    double period[2] = {0, 0};
+
+    // mesh (host)
+    int nn = 0, nf = 0, ne = 0, n_free_e = 0, n_free_n = 0;
+    std::vector<int32_t> tri_node, tri_edge, tri_nbr, edge_lo, edge_hi;
+    std::vector<int8_t> tri_sign, tri_nbrk;
+    std::vector<double> vxy, grad, area;
+    std::vector<int32_t> edge_f;  // [2 ne]
+    std::vector<int8_t> edge_s;   // [2 ne]
+    std::vector<uint8_t> edge_free, node_free;
+    Csr meps, mt;
+    double spai_fro = 0;
+
+    // device: mesh
+    int4 *d_tri_edge = nullptr, *d_tri_nbr = nullptr, *d_tri_node = nullptr, *d_edge_face = nullptr;
+    int2 *d_edge_nodes = nullptr;
+    double *d_grad64 = nullptr, *d_vxy64 = nullptr, *d_inv_mu_area = nullptr, *d_inv_2area = nullptr;
+    float *d_grad32 = nullptr, *d_vxy32 = nullptr;
+    int32_t *d_sl_ptr = nullptr, *d_sl_w = nullptr, *d_sl_col = nullptr;
+    double *d_sl_val = nullptr;
+    // device: fields
+    double *d_b = nullptr, *d_h = nullptr, *d_d = nullptr, *d_e = nullptr;
+    double *d_cur[2] = {nullptr, nullptr};
+    int cur_active = 0;
+    void *d_rec = nullptr;
+    double *d_bz_ext = nullptr, *d_e_ext = nullptr, *d_damp = nullptr;
+    bool has_affine = false;
+    double affine[6] = {0, 0, 0, 0, 0, 0};
+    // device: particles
+    std::vector<Species> species;
+    int64_t p_cap = 0;
+    uint32_t *d_key[2] = {nullptr, nullptr};
+    void *d_lam[2] = {nullptr, nullptr};
+    void *d_u[2] = {nullptr, nullptr};
+    int32_t *d_pid[2] = {nullptr, nullptr};
+    int pbuf = 0;
+    // device: sort and diagnostics scratch
+    int32_t *d_counts = nullptr, *d_offsets = nullptr, *d_block_sums = nullptr;
+    unsigned long long *d_counters = nullptr;
+    double *d_q = nullptr, *d_divd = nullptr, *d_partial = nullptr;
+    static constexpr int kPartial = 1024;
+
+    // state
+    int64_t step = 0;
+    int64_t steps_since_sort = 0;
+    bool have_baseline = false;
+    std::vector<double> q0, divd0, q_last;
+    int64_t q_last_step = -1;
+    int64_t device_bytes = 0;
+    std::string err;
+    // stage timing
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[FETD_N_STAGES];
+    std::vector<hipEvent_t> event_pool;
+    hipEvent_t take_event()
+    {
+        hipEvent_t ev = nullptr;
+        if (!event_pool.empty()) {
+            ev = event_pool.back();
+            event_pool.pop_back();
+        } else if (hipEventCreate(&ev) != hipSuccess) {
+            ev = nullptr;
+        }
+        return ev;
+    }
+    // Brackets a launch with events when timing is on.
+    struct Timer {
+        fetd_sim *s;
+        int stage;
+        hipEvent_t a = nullptr;
+        Timer(fetd_sim *s_, int st) : s(s_), stage(st)
+        {
+            if (s->profiling && (a = s->take_event())) (void)hipEventRecord(a, s->stream);
+        }
+        ~Timer()
+        {
+            if (!a) return;
+            hipEvent_t b = s->take_event();
+            if (b && hipEventRecord(b, s->stream) == hipSuccess) s->timed[stage].push_back({a, b});
+            else s->event_pool.push_back(a);
+        }
+    };
+
+    // ---------------------------------------------------------------
+    fetd_status fail(fetd_status st, const std::string &msg)
+    {
+        err = msg;
+        g_last_error = msg;
+        return st;
+    }
+    fetd_status hip_fail(hipError_t e, const char *what)
+    {
+        return fail(FETD_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+    bool dev_alloc(void **p, size_t bytes)
+    {
+        if (bytes == 0) bytes = 16;
+        if (alloc_cb) {
+            *p = alloc_cb(bytes, alloc_user);
+            if (!*p) return false;
+        } else if (hipMalloc(p, bytes) != hipSuccess) {
+            *p = nullptr;
+            return false;
+        }
+        device_bytes += int64_t(bytes);
+        allocs.push_back({*p, bytes});
+        return true;
+    }
+    void dev_free(void *p)
+    {
+        if (!p) return;
+        for (size_t i = 0; i < allocs.size(); ++i) {
+            if (allocs[i].first == p) {
+                device_bytes -= int64_t(allocs[i].second);
+                allocs[i] = allocs.back();
+                allocs.pop_back();
+                break;
+            }
+        }
+        if (free_cb) free_cb(p, alloc_user);
+        else (void)hipFree(p);
+    }
+    std::vector<std::pair<void *, size_t>> allocs;
+
+    bool fp32() const { return precision == FETD_MIXED; }
+    size_t real_bytes() const { return fp32() ? 4 : 8; }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------
+// Mesh topology and geometry (Sec. II.A: incidence C, S; dual C~ = C^T).
+// ---------------------------------------------------------------------
+fetd_status build_topology(fetd_sim *s, const fetd_mesh_desc *md)
+{
+#pragma clang fp contract(off)
+    const int nf = md->n_tris, nn = md->n_nodes;
+    s->nf = nf;
+    s->nn = nn;
+    s->tri_node.assign(md->tri_nodes, md->tri_nodes + 3 * size_t(nf));
+    for (int i = 0; i < 3 * nf; ++i)
+        if (s->tri_node[i] < 0 || s->tri_node[i] >= nn)
+            return s->fail(FETD_E_MESH, "triangle node id out of range");
+    // vertex coordinates (image-consistent on periodic meshes)
+    s->vxy.resize(6 * size_t(nf));
+    for (int f = 0; f < nf; ++f)
+        for (int k = 0; k < 3; ++k) {
+            const int nd = s->tri_node[3 * f + k];
+            double x = md->node_xy[2 * nd], y = md->node_xy[2 * nd + 1];
+            if (md->tri_shift && md->period) {
+                x = x + double(md->tri_shift[6 * f + 2 * k]) * md->period[0];
+                y = y + double(md->tri_shift[6 * f + 2 * k + 1]) * md->period[1];
+            }
+            s->vxy[6 * f + 2 * k] = x;
+            s->vxy[6 * f + 2 * k + 1] = y;
+        }
+    // area and grad lambda_k = perp(x_b - x_a) / 2A, perp(x, y) = (-y, x)
+    s->area.resize(nf);
+    s->grad.resize(6 * size_t(nf));
+    for (int f = 0; f < nf; ++f) {
+        const double *v = &s->vxy[6 * f];
+        const double a2 = (v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1]);
+        if (!(a2 > 0)) return s->fail(FETD_E_MESH, "triangle " + std::to_string(f) +
+                                                        " is not counter-clockwise");
+        s->area[f] = 0.5 * a2;
+        for (int k = 0; k < 3; ++k) {
+            const int ia = (k + 1) % 3, ib = (k + 2) % 3;
+            s->grad[6 * f + 2 * k] = -(v[2 * ib + 1] - v[2 * ia + 1]) / a2;
+            s->grad[6 * f + 2 * k + 1] = (v[2 * ib] - v[2 * ia]) / a2;
+        }
+    }
+    // edges: (low, high) node pairs in lexicographic order
+    struct Occ {
+        uint64_t key;
+        int32_t fk;
+    };
+    std::vector<Occ> occ(3 * size_t(nf));
+    for (int f = 0; f < nf; ++f)
+        for (int k = 0; k < 3; ++k) {
+            const int a = s->tri_node[3 * f + (k + 1) % 3], b = s->tri_node[3 * f + (k + 2) % 3];
+            if (a == b) return s->fail(FETD_E_MESH, "degenerate edge");
+            const uint64_t lo = uint64_t(std::min(a, b)), hi = uint64_t(std::max(a, b));
+            occ[3 * f + k] = {(lo << 32) | hi, 3 * f + k};
+        }
+    std::sort(occ.begin(), occ.end(), [](const Occ &x, const Occ &y) {
+        return x.key != y.key ? x.key < y.key : x.fk < y.fk;
+    });
+    s->tri_edge.assign(3 * size_t(nf), -1);
+    s->tri_sign.assign(3 * size_t(nf), 0);
+    s->tri_nbr.assign(3 * size_t(nf), -1);
+    s->tri_nbrk.assign(3 * size_t(nf), -1);
+    s->edge_lo.clear();
+    s->edge_hi.clear();
+    s->edge_f.clear();
+    s->edge_s.clear();
+    size_t i = 0;
+    while (i < occ.size()) {
+        size_t j = i;
+        while (j < occ.size() && occ[j].key == occ[i].key) ++j;
+        if (j - i > 2) return s->fail(FETD_E_MESH, "an edge has more than two triangles");
+        const int ed = int(s->edge_lo.size());
+        s->edge_lo.push_back(int32_t(occ[i].key >> 32));
+        s->edge_hi.push_back(int32_t(occ[i].key & 0xffffffffu));
+        int32_t ff[2] = {-1, -1};
+        int8_t ss[2] = {0, 0};
+        for (size_t t = i; t < j; ++t) {
+            const int fk = occ[t].fk, f = fk / 3, k = fk % 3;
+            const int a = s->tri_node[3 * f + (k + 1) % 3], b = s->tri_node[3 * f + (k + 2) % 3];
+            s->tri_edge[fk] = ed;
+            s->tri_sign[fk] = a < b ? 1 : -1;
+            ff[t - i] = f;
+            ss[t - i] = s->tri_sign[fk];
+        }
+        if (j - i == 2) {
+            const int fa = occ[i].fk, fb = occ[i + 1].fk;
+            s->tri_nbr[fa] = fb / 3;
+            s->tri_nbrk[fa] = int8_t(fb % 3);
+            s->tri_nbr[fb] = fa / 3;
+            s->tri_nbrk[fb] = int8_t(fa % 3);
+        }
+        s->edge_f.push_back(ff[0]);
+        s->edge_f.push_back(ff[1]);
+        s->edge_s.push_back(ss[0]);
+        s->edge_s.push_back(ss[1]);
+        i = j;
+    }
+    s->ne = int(s->edge_lo.size());
+    s->edge_free.assign(s->ne, 0);
+    s->node_free.assign(nn, 1);
+    s->n_free_e = 0;
+    for (int e = 0; e < s->ne; ++e) {
+        if (s->edge_f[2 * e + 1] >= 0) {
+            s->edge_free[e] = 1;
+            ++s->n_free_e;
+        } else {
+            s->node_free[s->edge_lo[e]] = 0;
+            s->node_free[s->edge_hi[e]] = 0;
+        }
+    }
+    s->n_free_n = 0;
+    for (int n = 0; n < nn; ++n) s->n_free_n += s->node_free[n];
+    return FETD_OK;
+}
+
+// [*eps]_ij = eps0 int W1_i . W1_j over the mesh (Sec. II.A), free edges.
+void assemble_hodge_eps(fetd_sim *s)
+{
+    const int ne = s->ne;
+    std::vector<std::vector<std::pair<int, double>>> rows(ne);
+    for (int f = 0; f < s->nf; ++f) {
+        const double *g = &s->grad[6 * f];
+        const double A = s->area[f];
+        auto gd = [&](int p, int q) { return g[2 * p] * g[2 * q] + g[2 * p + 1] * g[2 * q + 1]; };
+        auto mass = [&](int p, int q) { return A * (p == q ? 2.0 : 1.0) / 12.0; };
+        for (int k = 0; k < 3; ++k) {
+            const int ek = s->tri_edge[3 * f + k];
+            if (!s->edge_free[ek]) continue;
+            const int a = (k + 1) % 3, b = (k + 2) % 3;
+            for (int l = 0; l < 3; ++l) {
+                const int el = s->tri_edge[3 * f + l];
+                if (!s->edge_free[el]) continue;
+                const int cc = (l + 1) % 3, dd = (l + 2) % 3;
+                // int (l_a G_b - l_b G_a).(l_c G_d - l_d G_c)
+                const double v = gd(b, dd) * mass(a, cc) - gd(b, cc) * mass(a, dd) -
+                                 gd(a, dd) * mass(b, cc) + gd(a, cc) * mass(b, dd);
+                rows[ek].push_back({el, s->eps0 * double(s->tri_sign[3 * f + k]) *
+                                            double(s->tri_sign[3 * f + l]) * v});
+            }
+        }
+    }
+    Csr &M = s->meps;
+    M.ptr.assign(ne + 1, 0);
+    M.col.clear();
+    M.val.clear();
+    for (int e = 0; e < ne; ++e) {
+        auto &r = rows[e];
+        std::sort(r.begin(), r.end(),
+                  [](const std::pair<int, double> &x, const std::pair<int, double> &y) {
+                      return x.first < y.first;
+                  });
+        for (size_t t = 0; t < r.size(); ++t) {
+            if (!M.col.empty() && int(M.col.size()) > M.ptr[e] && M.col.back() == r[t].first)
+                M.val.back() += r[t].second;
+            else {
+                M.col.push_back(r[t].first);
+                M.val.push_back(r[t].second);
+            }
+        }
+        M.ptr[e + 1] = int32_t(M.col.size());
+    }
+}
+
+// Cholesky solve of the small SPD system N x = rhs (n x n, row-major).
+bool chol_solve(std::vector<double> &N, int n, std::vector<double> &x)
+{
+    for (int j = 0; j < n; ++j) {
+        double dgn = N[size_t(j) * n + j];
+        for (int k = 0; k < j; ++k) dgn -= N[size_t(j) * n + k] * N[size_t(j) * n + k];
+        if (!(dgn > 0)) return false;
+        dgn = std::sqrt(dgn);
+        N[size_t(j) * n + j] = dgn;
+        for (int i = j + 1; i < n; ++i) {
+            double v = N[size_t(i) * n + j];
+            for (int k = 0; k < j; ++k) v -= N[size_t(i) * n + k] * N[size_t(j) * n + k];
+            N[size_t(i) * n + j] = v / dgn;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double v = x[i];
+        for (int k = 0; k < i; ++k) v -= N[size_t(i) * n + k] * x[k];
+        x[i] = v / N[size_t(i) * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double v = x[i];
+        for (int k = i + 1; k < n; ++k) v -= N[size_t(k) * n + i] * x[k];
+        x[i] = v / N[size_t(i) * n + i];
+    }
+    return true;
+}
+
+// Frobenius-norm sparse approximate inverse of [*eps] (Sec. II.A: tunable
+// sparsity, exponential convergence in the Frobenius norm): for every free
+// column j, minimise ||M m_j - e_j||_2 over m_j supported on the nodes
+// within `level` hops of j in the graph of M; solved through the normal
+// equations of the small dense block; then symmetrised.
+fetd_status build_spai(fetd_sim *s, int level)
+{
+    const Csr &M = s->meps;
+    const int ne = s->ne;
+    std::vector<std::vector<int>> pat(ne);
+    std::vector<std::vector<double>> sol(ne);
+    std::atomic<bool> ok{true};
+    const int nthreads = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    auto worker = [&](int t) {
+        std::vector<int> mark(ne, -1), rpos(ne, -1);
+        std::vector<int> J, I;
+        std::vector<double> A, N, x;
+        for (int j = t; j < ne; j += nthreads) {
+            if (!s->edge_free[j]) continue;
+            J.assign(1, j);
+            mark[j] = j;
+            size_t head = 0;
+            for (int l = 0; l < level; ++l) {
+                const size_t end = J.size();
+                for (; head < end; ++head)
+                    for (int q = M.ptr[J[head]]; q < M.ptr[J[head] + 1]; ++q)
+                        if (mark[M.col[q]] != j) {
+                            mark[M.col[q]] = j;
+                            J.push_back(M.col[q]);
+                        }
+            }
+            std::sort(J.begin(), J.end());
+            I.clear();
+            for (int cj : J)
+                for (int q = M.ptr[cj]; q < M.ptr[cj + 1]; ++q)
+                    if (rpos[M.col[q]] != -2 - j) {
+                        rpos[M.col[q]] = -2 - j;
+                        I.push_back(M.col[q]);
+                    }
+            std::sort(I.begin(), I.end());
+            const int ni = int(I.size()), nj = int(J.size());
+            std::vector<int> pos(ni);
+            A.assign(size_t(ni) * nj, 0.0);
+            // row position lookup by binary search in I
+            for (int c = 0; c < nj; ++c) {
+                const int cj = J[c];
+                for (int q = M.ptr[cj]; q < M.ptr[cj + 1]; ++q) {
+                    const int r = int(std::lower_bound(I.begin(), I.end(), M.col[q]) - I.begin());
+                    A[size_t(r) * nj + c] = M.val[q];  // M symmetric: column cj = row cj
+                }
+            }
+            N.assign(size_t(nj) * nj, 0.0);
+            for (int r = 0; r < ni; ++r)
+                for (int p = 0; p < nj; ++p) {
+                    const double arp = A[size_t(r) * nj + p];
+                    if (arp == 0.0) continue;
+                    for (int q = 0; q < nj; ++q) N[size_t(p) * nj + q] += arp * A[size_t(r) * nj + q];
+                }
+            const int rj = int(std::lower_bound(I.begin(), I.end(), j) - I.begin());
+            x.assign(nj, 0.0);
+            for (int p = 0; p < nj; ++p) x[p] = A[size_t(rj) * nj + p];
+            if (!chol_solve(N, nj, x)) {
+                ok = false;
+                return;
+            }
+            pat[j] = J;
+            sol[j] = x;
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthreads; ++t) th.emplace_back(worker, t);
+    for (auto &x : th) x.join();
+    if (!ok) return s->fail(FETD_E_MESH, "SPAI normal equations not positive definite");
+    // symmetrise: M~_ij = (m_ij + m_ji) / 2 on the symmetric pattern
+    Csr &T = s->mt;
+    T.ptr.assign(ne + 1, 0);
+    T.col.clear();
+    T.val.clear();
+    for (int i = 0; i < ne; ++i) {
+        for (size_t a = 0; a < pat[i].size(); ++a) {
+            const int j = pat[i][a];
+            // value of column j at row i, and of column i at row j
+            const double mij = sol[j].empty() ? 0.0 :
+                sol[j][std::lower_bound(pat[j].begin(), pat[j].end(), i) - pat[j].begin()];
+            const double mji = sol[i][a];
+            T.col.push_back(j);
+            T.val.push_back(0.5 * (mij + mji));
+        }
+        T.ptr[i + 1] = int32_t(T.col.size());
+    }
+    return FETD_OK;
+}
+
+// Exact inverse of the free block of [*eps] by dense Cholesky (small meshes).
+fetd_status build_exact_inverse(fetd_sim *s)
+{
+    const int ne = s->ne;
+    std::vector<int> fidx, pos(ne, -1);
+    for (int e = 0; e < ne; ++e)
+        if (s->edge_free[e]) {
+            pos[e] = int(fidx.size());
+            fidx.push_back(e);
+        }
+    const int n = int(fidx.size());
+    if (n > 4096) return s->fail(FETD_E_ARG, "exact inverse limited to 4096 free edges");
+    std::vector<double> L(size_t(n) * n, 0.0);
+    for (int r = 0; r < n; ++r) {
+        const int e = fidx[r];
+        for (int q = s->meps.ptr[e]; q < s->meps.ptr[e + 1]; ++q)
+            L[size_t(r) * n + pos[s->meps.col[q]]] = s->meps.val[q];
+    }
+    for (int j = 0; j < n; ++j) {
+        double dgn = L[size_t(j) * n + j];
+        for (int k = 0; k < j; ++k) dgn -= L[size_t(j) * n + k] * L[size_t(j) * n + k];
+        if (!(dgn > 0)) return s->fail(FETD_E_MESH, "[*eps] not positive definite");
+        dgn = std::sqrt(dgn);
+        L[size_t(j) * n + j] = dgn;
+        for (int i = j + 1; i < n; ++i) {
+            double v = L[size_t(i) * n + j];
+            for (int k = 0; k < j; ++k) v -= L[size_t(i) * n + k] * L[size_t(j) * n + k];
+            L[size_t(i) * n + j] = v / dgn;
+        }
+    }
+    std::vector<double> inv(size_t(n) * n, 0.0), col(n);
+    for (int c = 0; c < n; ++c) {
+        std::fill(col.begin(), col.end(), 0.0);
+        col[c] = 1.0;
+        for (int i = 0; i < n; ++i) {
+            double v = col[i];
+            for (int k = 0; k < i; ++k) v -= L[size_t(i) * n + k] * col[k];
+            col[i] = v / L[size_t(i) * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double v = col[i];
+            for (int k = i + 1; k < n; ++k) v -= L[size_t(k) * n + i] * col[k];
+            col[i] = v / L[size_t(i) * n + i];
+        }
+        for (int i = 0; i < n; ++i) inv[size_t(i) * n + c] = col[i];
+    }
+    Csr &T = s->mt;
+    T.ptr.assign(ne + 1, 0);
+    T.col.clear();
+    T.val.clear();
+    for (int e = 0; e < ne; ++e) {
+        if (pos[e] >= 0)
+            for (int c = 0; c < n; ++c) {
+                T.col.push_back(fidx[c]);
+                T.val.push_back(0.5 * (inv[size_t(pos[e]) * n + c] + inv[size_t(c) * n + pos[e]]));
+            }
+        T.ptr[e + 1] = int32_t(T.col.size());
+    }
+    return FETD_OK;
+}
+
+double spai_frobenius(const fetd_sim *s)
+{
+    // ||I - M M~||_F over the free block, by columns of M~ (symmetric)
+    const Csr &M = s->meps, &T = s->mt;
+    std::vector<double> acc(s->ne, 0.0);
+    std::vector<int> touched;
+    double tot = 0.0;
+    for (int j = 0; j < s->ne; ++j) {
+        if (!s->edge_free[j]) continue;
+        touched.clear();
+        for (int q = T.ptr[j]; q < T.ptr[j + 1]; ++q) {
+            const int k = T.col[q];
+            for (int p = M.ptr[k]; p < M.ptr[k + 1]; ++p) {
+                if (acc[M.col[p]] == 0.0) touched.push_back(M.col[p]);
+                acc[M.col[p]] += M.val[p] * T.val[q];
+            }
+        }
+        bool diag_seen = false;
+        for (int r : touched) {
+            const double v = acc[r] - (r == j ? 1.0 : 0.0);
+            if (r == j) diag_seen = true;
+            tot += v * v;
+            acc[r] = 0.0;
+        }
+        if (!diag_seen) tot += 1.0;
+    }
+    return std::sqrt(tot / std::max(1, s->n_free_e));
+}
+
+template <typename T>
+fetd_status upload(fetd_sim *s, T **dst, const T *src, size_t count)
+{
+    void *p = nullptr;
+    if (!s->dev_alloc(&p, sizeof(T) * count))
+        return s->fail(FETD_E_OOM, "device allocation failed");
+    *dst = static_cast<T *>(p);
+    if (count) {
+        hipError_t e = hipMemcpyAsync(p, src, sizeof(T) * count, hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "hipMemcpyAsync");
+        e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "hipStreamSynchronize");
+    }
+    return FETD_OK;
+}
+
+template <typename T>
+fetd_status alloc_zero(fetd_sim *s, T **dst, size_t count)
+{
+    std::vector<T> z(count, T());
+    return upload(s, dst, z.data(), count);
+}
+
+fetd_status upload_mesh(fetd_sim *s)
+{
+    const int nf = s->nf, ne = s->ne, nn = s->nn;
+    std::vector<int4> te(nf), tn(nf), tno(nf);
+    for (int f = 0; f < nf; ++f) {
+        int sb = 0, kb = 0;
+        for (int k = 0; k < 3; ++k) {
+            if (s->tri_sign[3 * f + k] < 0) sb |= 1 << k;
+            if (s->tri_nbrk[3 * f + k] >= 0) kb |= int(s->tri_nbrk[3 * f + k]) << (2 * k);
+        }
+        te[f] = make_int4(s->tri_edge[3 * f], s->tri_edge[3 * f + 1], s->tri_edge[3 * f + 2], sb);
+        tn[f] = make_int4(s->tri_nbr[3 * f], s->tri_nbr[3 * f + 1], s->tri_nbr[3 * f + 2], kb);
+        tno[f] = make_int4(s->tri_node[3 * f], s->tri_node[3 * f + 1], s->tri_node[3 * f + 2], 0);
+    }
+    std::vector<int4> ef(ne);
+    std::vector<int2> en(ne);
+    for (int e = 0; e < ne; ++e) {
+        ef[e] = make_int4(s->edge_f[2 * e], s->edge_f[2 * e + 1], s->edge_s[2 * e],
+                          s->edge_s[2 * e + 1]);
+        en[e] = make_int2(s->edge_lo[e], s->edge_hi[e]);
+    }
+    std::vector<float> g32(8 * size_t(nf), 0.f), v32(8 * size_t(nf), 0.f);
+    std::vector<double> imua(nf), i2a(nf);
+    for (int f = 0; f < nf; ++f) {
+        for (int k = 0; k < 6; ++k) {
+            g32[8 * f + k] = float(s->grad[6 * f + k]);
+            v32[8 * f + k] = float(s->vxy[6 * f + k]);
+        }
+        imua[f] = 1.0 / (s->mu0 * s->area[f]);
+        i2a[f] = 1.0 / (2.0 * s->area[f]);
+    }
+    fetd_status st;
+    if ((st = upload(s, &s->d_tri_edge, te.data(), nf))) return st;
+    if ((st = upload(s, &s->d_tri_nbr, tn.data(), nf))) return st;
+    if ((st = upload(s, &s->d_tri_node, tno.data(), nf))) return st;
+    if ((st = upload(s, &s->d_edge_face, ef.data(), ne))) return st;
+    if ((st = upload(s, &s->d_edge_nodes, en.data(), ne))) return st;
+    if ((st = upload(s, &s->d_grad64, s->grad.data(), s->grad.size()))) return st;
+    if ((st = upload(s, &s->d_vxy64, s->vxy.data(), s->vxy.size()))) return st;
+    if ((st = upload(s, &s->d_grad32, g32.data(), g32.size()))) return st;
+    if ((st = upload(s, &s->d_vxy32, v32.data(), v32.size()))) return st;
+    if ((st = upload(s, &s->d_inv_mu_area, imua.data(), imua.size()))) return st;
+    if ((st = upload(s, &s->d_inv_2area, i2a.data(), i2a.size()))) return st;
+    // SELL-64 of M~ (wall rows are empty: e = 0 there)
+    const int nsl = (ne + kSlice - 1) / kSlice;
+    std::vector<int32_t> sp(nsl + 1, 0), sw(nsl, 0);
+    for (int sl = 0; sl < nsl; ++sl) {
+        int w = 0;
+        for (int r = sl * kSlice; r < std::min(ne, (sl + 1) * kSlice); ++r)
+            w = std::max(w, s->mt.ptr[r + 1] - s->mt.ptr[r]);
+        sw[sl] = w;
+        sp[sl + 1] = sp[sl] + w * kSlice;
+    }
+    std::vector<int32_t> scol(std::max(1, sp[nsl]), 0);
+    std::vector<double> sval(std::max(1, sp[nsl]), 0.0);
+    for (int sl = 0; sl < nsl; ++sl)
+        for (int ln = 0; ln < kSlice; ++ln) {
+            const int r = sl * kSlice + ln;
+            for (int j = 0; j < sw[sl]; ++j) {
+                const int q = sp[sl] + j * kSlice + ln;
+                const int rr = std::min(r, ne - 1);
+                if (r < ne && s->mt.ptr[r] + j < s->mt.ptr[r + 1]) {
+                    scol[q] = s->mt.col[s->mt.ptr[r] + j];
+                    sval[q] = s->mt.val[s->mt.ptr[r] + j];
+                } else {
+                    scol[q] = rr;
+                    sval[q] = 0.0;
+                }
+            }
+        }
+    if ((st = upload(s, &s->d_sl_ptr, sp.data(), sp.size()))) return st;
+    if ((st = upload(s, &s->d_sl_w, sw.data(), sw.size()))) return st;
+    if ((st = upload(s, &s->d_sl_col, scol.data(), scol.size()))) return st;
+    if ((st = upload(s, &s->d_sl_val, sval.data(), sval.size()))) return st;
+    // fields
+    if ((st = alloc_zero(s, &s->d_b, nf))) return st;
+    if ((st = alloc_zero(s, &s->d_h, nf))) return st;
+    if ((st = alloc_zero(s, &s->d_d, ne))) return st;
+    if ((st = alloc_zero(s, &s->d_e, ne))) return st;
+    if ((st = alloc_zero(s, &s->d_cur[0], ne))) return st;
+    if ((st = alloc_zero(s, &s->d_cur[1], ne))) return st;
+    void *rec = nullptr;
+    if (!s->dev_alloc(&rec, 8 * s->real_bytes() * size_t(nf)))
+        return s->fail(FETD_E_OOM, "device allocation failed");
+    s->d_rec = rec;
+    if ((st = alloc_zero(s, &s->d_counts, size_t(nf) + 1))) return st;
+    if ((st = alloc_zero(s, &s->d_offsets, size_t(nf) + 1))) return st;
+    if ((st = alloc_zero(s, &s->d_block_sums, size_t(nf) / 1024 + 8))) return st;
+    std::vector<unsigned long long> ctr = {0, 0, 0, std::numeric_limits<unsigned long long>::max()};
+    if ((st = upload(s, &s->d_counters, ctr.data(), ctr.size()))) return st;
+    if ((st = alloc_zero(s, &s->d_q, size_t(nn)))) return st;
+    if ((st = alloc_zero(s, &s->d_divd, size_t(nn)))) return st;
+    if ((st = alloc_zero(s, &s->d_partial, size_t(fetd_sim::kPartial)))) return st;
+    return FETD_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+fetd_status check_device_errors(fetd_sim *s)
+{
+    unsigned long long ctr[4];
+    hipError_t e = hipMemcpyAsync(ctr, s->d_counters, sizeof ctr, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "device execution");
+    if (ctr[2]) {
+        return s->fail(FETD_E_TRACK, std::string(ctr[2] & 1 ? "crossing cap exceeded" :
+                                                              "non-finite momentum") +
+                                         " (first particle id " + std::to_string(ctr[3]) + ")");
+    }
+    return FETD_OK;
+}
+
+fetd_status grow_particles(fetd_sim *s, int64_t extra)
+{
+    const int64_t used = s->species.empty() ? 0 :
+        s->species.back().offset + s->species.back().n;
+    const int64_t need = used + extra;
+    if (need <= s->p_cap) return FETD_OK;
+    const size_t rb = s->real_bytes();
+    int64_t ncap = std::max<int64_t>(need, 1024);
+    uint32_t *key[2];
+    void *lam[2], *u[2];
+    int32_t *pid[2];
+    for (int b = 0; b < 2; ++b) {
+        void *p;
+        if (!s->dev_alloc(&p, sizeof(uint32_t) * ncap)) return s->fail(FETD_E_OOM, "particles");
+        key[b] = static_cast<uint32_t *>(p);
+        if (!s->dev_alloc(&lam[b], 2 * rb * ncap)) return s->fail(FETD_E_OOM, "particles");
+        if (!s->dev_alloc(&u[b], 2 * rb * ncap)) return s->fail(FETD_E_OOM, "particles");
+        if (!s->dev_alloc(&p, sizeof(int32_t) * ncap)) return s->fail(FETD_E_OOM, "particles");
+        pid[b] = static_cast<int32_t *>(p);
+    }
+    if (used > 0) {
+        const int cb = s->pbuf;
+        hipError_t e = hipMemcpyAsync(key[0], s->d_key[cb], sizeof(uint32_t) * used,
+                                      hipMemcpyDeviceToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(lam[0], s->d_lam[cb], 2 * rb * used, hipMemcpyDeviceToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(u[0], s->d_u[cb], 2 * rb * used, hipMemcpyDeviceToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(pid[0], s->d_pid[cb], sizeof(int32_t) * used, hipMemcpyDeviceToDevice,
+                               s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "particle copy");
+    }
+    for (int b = 0; b < 2; ++b) {
+        s->dev_free(s->d_key[b]);
+        s->dev_free(s->d_lam[b]);
+        s->dev_free(s->d_u[b]);
+        s->dev_free(s->d_pid[b]);
+        s->d_key[b] = key[b];
+        s->d_lam[b] = lam[b];
+        s->d_u[b] = u[b];
+        s->d_pid[b] = pid[b];
+    }
+    s->pbuf = 0;
+    s->p_cap = ncap;
+    return FETD_OK;
+}
+
+fetd_status sort_all(fetd_sim *s)
+{
+    const int cb = s->pbuf, ob = 1 - s->pbuf;
+    const size_t rb = s->real_bytes();
+    for (const Species &sp : s->species) {
+        if (sp.n == 0) continue;
+        SortArgs a;
+        a.n = sp.n;
+        a.nf = s->nf;
+        a.key_in = s->d_key[cb] + sp.offset;
+        a.lam_in = static_cast<char *>(s->d_lam[cb]) + 2 * rb * sp.offset;
+        a.u_in = static_cast<char *>(s->d_u[cb]) + 2 * rb * sp.offset;
+        a.pid_in = s->d_pid[cb] + sp.offset;
+        a.key_out = s->d_key[ob] + sp.offset;
+        a.lam_out = static_cast<char *>(s->d_lam[ob]) + 2 * rb * sp.offset;
+        a.u_out = static_cast<char *>(s->d_u[ob]) + 2 * rb * sp.offset;
+        a.pid_out = s->d_pid[ob] + sp.offset;
+        a.counts = s->d_counts;
+        a.offsets = s->d_offsets;
+        a.block_sums = s->d_block_sums;
+        a.elem_bytes = int(2 * rb);
+        // slots past the alive count keep the lost key
+        hipError_t e = hipMemsetAsync(a.key_out, 0xFF, sizeof(uint32_t) * size_t(sp.n), s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "sort");
+        e = launch_sort(s->stream, a);
+        if (e != hipSuccess) return s->hip_fail(e, "sort");
+    }
+    s->pbuf = ob;
+    s->steps_since_sort = 0;
+    return FETD_OK;
+}
+
+fetd_status compute_charge(fetd_sim *s)
+{
+    hipError_t e = hipMemsetAsync(s->d_q, 0, sizeof(double) * size_t(s->nn), s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "charge");
+    const size_t rb = s->real_bytes();
+    for (const Species &sp : s->species) {
+        e = launch_charge(s->stream, sp.n, s->d_key[s->pbuf] + sp.offset,
+                          static_cast<char *>(s->d_lam[s->pbuf]) + 2 * rb * sp.offset, s->fp32(),
+                          s->d_tri_node, sp.q * sp.w, s->d_q);
+        if (e != hipSuccess) return s->hip_fail(e, "charge");
+    }
+    return FETD_OK;
+}
+
+fetd_status compute_divd(fetd_sim *s)
+{
+    hipError_t e = hipMemsetAsync(s->d_divd, 0, sizeof(double) * size_t(s->nn), s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "divd");
+    e = launch_divd(s->stream, s->ne, s->d_edge_nodes, s->d_d, s->d_divd);
+    if (e != hipSuccess) return s->hip_fail(e, "divd");
+    return FETD_OK;
+}
+
+fetd_status download(fetd_sim *s, void *dst, const void *src, size_t bytes)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "download");
+    return FETD_OK;
+}
+
+fetd_status take_baseline(fetd_sim *s)
+{
+    fetd_status st;
+    if ((st = compute_charge(s)) || (st = compute_divd(s))) return st;
+    s->q0.resize(s->nn);
+    s->divd0.resize(s->nn);
+    if ((st = download(s, s->q0.data(), s->d_q, sizeof(double) * s->nn))) return st;
+    if ((st = download(s, s->divd0.data(), s->d_divd, sizeof(double) * s->nn))) return st;
+    s->have_baseline = true;
+    return FETD_OK;
+}
+
+}  // namespace
+
+// =====================================================================
+// C-ABI
+// =====================================================================
+extern "C" {
+
+fetd_status fetd_mesh_create(const fetd_mesh_desc *mesh, const fetd_opts *opts, fetd_sim **out)
+{
+    if (!out) {
+        g_last_error = "out is NULL";
+        return FETD_E_ARG;
+    }
+    *out = nullptr;
+    if (!mesh || !opts || !mesh->node_xy || !mesh->tri_nodes || mesh->n_nodes <= 0 ||
+        mesh->n_tris <= 0 || mesh->n_tris > int32_t(kTriMask)) {
+        g_last_error = "invalid mesh description";
+        return FETD_E_ARG;
+    }
+    if (!(opts->dt > 0) || !(opts->eps0 > 0) || !(opts->mu0 > 0) || !(opts->c > 0) ||
+        (opts->precision != FETD_FP64 && opts->precision != FETD_MIXED) || opts->spai_level < -1 ||
+        opts->spai_level > 4) {
+        g_last_error = "invalid options";
+        return FETD_E_ARG;
+    }
+    fetd_sim *s = new (std::nothrow) fetd_sim();
+    if (!s) {
+        g_last_error = "out of host memory";
+        return FETD_E_OOM;
+    }
+    s->precision = opts->precision;
+    s->dt = opts->dt;
+    s->eps0 = opts->eps0;
+    s->mu0 = opts->mu0;
+    s->c = opts->c;
+    s->spai_level = opts->spai_level;
+    s->device = opts->device;
+    s->stream = static_cast<hipStream_t>(opts->stream);
+    s->alloc_cb = opts->alloc;
+    s->free_cb = opts->free;
+    s->alloc_user = opts->alloc_user;
+    s->cap = opts->crossing_cap > 0 ? opts->crossing_cap : 64;
+    s->resort_every = opts->resort_every > 0 ? opts->resort_every : 20;
+    if ((s->alloc_cb == nullptr) != (s->free_cb == nullptr)) {
+        delete s;
+        g_last_error = "alloc and free callbacks must be given together";
+        return FETD_E_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || opts->device < 0 || opts->device >= ndev) {
+        delete s;
+        g_last_error = "no such HIP device";
+        return FETD_E_HIP;
+    }
+    if (mesh->period && mesh->tri_shift) {
+        s->period[0] = mesh->period[0];
+        s->period[1] = mesh->period[1];
+    }
+    DeviceGuard g(s->device);
+    fetd_status st = build_topology(s, mesh);
+    if (st == FETD_OK) {
+        assemble_hodge_eps(s);
+        st = s->spai_level < 0 ? build_exact_inverse(s) : build_spai(s, s->spai_level);
+    }
+    if (st == FETD_OK) {
+        s->spai_fro = spai_frobenius(s);
+        st = upload_mesh(s);
+    }
+    if (st != FETD_OK) {
+        g_last_error = s->err;
+        fetd_destroy(s);
+        return st;
+    }
+    *out = s;
+    return FETD_OK;
+}
+
+void fetd_destroy(fetd_sim *s)
+{
+    if (!s) return;
+    DeviceGuard g(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    auto allocs = s->allocs;
+    for (auto &a : allocs) s->dev_free(a.first);
+    for (auto &v : s->timed)
+        for (auto &p : v) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+    for (auto ev : s->event_pool) (void)hipEventDestroy(ev);
+    delete s;
+}
+
+const char *fetd_last_error(const fetd_sim *s)
+{
+    if (s) return s->err.c_str();
+    return g_last_error.c_str();
+}
+
+fetd_status fetd_fields_set(fetd_sim *s, const double *bz_ext, const double *e_ext,
+                            const double *e_affine)
+{
+    if (!s) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    fetd_status st;
+    if (bz_ext) {
+        if (!s->d_bz_ext && (st = alloc_zero(s, &s->d_bz_ext, s->nf))) return st;
+        hipError_t e = hipMemcpyAsync(s->d_bz_ext, bz_ext, sizeof(double) * s->nf,
+                                      hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "fields_set");
+    } else if (s->d_bz_ext) {
+        s->dev_free(s->d_bz_ext);
+        s->d_bz_ext = nullptr;
+    }
+    if (e_ext) {
+        if (!s->d_e_ext && (st = alloc_zero(s, &s->d_e_ext, s->ne))) return st;
+        hipError_t e = hipMemcpyAsync(s->d_e_ext, e_ext, sizeof(double) * s->ne,
+                                      hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "fields_set");
+    } else if (s->d_e_ext) {
+        s->dev_free(s->d_e_ext);
+        s->d_e_ext = nullptr;
+    }
+    s->has_affine = e_affine != nullptr;
+    for (int k = 0; k < 6; ++k) s->affine[k] = e_affine ? e_affine[k] : 0.0;
+    return FETD_OK;
+}
+
+fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, int64_t n,
+                                     const int32_t *tri, const int8_t *slot, const double *lam,
+                                     const double *u, int32_t *species_out)
+{
+    if (!s) return FETD_E_ARG;
+    if (n < 0 || (n > 0 && (!tri || !lam || !u)) || !(m > 0) || n > (int64_t(1) << 31) - 1)
+        return s->fail(FETD_E_ARG, "invalid particle arguments");
+    DeviceGuard g(s->device);
+    for (int64_t i = 0; i < n; ++i) {
+        if (tri[i] < 0 || tri[i] >= s->nf) return s->fail(FETD_E_ARG, "triangle id out of range");
+        if (slot && (slot[i] < 0 || slot[i] > 2)) return s->fail(FETD_E_ARG, "slot out of range");
+    }
+    fetd_status st = grow_particles(s, n);
+    if (st) return st;
+    Species sp;
+    sp.q = q;
+    sp.m = m;
+    sp.w = w;
+    sp.n_loaded = n;
+    sp.n = n;
+    sp.offset = s->species.empty() ? 0 : s->species.back().offset + s->species.back().n;
+    const size_t rb = s->real_bytes();
+    std::vector<uint32_t> key(n);
+    std::vector<int32_t> pid(n);
+    std::vector<char> lb(2 * rb * n), ub(2 * rb * n);
+    for (int64_t i = 0; i < n; ++i) {
+        key[i] = uint32_t(tri[i]) | (uint32_t(slot ? slot[i] : 0) << 30);
+        pid[i] = int32_t(i);
+        if (s->fp32()) {
+            float *lf = reinterpret_cast<float *>(lb.data()), *uf = reinterpret_cast<float *>(ub.data());
+            lf[2 * i] = float(lam[2 * i]);
+            lf[2 * i + 1] = float(lam[2 * i + 1]);
+            uf[2 * i] = float(u[2 * i]);
+            uf[2 * i + 1] = float(u[2 * i + 1]);
+        } else {
+            std::memcpy(lb.data() + 16 * i, lam + 2 * i, 16);
+            std::memcpy(ub.data() + 16 * i, u + 2 * i, 16);
+        }
+    }
+    const int cb = s->pbuf;
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        e = hipMemcpyAsync(s->d_key[cb] + sp.offset, key.data(), 4 * n, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(static_cast<char *>(s->d_lam[cb]) + 2 * rb * sp.offset, lb.data(),
+                               2 * rb * n, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(static_cast<char *>(s->d_u[cb]) + 2 * rb * sp.offset, ub.data(),
+                               2 * rb * n, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->d_pid[cb] + sp.offset, pid.data(), 4 * n, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    }
+    if (e != hipSuccess) return s->hip_fail(e, "particles_load");
+    s->species.push_back(sp);
+    if (species_out) *species_out = int32_t(s->species.size() - 1);
+    s->have_baseline = false;
+    // sorted order for the segmented deposit
+    if (n > 0 && (st = sort_all(s))) return st;
+    return FETD_OK;
+}
+
+fetd_status fetd_particles_load(fetd_sim *s, double q, double m, double w, int64_t n,
+                                const double *xy, const double *u, int32_t *species_out)
+{
+#pragma clang fp contract(off)
+    if (!s) return FETD_E_ARG;
+    if (n < 0 || (n > 0 && (!xy || !u))) return s->fail(FETD_E_ARG, "invalid particle arguments");
+    // uniform bucket grid over triangle bounding boxes
+    double x0 = 1e300, y0 = 1e300, x1 = -1e300, y1 = -1e300;
+    for (int f = 0; f < s->nf; ++f)
+        for (int k = 0; k < 3; ++k) {
+            x0 = std::min(x0, s->vxy[6 * f + 2 * k]);
+            x1 = std::max(x1, s->vxy[6 * f + 2 * k]);
+            y0 = std::min(y0, s->vxy[6 * f + 2 * k + 1]);
+            y1 = std::max(y1, s->vxy[6 * f + 2 * k + 1]);
+        }
+    const int nb = std::max(1, int(std::sqrt(double(s->nf) / 2.0)));
+    const double bx = (x1 - x0) / nb, by = (y1 - y0) / nb;
+    std::vector<std::vector<int>> bucket(size_t(nb) * nb);
+    for (int f = 0; f < s->nf; ++f) {
+        double lx = 1e300, ly = 1e300, hx = -1e300, hy = -1e300;
+        for (int k = 0; k < 3; ++k) {
+            lx = std::min(lx, s->vxy[6 * f + 2 * k]);
+            hx = std::max(hx, s->vxy[6 * f + 2 * k]);
+            ly = std::min(ly, s->vxy[6 * f + 2 * k + 1]);
+            hy = std::max(hy, s->vxy[6 * f + 2 * k + 1]);
+        }
+        const int i0 = std::clamp(int((lx - x0) / bx), 0, nb - 1), i1 = std::clamp(int((hx - x0) / bx), 0, nb - 1);
+        const int j0 = std::clamp(int((ly - y0) / by), 0, nb - 1), j1 = std::clamp(int((hy - y0) / by), 0, nb - 1);
+        for (int j = j0; j <= j1; ++j)
+            for (int i = i0; i <= i1; ++i) bucket[size_t(j) * nb + i].push_back(f);
+    }
+    // the point and, on periodic axes, its images one period away (triangle
+    // frames of a periodic mesh extend past the period cell)
+    std::vector<int32_t> tri(n);
+    std::vector<double> lam(2 * n);
+    const int mx = s->period[0] > 0 ? 1 : 0, my = s->period[1] > 0 ? 1 : 0;
+    for (int64_t p = 0; p < n; ++p) {
+        int best = -1;
+        double bl1 = 0, bl2 = 0;
+        for (int sx = -mx; sx <= mx; ++sx)
+            for (int sy = -my; sy <= my; ++sy) {
+                const double qx = xy[2 * p] + double(sx) * s->period[0];
+                const double qy = xy[2 * p + 1] + double(sy) * s->period[1];
+                if (qx < x0 || qx > x1 || qy < y0 || qy > y1) continue;
+                const int bi = std::clamp(int((qx - x0) / bx), 0, nb - 1);
+                const int bj = std::clamp(int((qy - y0) / by), 0, nb - 1);
+                for (int f : bucket[size_t(bj) * nb + bi]) {
+                    if (best >= 0 && f >= best) break;
+                    const double *v = &s->vxy[6 * f];
+                    const double den = (v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1]);
+                    const double l1 = ((qx - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (qy - v[1])) / den;
+                    const double l2 = ((v[2] - v[0]) * (qy - v[1]) - (qx - v[0]) * (v[3] - v[1])) / den;
+                    if (l1 >= 0 && l2 >= 0 && l1 + l2 <= 1) {
+                        best = f;
+                        bl1 = l1;
+                        bl2 = l2;
+                        break;
+                    }
+                }
+            }
+        if (best < 0) return s->fail(FETD_E_ARG, "particle " + std::to_string(p) + " is outside the mesh");
+        tri[p] = best;
+        lam[2 * p] = bl1;
+        lam[2 * p + 1] = bl2;
+    }
+    return fetd_particles_load_bary(s, q, m, w, n, tri.data(), nullptr, lam.data(), u, species_out);
+}
+
+fetd_status fetd_sort(fetd_sim *s)
+{
+    if (!s) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    return sort_all(s);
+}
+
+fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
+{
+    if (!s) return FETD_E_ARG;
+    if (n_steps < 0 || pusher < 0 || pusher > 3) return s->fail(FETD_E_ARG, "invalid step arguments");
+    DeviceGuard g(s->device);
+    fetd_status st;
+    if (!s->have_baseline && (st = take_baseline(s))) return st;
+    MeshView mv;
+    mv.tri_edge = s->d_tri_edge;
+    mv.tri_nbr = s->d_tri_nbr;
+    mv.grad64 = s->d_grad64;
+    mv.grad32 = s->d_grad32;
+    mv.vxy64 = s->d_vxy64;
+    mv.vxy32 = s->d_vxy32;
+    const size_t rb = s->real_bytes();
+    for (int it = 0; it < n_steps; ++it) {
+        if (s->steps_since_sort >= s->resort_every) {
+            fetd_sim::Timer t(s, 4);
+            if ((st = sort_all(s))) return st;
+        }
+        hipError_t e;
+        {
+        fetd_sim::Timer t(s, 0);
+        e = launch_faraday(s->stream, s->nf, s->d_tri_edge, s->d_e, s->d_e_ext, s->d_b,
+                                      s->d_h, s->d_inv_mu_area, s->d_inv_2area, s->d_bz_ext,
+                                      s->d_grad64, s->d_rec, s->fp32(), s->dt);
+        }
+        if (e != hipSuccess) return s->hip_fail(e, "faraday");
+        double *cur = s->d_cur[s->cur_active];
+        for (const Species &sp : s->species) {
+            StepArgs a;
+            a.n = sp.n;
+            a.key = s->d_key[s->pbuf] + sp.offset;
+            a.lam = static_cast<char *>(s->d_lam[s->pbuf]) + 2 * rb * sp.offset;
+            a.u = static_cast<char *>(s->d_u[s->pbuf]) + 2 * rb * sp.offset;
+            a.pid = s->d_pid[s->pbuf] + sp.offset;
+            a.rec = s->d_rec;
+            a.cur = cur;
+            a.qdt = sp.q * sp.w / s->dt;
+            a.alpha = sp.q * s->dt / (2.0 * sp.m);
+            a.dt = s->dt;
+            a.c = s->c;
+            a.inv_c2 = 1.0 / (s->c * s->c);
+            a.cap = s->cap;
+            a.has_affine = s->has_affine ? 1 : 0;
+            for (int k = 0; k < 6; ++k) a.aff[k] = s->affine[k];
+            a.counters = s->d_counters;
+            fetd_sim::Timer t(s, 1);
+            e = launch_particles(s->stream, mv, a, pusher, s->fp32());
+            if (e != hipSuccess) return s->hip_fail(e, "particle step");
+        }
+        double *next = s->d_cur[1 - s->cur_active];
+        {
+            fetd_sim::Timer t(s, 2);
+            e = launch_ampere(s->stream, s->ne, s->d_edge_face, s->d_h, cur, next, s->d_d,
+                              s->d_damp, s->dt);
+        }
+        if (e != hipSuccess) return s->hip_fail(e, "ampere");
+        {
+            fetd_sim::Timer t(s, 3);
+            e = launch_spmv(s->stream, s->ne, s->d_sl_ptr, s->d_sl_w, s->d_sl_col, s->d_sl_val,
+                            s->d_d, s->d_e);
+        }
+        if (e != hipSuccess) return s->hip_fail(e, "spmv");
+        s->cur_active = 1 - s->cur_active;
+        ++s->step;
+        ++s->steps_since_sort;
+    }
+    return FETD_OK;
+}
+
+fetd_status fetd_sync(fetd_sim *s)
+{
+    if (!s) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    return check_device_errors(s);
+}
+
+fetd_status fetd_fields_get(fetd_sim *s, int32_t which, void *dst, int64_t capacity,
+                            int64_t *written)
+{
+    if (!s) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    fetd_status st = check_device_errors(s);
+    if (st) return st;
+    const void *src = nullptr;
+    size_t bytes = 0;
+    bool host = false;
+    std::vector<int32_t> tmp;
+    switch (which) {
+    case FETD_FIELD_E: src = s->d_e; bytes = 8 * size_t(s->ne); break;
+    case FETD_FIELD_D: src = s->d_d; bytes = 8 * size_t(s->ne); break;
+    case FETD_FIELD_B: src = s->d_b; bytes = 8 * size_t(s->nf); break;
+    case FETD_FIELD_J: src = s->d_cur[1 - s->cur_active]; bytes = 8 * size_t(s->ne); break;
+    case FETD_FIELD_Q:
+        if ((st = compute_charge(s))) return st;
+        src = s->d_q;
+        bytes = 8 * size_t(s->nn);
+        break;
+    case FETD_FIELD_DIVD:
+        if ((st = compute_divd(s))) return st;
+        src = s->d_divd;
+        bytes = 8 * size_t(s->nn);
+        break;
+    case FETD_FIELD_SPAI_PTR: src = s->mt.ptr.data(); bytes = 4 * s->mt.ptr.size(); host = true; break;
+    case FETD_FIELD_SPAI_COL: src = s->mt.col.data(); bytes = 4 * s->mt.col.size(); host = true; break;
+    case FETD_FIELD_SPAI_VAL: src = s->mt.val.data(); bytes = 8 * s->mt.val.size(); host = true; break;
+    case FETD_FIELD_EDGES:
+        tmp.resize(2 * size_t(s->ne));
+        for (int e = 0; e < s->ne; ++e) {
+            tmp[2 * e] = s->edge_lo[e];
+            tmp[2 * e + 1] = s->edge_hi[e];
+        }
+        src = tmp.data();
+        bytes = 4 * tmp.size();
+        host = true;
+        break;
+    case FETD_FIELD_TRI_EDGE: src = s->tri_edge.data(); bytes = 4 * s->tri_edge.size(); host = true; break;
+    default: return s->fail(FETD_E_ARG, "unknown field selector");
+    }
+    if (written) *written = int64_t(bytes);
+    if (!dst) return FETD_OK;
+    if (capacity < int64_t(bytes)) return s->fail(FETD_E_ARG, "destination too small");
+    if (host) {
+        std::memcpy(dst, src, bytes);
+        return FETD_OK;
+    }
+    return download(s, dst, src, bytes);
+}
+
+fetd_status fetd_particles_get(fetd_sim *s, int32_t species, int64_t capacity, int32_t *tri,
+                               int8_t *slot, double *lam, double *u, int64_t *id, int64_t *n_out)
+{
+    if (!s) return FETD_E_ARG;
+    if (species < 0 || species >= int32_t(s->species.size()))
+        return s->fail(FETD_E_ARG, "no such species");
+    DeviceGuard g(s->device);
+    fetd_status st = check_device_errors(s);
+    if (st) return st;
+    const Species &sp = s->species[species];
+    const size_t rb = s->real_bytes();
+    std::vector<uint32_t> key(sp.n);
+    std::vector<int32_t> pid(sp.n);
+    std::vector<char> lb(2 * rb * sp.n), ub(2 * rb * sp.n);
+    if (sp.n) {
+        if ((st = download(s, key.data(), s->d_key[s->pbuf] + sp.offset, 4 * sp.n))) return st;
+        if ((st = download(s, pid.data(), s->d_pid[s->pbuf] + sp.offset, 4 * sp.n))) return st;
+        if ((st = download(s, lb.data(), static_cast<char *>(s->d_lam[s->pbuf]) + 2 * rb * sp.offset,
+                           2 * rb * sp.n)))
+            return st;
+        if ((st = download(s, ub.data(), static_cast<char *>(s->d_u[s->pbuf]) + 2 * rb * sp.offset,
+                           2 * rb * sp.n)))
+            return st;
+    }
+    std::vector<std::pair<int32_t, int64_t>> order;
+    order.reserve(sp.n);
+    for (int64_t i = 0; i < sp.n; ++i)
+        if (key[i] != kLost) order.push_back({pid[i], i});
+    std::sort(order.begin(), order.end());
+    if (n_out) *n_out = int64_t(order.size());
+    if (capacity < int64_t(order.size())) return s->fail(FETD_E_ARG, "capacity too small");
+    for (size_t o = 0; o < order.size(); ++o) {
+        const int64_t i = order[o].second;
+        if (tri) tri[o] = int32_t(key[i] & kTriMask);
+        if (slot) slot[o] = int8_t(key[i] >> 30);
+        if (id) id[o] = order[o].first;
+        for (int c = 0; c < 2; ++c) {
+            if (s->fp32()) {
+                if (lam) lam[2 * o + c] = double(reinterpret_cast<float *>(lb.data())[2 * i + c]);
+                if (u) u[2 * o + c] = double(reinterpret_cast<float *>(ub.data())[2 * i + c]);
+            } else {
+                if (lam) lam[2 * o + c] = reinterpret_cast<double *>(lb.data())[2 * i + c];
+                if (u) u[2 * o + c] = reinterpret_cast<double *>(ub.data())[2 * i + c];
+            }
+        }
+    }
+    return FETD_OK;
+}
+
+fetd_status fetd_diagnostics(fetd_sim *s, fetd_diag *out)
+{
+    if (!s || !out) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    std::memset(out, 0, sizeof *out);
+    unsigned long long ctr[4];
+    fetd_status st = download(s, ctr, s->d_counters, sizeof ctr);
+    if (st) return st;
+    out->error_code = int32_t(ctr[2] & 1 ? 1 : (ctr[2] & 2 ? 2 : 0));
+    out->error_particle = ctr[2] ? int64_t(ctr[3]) : -1;
+    if (!s->have_baseline && (st = take_baseline(s))) return st;
+    if ((st = compute_charge(s)) || (st = compute_divd(s))) return st;
+    const int nn = s->nn, ne = s->ne;
+    std::vector<double> q(nn), dv(nn), e(ne), d(ne), b(s->nf), jl(ne);
+    if ((st = download(s, q.data(), s->d_q, 8 * size_t(nn)))) return st;
+    if ((st = download(s, dv.data(), s->d_divd, 8 * size_t(nn)))) return st;
+    if ((st = download(s, e.data(), s->d_e, 8 * size_t(ne)))) return st;
+    if ((st = download(s, d.data(), s->d_d, 8 * size_t(ne)))) return st;
+    if ((st = download(s, b.data(), s->d_b, 8 * size_t(s->nf)))) return st;
+    if ((st = download(s, jl.data(), s->d_cur[1 - s->cur_active], 8 * size_t(ne)))) return st;
+    double gmax = 0, qmax = 0;
+    for (int n = 0; n < nn; ++n) {
+        qmax = std::max(qmax, std::max(std::fabs(q[n]), std::fabs(s->q0[n])));
+        if (!s->node_free[n]) continue;
+        gmax = std::max(gmax, std::fabs((dv[n] - s->divd0[n]) - (q[n] - s->q0[n])));
+    }
+    out->gauss_abs = gmax;
+    out->gauss_rel = qmax > 0 ? gmax / qmax : 0.0;
+    out->dce_abs = -1;
+    out->dce_rel = -1;
+    if (s->q_last_step >= 0 && s->q_last_step + 1 == s->step) {
+        std::vector<double> divj(nn, 0.0);
+        for (int ed = 0; ed < ne; ++ed) {
+            divj[s->edge_lo[ed]] += jl[ed];
+            divj[s->edge_hi[ed]] -= jl[ed];
+        }
+        double dm = 0, qm = 0;
+        for (int n = 0; n < nn; ++n) {
+            qm = std::max(qm, std::max(std::fabs(q[n]), std::fabs(s->q_last[n])));
+            if (!s->node_free[n]) continue;
+            dm = std::max(dm, std::fabs((q[n] - s->q_last[n]) + s->dt * divj[n]));
+        }
+        out->dce_abs = dm;
+        out->dce_rel = qm > 0 ? dm / qm : 0.0;
+    }
+    s->q_last = q;
+    s->q_last_step = s->step;
+    double we = 0, wb = 0;
+    for (int ed = 0; ed < ne; ++ed) we += e[ed] * d[ed];
+    for (int f = 0; f < s->nf; ++f) wb += b[f] * b[f] / (s->mu0 * s->area[f]);
+    out->W_E = 0.5 * we;
+    out->W_B = 0.5 * wb;
+    double wk = 0;
+    const size_t rb = s->real_bytes();
+    std::vector<double> part(fetd_sim::kPartial);
+    int64_t alive = 0;
+    for (const Species &sp : s->species) {
+        hipError_t err = hipMemsetAsync(s->d_partial, 0, 8 * fetd_sim::kPartial, s->stream);
+        if (err != hipSuccess) return s->hip_fail(err, "kinetic");
+        err = launch_kinetic(s->stream, sp.n, s->d_key[s->pbuf] + sp.offset,
+                             static_cast<char *>(s->d_u[s->pbuf]) + 2 * rb * sp.offset, s->fp32(),
+                             1.0 / (s->c * s->c), s->d_partial, fetd_sim::kPartial);
+        if (err != hipSuccess) return s->hip_fail(err, "kinetic");
+        if ((st = download(s, part.data(), s->d_partial, 8 * fetd_sim::kPartial))) return st;
+        double acc = 0;
+        for (double v : part) acc += v;
+        wk += sp.w * sp.m * s->c * s->c * acc;
+        alive += sp.n_loaded;
+    }
+    out->W_kin = wk;
+    out->step = s->step;
+    out->n_lost = int64_t(ctr[1]);
+    out->n_alive = alive - out->n_lost;
+    out->n_segments = int64_t(ctr[0]);
+    if (ctr[2]) {
+        s->err = std::string("device error flag ") + std::to_string(ctr[2]);
+        return FETD_E_TRACK;
+    }
+    return FETD_OK;
+}
+
+fetd_status fetd_profile(fetd_sim *s, int32_t enable)
+{
+    if (!s) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "profile");
+    for (auto &v : s->timed) {
+        for (auto &p : v) {
+            s->event_pool.push_back(p.first);
+            s->event_pool.push_back(p.second);
+        }
+        v.clear();
+    }
+    s->profiling = enable != 0;
+    return FETD_OK;
+}
+
+fetd_status fetd_stage_times(fetd_sim *s, double *ms, int64_t *launches)
+{
+    if (!s || !ms || !launches) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "stage_times");
+    for (int k = 0; k < FETD_N_STAGES; ++k) {
+        double tot = 0.0;
+        for (auto &p : s->timed[k]) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, p.first, p.second) == hipSuccess) tot += double(t);
+        }
+        ms[k] = tot;
+        launches[k] = int64_t(s->timed[k].size());
+    }
+    return FETD_OK;
+}
+
+fetd_status fetd_info_get(fetd_sim *s, fetd_info *out)
+{
+    if (!s || !out) return FETD_E_ARG;
+    out->n_nodes = s->nn;
+    out->n_tris = s->nf;
+    out->n_edges = s->ne;
+    out->n_free_edges = s->n_free_e;
+    out->n_free_nodes = s->n_free_n;
+    out->spai_nnz = int64_t(s->mt.col.size());
+    out->spai_frobenius = s->spai_fro;
+    out->n_species = int32_t(s->species.size());
+    out->device_bytes = s->device_bytes;
+    return FETD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// the FETD-PIC library.  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fetd {
+
+constexpr uint32_t kLost = 0xFFFFFFFFu;   // key of a removed particle
+constexpr uint32_t kTriMask = 0x3FFFFFFFu; // triangle id bits of a key
+constexpr int kBlock = 256;                // threads per block of the particle kernels
+constexpr int kSlice = 64;                 // rows per SELL slice of the SpMV
+
+// Per-triangle tables (device).
+//   tri_edge[f] = {edge of local edge 0, 1, 2, sign bits: bit k set when
+//                  local edge k runs against the global orientation}
+//   tri_nbr[f]  = {neighbour across local edge 0, 1, 2 (-1 = wall),
+//                  local index of the shared edge in the neighbour, 2 bits each}
+struct MeshView {
+    const int4 *tri_edge;
+    const int4 *tri_nbr;
+    const double *grad64;  // [nf*6]: (gx, gy) of local node 0, 1, 2
+    const float *grad32;   // [nf*8]: same in FP32, padded to 32 B
+    const double *vxy64;   // [nf*6]: image-consistent vertex coordinates
+    const float *vxy32;    // [nf*8]
+};
+
+// Arguments of one particle-stage launch (one species).
+struct StepArgs {
+    int64_t n;
+    uint32_t *key;
+    void *lam;        // double2 or float2 [n]: barycentric pair
+    void *u;          // double2 or float2 [n]: momentum u = gamma v
+    const void *rec;  // per-triangle field record, 8 reals: V0, V1, V2 (E = sum l_n V_n), Bz, pad
+    double *cur;      // FP64 current accumulator [ne]
+    double qdt;       // Q / dt of the species
+    double alpha;     // q dt / (2 m)
+    double dt;
+    double c;
+    double inv_c2;
+    int cap;          // crossing cap
+    int has_affine;
+    double aff[6];
+    unsigned long long *counters;  // [0] segments, [1] lost, [2] error flags, [3] first bad id
+    const int32_t *pid;            // load ids (for error reports)
+};
+
+// Host-callable launchers (fetd_kernels.hip).
+hipError_t launch_faraday(hipStream_t s, int nf, const int4 *tri_edge, const double *e,
+                          const double *e_ext, double *b, double *h, const double *inv_mu_area,
+                          const double *inv_2area, const double *bz_ext, const double *grad64,
+                          void *rec, bool rec_fp32, double dt);
+hipError_t launch_particles(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
+                            bool fp32);
+hipError_t launch_ampere(hipStream_t s, int ne, const int4 *edge_face, const double *h,
+                         const double *cur, double *cur_next, double *d, const double *damp,
+                         double dt);
+hipError_t launch_spmv(hipStream_t s, int ne, const int32_t *slice_ptr, const int32_t *slice_w,
+                       const int32_t *col, const double *val, const double *d, double *e);
+
+// Counting sort of one species segment by triangle (drops lost particles).
+// counts/offsets need nf+1 ints, block_sums a few thousand.
+struct SortArgs {
+    int64_t n;
+    int nf;
+    const uint32_t *key_in;
+    const void *lam_in;
+    const void *u_in;
+    const int32_t *pid_in;
+    uint32_t *key_out;
+    void *lam_out;
+    void *u_out;
+    int32_t *pid_out;
+    int32_t *counts;   // [nf + 1]
+    int32_t *offsets;  // [nf + 1]
+    int32_t *block_sums;
+    int elem_bytes;    // 8 (float2) or 16 (double2)
+};
+hipError_t launch_sort(hipStream_t s, const SortArgs &a);
+
+// Diagnostics.
+hipError_t launch_charge(hipStream_t s, int64_t n, const uint32_t *key, const void *lam,
+                         bool fp32, const int4 *tri_node, double qw, double *q);
+hipError_t launch_divd(hipStream_t s, int ne, const int2 *edge_nodes, const double *d,
+                       double *out);
+hipError_t launch_kinetic(hipStream_t s, int64_t n, const uint32_t *key, const void *u, bool fp32,
+                          double inv_c2, double *partial, int n_partial);
+
+}  // namespace fetd

@@ -238,7 +238,9 @@ def locate_points(mesh: Mesh, xy: np.ndarray):
     triangle containing it and its barycentric pair (lambda_1, lambda_2).
     Uses a bucket grid over triangle bounding boxes."""
     v = mesh.vertex_xy()
-    x0, y0, x1, y1 = mesh.bbox
+    # bucket grid over the triangle frames (periodic frames extend past the cell)
+    x0, y0 = v[:, :, 0].min(), v[:, :, 1].min()
+    x1, y1 = v[:, :, 0].max(), v[:, :, 1].max()
     nb = max(1, int(math.sqrt(mesh.n_tris / 2)))
     bx = (x1 - x0) / nb
     by = (y1 - y0) / nb
@@ -253,23 +255,36 @@ def locate_points(mesh: Mesh, xy: np.ndarray):
                 buckets[j * nb + i].append(t)
     out_t = np.full(xy.shape[0], -1, dtype=np.int32)
     out_l = np.zeros((xy.shape[0], 2))
-    pi = np.clip(np.floor((xy[:, 0] - x0) / bx).astype(np.int64), 0, nb - 1)
-    pj = np.clip(np.floor((xy[:, 1] - y0) / by).astype(np.int64), 0, nb - 1)
     for p in range(xy.shape[0]):
         best = None
-        for t in sorted(buckets[pj[p] * nb + pi[p]]):
-            a, b, c = v[t]
-            den = (b[0] - a[0]) * (c[1] - a[1]) - (c[0] - a[0]) * (b[1] - a[1])
-            l1 = ((xy[p, 0] - a[0]) * (c[1] - a[1]) - (c[0] - a[0]) * (xy[p, 1] - a[1])) / den
-            l2 = ((b[0] - a[0]) * (xy[p, 1] - a[1]) - (xy[p, 0] - a[0]) * (b[1] - a[1])) / den
-            if l1 >= 0 and l2 >= 0 and l1 + l2 <= 1:
-                best = (t, l1, l2)
-                break
+        for q in _images(mesh, xy[p]):
+            qi = int(np.clip(np.floor((q[0] - x0) / bx), 0, nb - 1))
+            qj = int(np.clip(np.floor((q[1] - y0) / by), 0, nb - 1))
+            for t in sorted(buckets[qj * nb + qi]):
+                if best is not None and t >= best[0]:
+                    break
+                a, b, c = v[t]
+                den = (b[0] - a[0]) * (c[1] - a[1]) - (c[0] - a[0]) * (b[1] - a[1])
+                l1 = ((q[0] - a[0]) * (c[1] - a[1]) - (c[0] - a[0]) * (q[1] - a[1])) / den
+                l2 = ((b[0] - a[0]) * (q[1] - a[1]) - (q[0] - a[0]) * (b[1] - a[1])) / den
+                if l1 >= 0 and l2 >= 0 and l1 + l2 <= 1:
+                    best = (t, l1, l2)
+                    break
         if best is None:
             raise ValueError(f"point {xy[p]} is outside the mesh")
         out_t[p] = best[0]
         out_l[p] = best[1:]
     return out_t, out_l
+
+
+def _images(mesh: Mesh, q):
+    """The point and its images one period away along periodic axes."""
+    px, py = (0.0, 0.0) if mesh.period is None else (float(mesh.period[0]), float(mesh.period[1]))
+    out = []
+    for sx in ((-1, 0, 1) if px > 0 else (0,)):
+        for sy in ((-1, 0, 1) if py > 0 else (0,)):
+            out.append((q[0] + sx * px, q[1] + sy * py))
+    return out
 
 
 def sample_mj2d(n: int, theta: float, rng) -> np.ndarray:
@@ -384,7 +399,9 @@ def _locate_fast(mesh: Mesh, xy: np.ndarray):
     """Vectorised point location by a walk-free bucket search (input
     generation only; same result as ``locate_points`` for interior points)."""
     v = mesh.vertex_xy()
-    x0, y0, x1, y1 = mesh.bbox
+    # bucket grid over the triangle frames (periodic frames extend past the cell)
+    x0, y0 = v[:, :, 0].min(), v[:, :, 1].min()
+    x1, y1 = v[:, :, 0].max(), v[:, :, 1].max()
     nb = max(1, int(math.sqrt(mesh.n_tris / 2)))
     bx = (x1 - x0) / nb
     by = (y1 - y0) / nb
@@ -404,30 +421,39 @@ def _locate_fast(mesh: Mesh, xy: np.ndarray):
     pb, pt = pb[order], pt[order]
     start = np.searchsorted(pb, np.arange(nb * nb))
     end = np.searchsorted(pb, np.arange(nb * nb), side="right")
-    pi = np.clip(np.floor((xy[:, 0] - x0) / bx).astype(np.int64), 0, nb - 1)
-    pj = np.clip(np.floor((xy[:, 1] - y0) / by).astype(np.int64), 0, nb - 1)
-    bk = pj * nb + pi
-    out_t = np.full(xy.shape[0], -1, dtype=np.int32)
+    out_t = np.full(xy.shape[0], np.iinfo(np.int32).max, dtype=np.int32)
     out_l = np.zeros((xy.shape[0], 2))
     maxc = int((end - start).max())
-    for c in range(maxc):
-        todo = np.nonzero(out_t < 0)[0]
-        if todo.size == 0:
-            break
-        has = start[bk[todo]] + c < end[bk[todo]]
-        todo = todo[has]
-        t = pt[start[bk[todo]] + c]
-        a, b, cc = v[t, 0], v[t, 1], v[t, 2]
-        p = xy[todo]
-        den = (b[:, 0] - a[:, 0]) * (cc[:, 1] - a[:, 1]) - (cc[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1])
-        l1 = ((p[:, 0] - a[:, 0]) * (cc[:, 1] - a[:, 1]) - (cc[:, 0] - a[:, 0]) * (p[:, 1] - a[:, 1])) / den
-        l2 = ((b[:, 0] - a[:, 0]) * (p[:, 1] - a[:, 1]) - (p[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1])) / den
-        inside = (l1 >= 0) & (l2 >= 0) & (l1 + l2 <= 1)
-        sel = todo[inside]
-        out_t[sel] = t[inside]
-        out_l[sel, 0] = l1[inside]
-        out_l[sel, 1] = l2[inside]
-    if np.any(out_t < 0):
+    px, py = (0.0, 0.0) if mesh.period is None else (float(mesh.period[0]), float(mesh.period[1]))
+    for sx in ((-1, 0, 1) if px > 0 else (0,)):
+        for sy in ((-1, 0, 1) if py > 0 else (0,)):
+            q = xy + np.array([sx * px, sy * py])
+            ok = (q[:, 0] >= x0) & (q[:, 0] <= x1) & (q[:, 1] >= y0) & (q[:, 1] <= y1)
+            pi = np.clip(np.floor((q[:, 0] - x0) / bx).astype(np.int64), 0, nb - 1)
+            pj = np.clip(np.floor((q[:, 1] - y0) / by).astype(np.int64), 0, nb - 1)
+            bk = pj * nb + pi
+            found = ~ok
+            for c in range(maxc):
+                todo = np.nonzero(~found)[0]
+                if todo.size == 0:
+                    break
+                has = start[bk[todo]] + c < end[bk[todo]]
+                found[todo[~has]] = True
+                todo = todo[has]
+                t = pt[start[bk[todo]] + c]
+                a, b, cc = v[t, 0], v[t, 1], v[t, 2]
+                p = q[todo]
+                den = (b[:, 0] - a[:, 0]) * (cc[:, 1] - a[:, 1]) - (cc[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1])
+                l1 = ((p[:, 0] - a[:, 0]) * (cc[:, 1] - a[:, 1]) - (cc[:, 0] - a[:, 0]) * (p[:, 1] - a[:, 1])) / den
+                l2 = ((b[:, 0] - a[:, 0]) * (p[:, 1] - a[:, 1]) - (p[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1])) / den
+                inside = (l1 >= 0) & (l2 >= 0) & (l1 + l2 <= 1)
+                sel = todo[inside]
+                found[sel] = True
+                better = t[inside] < out_t[sel]
+                out_t[sel[better]] = t[inside][better]
+                out_l[sel[better], 0] = l1[inside][better]
+                out_l[sel[better], 1] = l2[inside][better]
+    if np.any(out_t == np.iinfo(np.int32).max):
         raise ValueError("points outside the mesh")
     return out_t, out_l
 
