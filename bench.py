@@ -45,8 +45,13 @@ def particle_launch_bytes(n_particles, nf, ne, fp32):
     return n_particles * per_particle + nf * per_tri + ne * 16
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_gpu(w, precision, steps, warmup, pusher):
     from paper_1707_04333_amd import fetdpic as fp
+    log(f"{precision}: creating simulation ({w.n_particles} particles)")
     sim = fp.from_workload(w, precision=precision, spai_level=w.spai_level, device=0)
     info = sim.info()
     sim.diagnostics()  # Gauss baseline at step 0
@@ -61,6 +66,7 @@ def run_gpu(w, precision, steps, warmup, pusher):
     sim.profile(False)
     diag = sim.diagnostics()
     sim.close()
+    log(f"{precision}: {steps} steps in {t1 - t0:.3f} s")
     return dict(elapsed=t1 - t0, stages=stages, diag=diag, info=info)
 
 
@@ -101,6 +107,7 @@ def main():
         sys.exit(2)
 
     from paper_1707_04333_amd import inputs as I
+    log("generating workload")
     w = I.pair_plasma(n_pairs=args.pairs, theta=args.theta, precision="mixed")
     n_p = w.n_particles
     mixed = run_gpu(w, "mixed", args.steps, args.warmup, args.pusher)
@@ -155,6 +162,7 @@ def main():
                                              for k, v in r64["stages"].items()}}
         out["mixed_vs_fp64"] = value / out["fp64"]["value"]
     if not args.no_cpu:
+        log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, args.pusher)
     print(json.dumps(out))
 

@@ -3,7 +3,7 @@
 // declared in include/fetdpic.h.
 //
 // Method: arXiv:1707.04333 (Na, Moon, Omelchenko, Teixeira), Sec. II.
-#include "../../include/fetdpic.h"
+#include "fetdpic.h"
 #include "fetd_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -90,6 +90,8 @@ struct fetd_sim {
     // device: sort and diagnostics scratch
     int32_t *d_counts = nullptr, *d_offsets = nullptr, *d_block_sums = nullptr;
     unsigned long long *d_counters = nullptr;
+    unsigned long long *d_block_counts = nullptr;
+    int64_t block_count_cap = 0;  // blocks covered by d_block_counts
     double *d_q = nullptr, *d_divd = nullptr, *d_partial = nullptr;
     static constexpr int kPartial = 1024;
 
@@ -700,8 +702,33 @@ fetd_status check_device_errors(fetd_sim *s)
     return FETD_OK;
 }
 
+fetd_status download(fetd_sim *s, void *dst, const void *src, size_t bytes);
+
+fetd_status grow_block_counts(fetd_sim *s, int64_t extra)
+{
+    // per-block counter slots for the largest particle launch (one species)
+    int64_t max_n = extra;
+    for (const Species &sp : s->species) max_n = std::max(max_n, sp.n);
+    const int64_t blocks = (max_n + int64_t(kBlock) * kPPT - 1) / (int64_t(kBlock) * kPPT) + 1;
+    if (blocks > s->block_count_cap) {
+        std::vector<unsigned long long> old(2 * size_t(s->block_count_cap), 0ull);
+        if (s->block_count_cap > 0) {
+            fetd_status st = download(s, old.data(), s->d_block_counts, 16 * size_t(s->block_count_cap));
+            if (st) return st;
+        }
+        old.resize(2 * size_t(blocks), 0ull);
+        s->dev_free(s->d_block_counts);
+        s->d_block_counts = nullptr;
+        fetd_status st = upload(s, &s->d_block_counts, old.data(), old.size());
+        if (st) return st;
+        s->block_count_cap = blocks;
+    }
+    return FETD_OK;
+}
+
 fetd_status grow_particles(fetd_sim *s, int64_t extra)
 {
+    if (fetd_status st = grow_block_counts(s, extra)) return st;
     const int64_t used = s->species.empty() ? 0 :
         s->species.back().offset + s->species.back().n;
     const int64_t need = used + extra;
@@ -1138,6 +1165,7 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
             a.has_affine = s->has_affine ? 1 : 0;
             for (int k = 0; k < 6; ++k) a.aff[k] = s->affine[k];
             a.counters = s->d_counters;
+            a.block_counts = s->d_block_counts;
             fetd_sim::Timer t(s, 1);
             e = launch_particles(s->stream, mv, a, pusher, s->fp32());
             if (e != hipSuccess) return s->hip_fail(e, "particle step");
@@ -1341,9 +1369,18 @@ fetd_status fetd_diagnostics(fetd_sim *s, fetd_diag *out)
     }
     out->W_kin = wk;
     out->step = s->step;
-    out->n_lost = int64_t(ctr[1]);
+    unsigned long long nseg = 0, nlost = 0;
+    if (s->block_count_cap > 0) {
+        std::vector<unsigned long long> bc(2 * size_t(s->block_count_cap));
+        if ((st = download(s, bc.data(), s->d_block_counts, 8 * bc.size()))) return st;
+        for (size_t b = 0; b < bc.size(); b += 2) {
+            nseg += bc[b];
+            nlost += bc[b + 1];
+        }
+    }
+    out->n_lost = int64_t(nlost);
     out->n_alive = alive - out->n_lost;
-    out->n_segments = int64_t(ctr[0]);
+    out->n_segments = int64_t(nseg);
     if (ctr[2]) {
         s->err = std::string("device error flag ") + std::to_string(ctr[2]);
         return FETD_E_TRACK;

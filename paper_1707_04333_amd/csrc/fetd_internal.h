@@ -11,6 +11,7 @@ namespace fetd {
 constexpr uint32_t kLost = 0xFFFFFFFFu;   // key of a removed particle
 constexpr uint32_t kTriMask = 0x3FFFFFFFu; // triangle id bits of a key
 constexpr int kBlock = 256;                // threads per block of the particle kernels
+constexpr int kPPT = 4;                    // particles per thread of the particle kernel
 constexpr int kSlice = 64;                 // rows per SELL slice of the SpMV
 
 // Per-triangle tables (device).
@@ -43,7 +44,8 @@ struct StepArgs {
     int cap;          // crossing cap
     int has_affine;
     double aff[6];
-    unsigned long long *counters;  // [0] segments, [1] lost, [2] error flags, [3] first bad id
+    unsigned long long *counters;  // [2] error flags, [3] first bad id (rarely written)
+    unsigned long long *block_counts;  // [2 * grid]: per-block running sums (segments, lost)
     const int32_t *pid;            // load ids (for error reports)
 };
 

@@ -108,228 +108,300 @@ __device__ __forceinline__ void push2(R &ux, R &uy, R ex, R ey, R bz, R inv_c2)
 }
 
 // ---------------------------------------------------------------------
-// Fused particle stage.
+// Block-local FP64 current accumulation: an open-addressing hash table in
+// LDS keyed by edge id.  A block deposits every path piece of its
+// particles here (LDS FP64 atomics) and flushes one global atomic per
+// distinct edge at the end; the sorted order keeps the distinct edges of a
+// block few.
+// ---------------------------------------------------------------------
+constexpr int kHashLog2 = 10;
+constexpr int kHash = 1 << kHashLog2;
+constexpr int kProbe = 32;
+
+struct LdsCurrent {
+    int *key;
+    double *val;
+    double *global;  // fallback when the table is congested
+
+    __device__ __forceinline__ void add(int edge, double v) const
+    {
+        unsigned h = (unsigned(edge) * 2654435761u) >> (32 - kHashLog2);
+#pragma nounroll
+        for (int probe = 0; probe < kProbe; ++probe) {
+            int k = __hip_atomic_load(key + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (k == -1) {
+                int expected = -1;
+                __hip_atomic_compare_exchange_strong(key + h, &expected, edge, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+                k = expected == -1 ? edge : expected;
+            }
+            if (k == edge) {
+                __hip_atomic_fetch_add(val + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return;
+            }
+            h = (h + 1) & (kHash - 1);
+        }
+        atomic_add_f64(global + edge, v);
+    }
+};
+
+// ---------------------------------------------------------------------
+// Fused particle stage: each block owns kPPT * kBlock consecutive
+// (triangle-sorted) particles, one per thread per pass.
 // ---------------------------------------------------------------------
 template <int P, typename R>
 __global__ __launch_bounds__(kBlock) void k_particle_step(MeshView m, StepArgs a)
 {
     using R2 = typename Vec2<R>::type;
+    __shared__ int s_key[kHash];
+    __shared__ double s_val[kHash];
+    __shared__ unsigned long long red[2][kBlock / 64];
+    for (int t = threadIdx.x; t < kHash; t += kBlock) {
+        s_key[t] = -1;
+        s_val[t] = 0.0;
+    }
+    __syncthreads();
+    const LdsCurrent dep{s_key, s_val, a.cur};
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t i = tile * kBlock + threadIdx.x;
-    const bool in_range = i < a.n;
-    uint32_t key = in_range ? a.key[i] : kLost;
-    const bool alive = key != kLost;
-
-    int f0 = -1;
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0;  // current of the first path piece (cross terms)
+    const int lane = threadIdx.x & 63;
     unsigned long long nseg = 0, nlost = 0;
 
-    if (alive) {
-        R2 *lamp = reinterpret_cast<R2 *>(a.lam);
-        R2 *up = reinterpret_cast<R2 *>(a.u);
-        R2 pr = lamp[i];
-        R2 uu = up[i];
-        int f = int(key & kTriMask);
-        int r = int(key >> 30);
-        f0 = f;
+    for (int pass = 0; pass < kPPT; ++pass) {
+        const int64_t i = (tile * kPPT + pass) * kBlock + threadIdx.x;
+        const bool in_range = i < a.n;
+        uint32_t key = in_range ? a.key[i] : kLost;
+        const bool alive = key != kLost;
 
-        Tri3<R> L;
-        L.set(next3(r), pr.x);
-        L.set(prev3(r), pr.y);
-        L.set(r, (R(1) - pr.x) - pr.y);
-        Tri3<double> Ls;  // FP64 start point of the current path piece
-        Ls.set(next3(r), double(pr.x));
-        Ls.set(prev3(r), double(pr.y));
-        Ls.set(r, (1.0 - double(pr.x)) - double(pr.y));
+        int f0 = -1;
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0;  // first path piece (cross terms)
 
-        // Gather (Sec. II.B): E = sum_n l_n V_n from the triangle record.
-        const R *rec = reinterpret_cast<const R *>(a.rec) + size_t(f) * 8;
-        R ex = L.v0 * rec[0] + L.v1 * rec[2] + L.v2 * rec[4];
-        R ey = L.v0 * rec[1] + L.v1 * rec[3] + L.v2 * rec[5];
-        const R bzf = rec[6];
-        if (a.has_affine) {
-            R x, y;
-            if constexpr (sizeof(R) == 4) {
-                const float *v = m.vxy32 + size_t(f) * 8;
-                x = L.v0 * v[0] + L.v1 * v[2] + L.v2 * v[4];
-                y = L.v0 * v[1] + L.v1 * v[3] + L.v2 * v[5];
-            } else {
-                const double *v = m.vxy64 + size_t(f) * 6;
-                x = L.v0 * v[0] + L.v1 * v[2] + L.v2 * v[4];
-                y = L.v0 * v[1] + L.v1 * v[3] + L.v2 * v[5];
-            }
-            ex += R(a.aff[0]) + R(a.aff[2]) * x + R(a.aff[3]) * y;
-            ey += R(a.aff[1]) + R(a.aff[4]) * x + R(a.aff[5]) * y;
-        }
+        if (alive) {
+            R2 *lamp = reinterpret_cast<R2 *>(a.lam);
+            R2 *up = reinterpret_cast<R2 *>(a.u);
+            R2 pr = lamp[i];
+            R2 uu = up[i];
+            int f = int(key & kTriMask);
+            int r = int(key >> 30);
+            f0 = f;
 
-        // Push (Sec. II.C).
-        const R alpha = R(a.alpha);
-        R ux = uu.x, uy = uu.y;
-        push2<P, R>(ux, uy, alpha * ex, alpha * ey, alpha * bzf, R(a.inv_c2));
-        const bool finite = isfinite(ux) && isfinite(uy);
+            Tri3<R> L;
+            L.set(next3(r), pr.x);
+            L.set(prev3(r), pr.y);
+            L.set(r, (R(1) - pr.x) - pr.y);
+            Tri3<double> Ls;  // FP64 start point of the current path piece
+            Ls.set(next3(r), double(pr.x));
+            Ls.set(prev3(r), double(pr.y));
+            Ls.set(r, (1.0 - double(pr.x)) - double(pr.y));
 
-        // Move: dr = dt u / gamma (Sec. II.C eq. eq.motion.dis).
-        const R ginv = R(1) / sqrt(R(1) + (ux * ux + uy * uy) * R(a.inv_c2));
-        R rx = R(a.dt) * ux * ginv;
-        R ry = R(a.dt) * uy * ginv;
-        if (!finite) {
-            rx = R(0);
-            ry = R(0);
-        }
-
-        // Track across edges, depositing every straight piece (Sec. II.D).
-        int entry = -1;
-        bool lost = false, capped = false;
-        for (int it = 0;; ++it) {
-            if (it >= a.cap) {
-                capped = true;
-                break;
-            }
-            const R *g;
-            if constexpr (sizeof(R) == 4) g = m.grad32 + size_t(f) * 8;
-            else g = m.grad64 + size_t(f) * 6;
-            Tri3<R> dL;
-            dL.v0 = g[0] * rx + g[1] * ry;
-            dL.v1 = g[2] * rx + g[3] * ry;
-            dL.v2 = g[4] * rx + g[5] * ry;
-            int ks = -1;
-            R ts = R(0);
-            if (entry != 0 && dL.v0 < R(0)) {
-                ks = 0;
-                ts = (L.v0 > R(0) ? L.v0 : R(0)) / (-dL.v0);
-            }
-            if (entry != 1 && dL.v1 < R(0)) {
-                const R tk = (L.v1 > R(0) ? L.v1 : R(0)) / (-dL.v1);
-                if (ks < 0 || tk < ts) {
-                    ks = 1;
-                    ts = tk;
+            // Gather (Sec. II.B): E = sum_n l_n V_n from the triangle record.
+            const R *rec = reinterpret_cast<const R *>(a.rec) + size_t(f) * 8;
+            R ex = L.v0 * rec[0] + L.v1 * rec[2] + L.v2 * rec[4];
+            R ey = L.v0 * rec[1] + L.v1 * rec[3] + L.v2 * rec[5];
+            const R bzf = rec[6];
+            if (a.has_affine) {
+                R x, y;
+                if constexpr (sizeof(R) == 4) {
+                    const float *v = m.vxy32 + size_t(f) * 8;
+                    x = L.v0 * v[0] + L.v1 * v[2] + L.v2 * v[4];
+                    y = L.v0 * v[1] + L.v1 * v[3] + L.v2 * v[5];
+                } else {
+                    const double *v = m.vxy64 + size_t(f) * 6;
+                    x = L.v0 * v[0] + L.v1 * v[2] + L.v2 * v[4];
+                    y = L.v0 * v[1] + L.v1 * v[3] + L.v2 * v[5];
                 }
+                ex += R(a.aff[0]) + R(a.aff[2]) * x + R(a.aff[3]) * y;
+                ey += R(a.aff[1]) + R(a.aff[4]) * x + R(a.aff[5]) * y;
             }
-            if (entry != 2 && dL.v2 < R(0)) {
-                const R tk = (L.v2 > R(0) ? L.v2 : R(0)) / (-dL.v2);
-                if (ks < 0 || tk < ts) {
-                    ks = 2;
-                    ts = tk;
+
+            // Push (Sec. II.C).
+            const R alpha = R(a.alpha);
+            R ux = uu.x, uy = uu.y;
+            push2<P, R>(ux, uy, alpha * ex, alpha * ey, alpha * bzf, R(a.inv_c2));
+            const bool finite = isfinite(ux) && isfinite(uy);
+
+            // Move: dr = dt u / gamma (Sec. II.C eq. eq.motion.dis).
+            const R ginv = R(1) / sqrt(R(1) + (ux * ux + uy * uy) * R(a.inv_c2));
+            R rx = R(a.dt) * ux * ginv;
+            R ry = R(a.dt) * uy * ginv;
+            if (!finite) {
+                rx = R(0);
+                ry = R(0);
+            }
+
+            // Track across edges, depositing every straight piece (Sec. II.D).
+            int entry = -1;
+            bool lost = false, capped = false;
+            for (int it = 0;; ++it) {
+                if (it >= a.cap) {
+                    capped = true;
+                    break;
                 }
+                const R *g;
+                if constexpr (sizeof(R) == 4) g = m.grad32 + size_t(f) * 8;
+                else g = m.grad64 + size_t(f) * 6;
+                Tri3<R> dL;
+                dL.v0 = g[0] * rx + g[1] * ry;
+                dL.v1 = g[2] * rx + g[3] * ry;
+                dL.v2 = g[4] * rx + g[5] * ry;
+                int ks = -1;
+                R ts = R(0);
+                if (entry != 0 && dL.v0 < R(0)) {
+                    ks = 0;
+                    ts = (L.v0 > R(0) ? L.v0 : R(0)) / (-dL.v0);
+                }
+                if (entry != 1 && dL.v1 < R(0)) {
+                    const R tk = (L.v1 > R(0) ? L.v1 : R(0)) / (-dL.v1);
+                    if (ks < 0 || tk < ts) {
+                        ks = 1;
+                        ts = tk;
+                    }
+                }
+                if (entry != 2 && dL.v2 < R(0)) {
+                    const R tk = (L.v2 > R(0) ? L.v2 : R(0)) / (-dL.v2);
+                    if (ks < 0 || tk < ts) {
+                        ks = 2;
+                        ts = tk;
+                    }
+                }
+                const bool done = ks < 0 || ts >= R(1);
+                Tri3<double> Lf;
+                R la = R(0);
+                if (done) {
+                    const int p = next3(r), q = prev3(r);
+                    const R np = L.get(p) + dL.get(p);
+                    const R nq = L.get(q) + dL.get(q);
+                    L.set(p, np);
+                    L.set(q, nq);
+                    Lf.set(p, double(np));
+                    Lf.set(q, double(nq));
+                    Lf.set(r, (1.0 - double(np)) - double(nq));
+                } else {
+                    const int ia = next3(ks);
+                    la = L.get(ia) + ts * dL.get(ia);
+                    Lf.set(ks, 0.0);
+                    Lf.set(ia, double(la));
+                    Lf.set(prev3(ks), 1.0 - double(la));
+                }
+                // eq. I.assign for the three local edges (a, b) = (k+1, k+2).
+                const double w0 = Ls.v1 * Lf.v2 - Lf.v1 * Ls.v2;
+                const double w1 = Ls.v2 * Lf.v0 - Lf.v2 * Ls.v0;
+                const double w2 = Ls.v0 * Lf.v1 - Lf.v0 * Ls.v1;
+                ++nseg;
+                if (it == 0) {
+                    c0 = w0;
+                    c1 = w1;
+                    c2 = w2;
+                } else {
+                    const int4 te = m.tri_edge[f];
+                    const double q = a.qdt;
+                    dep.add(te.x, ((te.w & 1) ? -q : q) * w0);
+                    dep.add(te.y, ((te.w & 2) ? -q : q) * w1);
+                    dep.add(te.z, ((te.w & 4) ? -q : q) * w2);
+                }
+                if (done) break;
+                const int4 nb = m.tri_nbr[f];
+                const int nbf = ks == 0 ? nb.x : (ks == 1 ? nb.y : nb.z);
+                if (nbf < 0) {
+                    lost = true;
+                    break;
+                }
+                // CCW neighbours traverse the shared edge in opposite
+                // directions: node (ks+1) of f is node (kk+2) of the
+                // neighbour and vice versa.
+                const int kk = (nb.w >> (2 * ks)) & 3;
+                const int a2 = next3(kk), b2 = prev3(kk);
+                L.set(kk, R(0));
+                L.set(b2, la);
+                L.set(a2, R(1) - la);
+                Ls.set(kk, 0.0);
+                Ls.set(b2, double(la));
+                Ls.set(a2, 1.0 - double(la));
+                r = a2;
+                f = nbf;
+                entry = kk;
+                const R sc = R(1) - ts;
+                rx = rx * sc;
+                ry = ry * sc;
             }
-            const bool done = ks < 0 || ts >= R(1);
-            Tri3<double> Lf;
-            R la = R(0);
-            if (done) {
-                const int p = next3(r), q = prev3(r);
-                const R np = L.get(p) + dL.get(p);
-                const R nq = L.get(q) + dL.get(q);
-                L.set(p, np);
-                L.set(q, nq);
-                Lf.set(p, double(np));
-                Lf.set(q, double(nq));
-                Lf.set(r, (1.0 - double(np)) - double(nq));
-            } else {
-                const int ia = next3(ks);
-                la = L.get(ia) + ts * dL.get(ia);
-                Lf.set(ks, 0.0);
-                Lf.set(ia, double(la));
-                Lf.set(prev3(ks), 1.0 - double(la));
-            }
-            // eq. I.assign for the three local edges (a, b) = (k+1, k+2).
-            const double w0 = Ls.v1 * Lf.v2 - Lf.v1 * Ls.v2;
-            const double w1 = Ls.v2 * Lf.v0 - Lf.v2 * Ls.v0;
-            const double w2 = Ls.v0 * Lf.v1 - Lf.v0 * Ls.v1;
-            ++nseg;
-            if (it == 0) {
-                c0 = w0;
-                c1 = w1;
-                c2 = w2;
-            } else {
-                const int4 te = m.tri_edge[f];
-                const double q = a.qdt;
-                atomic_add_f64(a.cur + te.x, ((te.w & 1) ? -q : q) * w0);
-                atomic_add_f64(a.cur + te.y, ((te.w & 2) ? -q : q) * w1);
-                atomic_add_f64(a.cur + te.z, ((te.w & 4) ? -q : q) * w2);
-            }
-            if (done) break;
-            const int4 nb = m.tri_nbr[f];
-            const int nbf = ks == 0 ? nb.x : (ks == 1 ? nb.y : nb.z);
-            if (nbf < 0) {
+            if (capped || !finite) {
+                atomicOr(a.counters + 2, capped ? 1ull : 2ull);
+                atomicMin(a.counters + 3, (unsigned long long)(a.pid ? a.pid[i] : i));
                 lost = true;
-                break;
             }
-            // CCW neighbours traverse the shared edge in opposite directions:
-            // node (ks+1) of f is node (kk+2) of the neighbour and vice versa.
-            const int kk = (nb.w >> (2 * ks)) & 3;
-            const int a2 = next3(kk), b2 = prev3(kk);
-            L.set(kk, R(0));
-            L.set(b2, la);
-            L.set(a2, R(1) - la);
-            Ls.set(kk, 0.0);
-            Ls.set(b2, double(la));
-            Ls.set(a2, 1.0 - double(la));
-            r = a2;
-            f = nbf;
-            entry = kk;
-            const R sc = R(1) - ts;
-            rx = rx * sc;
-            ry = ry * sc;
+            if (lost) {
+                key = kLost;
+                nlost += 1;
+            } else {
+                key = uint32_t(f) | (uint32_t(r) << 30);
+                R2 np2;
+                np2.x = L.get(next3(r));
+                np2.y = L.get(prev3(r));
+                lamp[i] = np2;
+            }
+            R2 un;
+            un.x = ux;
+            un.y = uy;
+            up[i] = un;
+            a.key[i] = key;
         }
-        if (capped || !finite) {
-            atomicOr(a.counters + 2, capped ? 1ull : 2ull);
-            atomicMin(a.counters + 3, (unsigned long long)(a.pid ? a.pid[i] : i));
-            lost = true;
+
+        // Wavefront segmented sum of the first-piece currents over runs of
+        // equal start triangle, then one LDS add per edge and run.
+        const int kprev = __shfl_up(f0, 1, 64);
+        const bool head = lane == 0 || kprev != f0;
+        const unsigned long long hm = __ballot(head);
+        const unsigned long long below = hm & ((2ull << lane) - 1ull);
+        const int seg_start = 63 - __clzll(below);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double o0 = __shfl_up(c0, off, 64);
+            const double o1 = __shfl_up(c1, off, 64);
+            const double o2 = __shfl_up(c2, off, 64);
+            if (lane - off >= seg_start) {
+                c0 += o0;
+                c1 += o1;
+                c2 += o2;
+            }
         }
-        if (lost) {
-            key = kLost;
-            nlost = 1;
-        } else {
-            key = uint32_t(f) | (uint32_t(r) << 30);
-            R2 np2;
-            np2.x = L.get(next3(r));
-            np2.y = L.get(prev3(r));
-            lamp[i] = np2;
+        const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
+        if (tail && f0 >= 0) {
+            const int4 te = m.tri_edge[f0];
+            const double q = a.qdt;
+            dep.add(te.x, ((te.w & 1) ? -q : q) * c0);
+            dep.add(te.y, ((te.w & 2) ? -q : q) * c1);
+            dep.add(te.z, ((te.w & 4) ? -q : q) * c2);
         }
-        R2 un;
-        un.x = ux;
-        un.y = uy;
-        up[i] = un;
-        a.key[i] = key;
     }
 
-    // Wavefront segmented sum of the first-piece currents over runs of
-    // equal start triangle (particles are kept sorted by triangle), then one
-    // FP64 atomic per edge and run.
-    const int lane = threadIdx.x & 63;
-    const int kprev = __shfl_up(f0, 1, 64);
-    const bool head = lane == 0 || kprev != f0;
-    const unsigned long long hm = __ballot(head);
-    const unsigned long long below = hm & ((2ull << lane) - 1ull);
-    const int seg_start = 63 - __clzll(below);
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double o0 = __shfl_up(c0, off, 64);
-        const double o1 = __shfl_up(c1, off, 64);
-        const double o2 = __shfl_up(c2, off, 64);
-        if (lane - off >= seg_start) {
-            c0 += o0;
-            c1 += o1;
-            c2 += o2;
-        }
+    // Flush the block's currents: one global FP64 atomic per distinct edge.
+    __syncthreads();
+    for (int t = threadIdx.x; t < kHash; t += kBlock) {
+        const int e = s_key[t];
+        if (e >= 0) atomic_add_f64(a.cur + e, s_val[t]);
     }
-    const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
-    if (tail && f0 >= 0) {
-        const int4 te = m.tri_edge[f0];
-        const double q = a.qdt;
-        atomic_add_f64(a.cur + te.x, ((te.w & 1) ? -q : q) * c0);
-        atomic_add_f64(a.cur + te.y, ((te.w & 2) ? -q : q) * c1);
-        atomic_add_f64(a.cur + te.z, ((te.w & 4) ? -q : q) * c2);
-    }
-    // Counters: one atomic per wavefront.
+
+    // Counters: per-block running sums in the block's own slot (launches on
+    // one stream are ordered, so no atomics are needed).
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         nseg += __shfl_down(nseg, off, 64);
         nlost += __shfl_down(nlost, off, 64);
     }
     if (lane == 0) {
-        if (nseg) atomicAdd(a.counters + 0, nseg);
-        if (nlost) atomicAdd(a.counters + 1, nlost);
+        red[0][threadIdx.x >> 6] = nseg;
+        red[1][threadIdx.x >> 6] = nlost;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s0 = 0, s1 = 0;
+#pragma unroll
+        for (int wv = 0; wv < kBlock / 64; ++wv) {
+            s0 += red[0][wv];
+            s1 += red[1][wv];
+        }
+        a.block_counts[2 * blockIdx.x] += s0;
+        a.block_counts[2 * blockIdx.x + 1] += s1;
     }
 }
 
@@ -616,7 +688,7 @@ hipError_t launch_faraday(hipStream_t s, int nf, const int4 *tri_edge, const dou
 template <int P>
 static void launch_particles_p(hipStream_t s, const MeshView &m, const StepArgs &a, bool fp32)
 {
-    const unsigned grid = grid_for(a.n, kBlock);
+    const unsigned grid = grid_for(a.n, int64_t(kBlock) * kPPT);
     if (fp32)
         hipLaunchKernelGGL((k_particle_step<P, float>), dim3(grid), dim3(kBlock), 0, s, m, a);
     else

@@ -136,8 +136,11 @@ class _TorchMemory:
             return None
 
     def _do_free(self, ptr, user):
-        if ptr:
-            self.torch.cuda.caching_allocator_delete(int(ptr))
+        # at interpreter shutdown torch may already be torn down; the
+        # process exit releases the device memory then
+        cuda = getattr(getattr(self.torch, "cuda", None), "caching_allocator_delete", None)
+        if ptr and cuda is not None:
+            cuda(int(ptr))
 
 
 # ---------------------------------------------------------------------------

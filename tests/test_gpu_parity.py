@@ -150,25 +150,51 @@ def test_boosted_oscillator_full_size_parity(oracle_lib):
     g.close()
 
 
+def _percentile_errors(osim, g):
+    el, eu, mis, total = [], [], 0, 0
+    us = max(float(np.abs(s.u).max()) for s in osim.species)
+    for si, s in enumerate(osim.species):
+        gp = g.particles(si)
+        alive = np.nonzero(s.tri >= 0)[0]
+        assert np.array_equal(gp["id"], alive), "lost sets differ"
+        same = (gp["tri"] == s.tri[alive]) & (gp["slot"] == s.slot[alive])
+        mis += int((~same).sum())
+        total += alive.size
+        el.append(np.abs(gp["lam"][same] - s.lam[alive][same]).max(axis=1))
+        eu.append(np.abs(gp["u"][same] - s.u[alive][same]).max(axis=1) / us)
+    el, eu = np.concatenate(el), np.concatenate(eu)
+    return mis, total, np.percentile(el, [50, 99, 100]), np.percentile(eu, [50, 99, 100])
+
+
 def test_mixed_precision_gauss_and_error(oracle_lib):
+    """Mixed mode against the FP64 oracle.  Without self-fields every
+    particle agrees to FP32 accuracy; in a self-consistent noisy plasma the
+    FP32 perturbations are amplified by the chaotic particle dynamics, so
+    the bound is on the bulk (99th percentile) and on conserved or
+    statistical quantities (Gauss's law to FP64 rounding, kinetic energy)."""
     w = I.pair_plasma(n_side=24, length=0.038, n_pairs=20_000, theta=0.3, steps=100,
                       precision="mixed")
-    osim = _oracle_sim(oracle_lib, w, 1)
-    g = _gpu_sim(w, 1, precision="mixed")
-    g.diagnostics()
-    osim.step(50, "boris")
-    g.step(50, "boris")
-    d = g.diagnostics()
-    assert d["gauss_rel"] <= 1e-6, d
-    # FP32 positions: ownership may differ for particles within ~1e-7 of an
-    # edge; the rest agree with the FP64 oracle to FP32 accuracy after 50 steps
-    w_ = _compare_particles(osim, g, tol_lam=5e-4, tol_u=5e-4, exact_owner=False)
-    total = sum(s.n for s in osim.species)
-    assert w_["owner_mismatch"] <= 0.01 * total, w_
-    # field energy against the oracle
-    WE, WB, WK = osim.energies()
-    assert abs(d["W_kin"] / WK - 1) < 1e-4
-    g.close()
+    weak = I.pair_plasma(n_side=24, length=0.038, n_pairs=20_000, theta=0.3, steps=100,
+                         precision="mixed")
+    for s in weak.species:
+        s.w = 1e-6  # negligible self-field
+    for wl, tol in ((weak, None), (w, 1e-4)):
+        osim = _oracle_sim(oracle_lib, wl, 1)
+        g = _gpu_sim(wl, 1, precision="mixed")
+        g.diagnostics()
+        osim.step(50, "boris")
+        g.step(50, "boris")
+        d = g.diagnostics()
+        assert d["gauss_rel"] <= 1e-6, d
+        mis, total, el, eu = _percentile_errors(osim, g)
+        assert mis <= 1e-3 * total, mis
+        if tol is None:
+            assert el[2] <= 2e-5 and eu[2] <= 2e-6, (el, eu)
+        else:
+            assert el[1] <= tol and eu[1] <= tol, (el, eu)
+            WE, WB, WK = osim.energies()
+            assert abs(d["W_kin"] / WK - 1) < 1e-4
+        g.close()
 
 
 def test_step_zero_and_empty():
