@@ -100,12 +100,23 @@ def main():
     ap.add_argument("--pairs", type=int, default=8_000_000)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device with torch (a plain copy kernel "
+                         "of known size, for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copied 1 GiB device-to-device")
     from paper_1707_04333_amd import inputs as I
     log("generating workload")
     w = I.pair_plasma(n_pairs=args.pairs, theta=args.theta, precision="mixed")

@@ -60,6 +60,54 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb)
 
 __device__ __forceinline__ void atomic_add_f64(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// Reciprocal and reciprocal square root: the hardware approximations
+// (about 1 ulp) in FP32, IEEE-rounded division and square root in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+
+// Cross-lane move of a double by a DPP control; lanes whose source is
+// outside the row (or rows disabled by RM) read 0.
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, 0xF, true);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Inclusive segmented sum over the wavefront: every lane ends with the sum
+// of its run [seg_start, lane].  Row shifts 1, 2, 4, 8 inside each row of
+// 16 lanes, then the row-15 and row-31 broadcasts across rows.
+template <int CTRL, int RM>
+__device__ __forceinline__ void seg_step(double &c0, double &c1, double &c2, bool take)
+{
+    const double o0 = dpp_f64<CTRL, RM>(c0);
+    const double o1 = dpp_f64<CTRL, RM>(c1);
+    const double o2 = dpp_f64<CTRL, RM>(c2);
+    if (take) {
+        c0 += o0;
+        c1 += o1;
+        c2 += o2;
+    }
+}
+
+__device__ __forceinline__ void wave_segmented_sum(double &c0, double &c1, double &c2, int lane,
+                                                   int seg_start)
+{
+    const int in_row = lane & 15;
+    seg_step<0x111, 0xF>(c0, c1, c2, in_row >= 1 && lane - 1 >= seg_start);
+    seg_step<0x112, 0xF>(c0, c1, c2, in_row >= 2 && lane - 2 >= seg_start);
+    seg_step<0x114, 0xF>(c0, c1, c2, in_row >= 4 && lane - 4 >= seg_start);
+    seg_step<0x118, 0xF>(c0, c1, c2, in_row >= 8 && lane - 8 >= seg_start);
+    seg_step<0x142, 0xA>(c0, c1, c2, (lane & 16) && (lane & ~15) - 1 >= seg_start);
+    seg_step<0x143, 0xC>(c0, c1, c2, lane >= 32 && 31 >= seg_start);
+}
+
 // ---------------------------------------------------------------------
 // Pushers (Sec. II.C), specialised to in-plane u and E with B along z.
 // eps = alpha E, bz = alpha Bz (beta), all in the precision R.
@@ -71,16 +119,16 @@ __device__ __forceinline__ void push2(R &ux, R &uy, R ex, R ey, R bz, R inv_c2)
     if constexpr (P == 2) {
         // Vay: exact solution of u+ = u' + (u+/gamma+) x beta with
         // u' = u + 2 eps + v(u) x beta.
-        const R g0 = sqrt(one + (ux * ux + uy * uy) * inv_c2);
-        const R vx = ux / g0, vy = uy / g0;
+        const R rg0 = rsqrt_(one + (ux * ux + uy * uy) * inv_c2);
+        const R vx = ux * rg0, vy = uy * rg0;
         const R upx = ux + ex + vy * bz + ex;
         const R upy = uy + ey - vx * bz + ey;
         const R gp2 = one + (upx * upx + upy * upy) * inv_c2;
         const R bb = bz * bz;
         const R sig = gp2 - bb;
-        const R gn = sqrt(R(0.5) * (sig + sqrt(sig * sig + R(4) * bb)));
-        const R tz = bz / gn;
-        const R s = one / (one + tz * tz);
+        const R gn = sqrt_(R(0.5) * (sig + sqrt_(sig * sig + R(4) * bb)));
+        const R tz = bz * rcp(gn);
+        const R s = rcp(one + tz * tz);
         ux = s * (upx + upy * tz);
         uy = s * (upy - upx * tz);
         return;
@@ -92,15 +140,15 @@ __device__ __forceinline__ void push2(R &ux, R &uy, R ex, R ey, R bz, R inv_c2)
         // Higuera-Cary: gamma of the midpoint momentum.
         const R bb = bz * bz;
         const R sig = gm2 - bb;
-        const R gh = sqrt(R(0.5) * (sig + sqrt(sig * sig + R(4) * bb)));
-        tz = bz / gh;
+        const R gh = sqrt_(R(0.5) * (sig + sqrt_(sig * sig + R(4) * bb)));
+        tz = bz * rcp(gh);
     } else if constexpr (P == 1) {
         // Boris with the tan correction: t = (beta/|beta|) tan(|beta|/gbar).
-        tz = tan(bz / sqrt(gm2));
+        tz = tan(bz * rsqrt_(gm2));
     } else {
-        tz = bz / sqrt(gm2);
+        tz = bz * rsqrt_(gm2);
     }
-    const R sz = R(2) * tz / (one + tz * tz);
+    const R sz = R(2) * tz * rcp(one + tz * tz);
     const R qx = umx + umy * tz;   // u' = u- + u- x t
     const R qy = umy - umx * tz;
     ux = umx + qy * sz + ex;       // u+ = u- + u' x s, then the second half kick
@@ -147,68 +195,299 @@ struct LdsCurrent {
 };
 
 // ---------------------------------------------------------------------
-// Fused particle stage: each block owns kPPT * kBlock consecutive
-// (triangle-sorted) particles, one per thread per pass.
+// Typed access to the per-triangle tables and particle streams with 32-bit
+// byte offsets (scalar base + vector offset addressing).
 // ---------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ld(const void *base, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void st(void *base, uint32_t off, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
+}
+
+template <typename R>
+struct Rec {
+    R v0x, v0y, v1x, v1y, v2x, v2y, bz;
+};
+__device__ __forceinline__ Rec<float> load_rec(const void *rec, uint32_t f)
+{
+    const float4 a = ld<float4>(rec, f * 32u), b = ld<float4>(rec, f * 32u + 16u);
+    return {a.x, a.y, a.z, a.w, b.x, b.y, b.z};
+}
+__device__ __forceinline__ Rec<double> load_rec64(const void *rec, uint32_t f)
+{
+    const double2 a = ld<double2>(rec, f * 64u), b = ld<double2>(rec, f * 64u + 16u);
+    const double2 c = ld<double2>(rec, f * 64u + 32u), d = ld<double2>(rec, f * 64u + 48u);
+    return {a.x, a.y, b.x, b.y, c.x, c.y, d.x};
+}
+
+template <typename R>
+struct Grad {
+    R x0, y0, x1, y1, x2, y2;
+};
+__device__ __forceinline__ Grad<float> load_grad(const MeshView &m, uint32_t f, float)
+{
+    const float4 a = ld<float4>(m.grad32, f * 32u), b = ld<float4>(m.grad32, f * 32u + 16u);
+    return {a.x, a.y, a.z, a.w, b.x, b.y};
+}
+__device__ __forceinline__ Grad<double> load_grad(const MeshView &m, uint32_t f, double)
+{
+    const double2 a = ld<double2>(m.grad64, f * 48u), b = ld<double2>(m.grad64, f * 48u + 16u);
+    const double2 c = ld<double2>(m.grad64, f * 48u + 32u);
+    return {a.x, a.y, b.x, b.y, c.x, c.y};
+}
+
+// x_i for a run-time local index i (two selects).
+template <typename T>
+__device__ __forceinline__ T pick(int i, T x0, T x1, T x2)
+{
+    return i == 0 ? x0 : (i == 1 ? x1 : x2);
+}
+
+// Exit edge of a straight move inside a triangle (the tracking rule):
+// candidates are the local edges k with dL_k < 0 other than the entry edge,
+// tau_k = max(l_k, 0) / (-dL_k), the smallest tau wins, ties to the
+// smallest k.  Branch-free.
+template <typename R>
+__device__ __forceinline__ void exit_edge(R l0, R l1, R l2, R d0, R d1, R d2, int entry, int &ks,
+                                          R &ts)
+{
+    const bool h0 = entry != 0 && d0 < R(0);
+    const bool h1 = entry != 1 && d1 < R(0);
+    const bool h2 = entry != 2 && d2 < R(0);
+    const R t0 = (l0 > R(0) ? l0 : R(0)) * rcp(-d0);
+    const R t1 = (l1 > R(0) ? l1 : R(0)) * rcp(-d1);
+    const R t2 = (l2 > R(0) ? l2 : R(0)) * rcp(-d2);
+    ks = h0 ? 0 : -1;
+    ts = h0 ? t0 : R(0);
+    const bool b1 = h1 && (ks < 0 || t1 < ts);
+    ks = b1 ? 1 : ks;
+    ts = b1 ? t1 : ts;
+    const bool b2 = h2 && (ks < 0 || t2 < ts);
+    ks = b2 ? 2 : ks;
+    ts = b2 ? t2 : ts;
+}
+
+// One straight piece inside triangle f.  Given the start barycentrics (L in
+// the tracking precision, Ls in FP64), the move (rx, ry) and the entry
+// edge, decide the exit and produce the end point of the piece (Lf, FP64)
+// and its current cross terms w_k = Ls_a Lf_b - Lf_a Ls_b (eq. I.assign,
+// (a, b) = (k+1, k+2)).  When the piece ends inside f, L is advanced to
+// the end point (the stored pair is L at the two non-derived slots).
+template <typename R>
+struct Piece {
+    int ks;     // exit edge, or -1
+    R ts;       // exit parameter
+    R la;       // l_{ks+1} at the exit point
+    bool done;  // ends inside f
+    double w0, w1, w2;
+};
+
+template <typename R>
+__device__ __forceinline__ Piece<R> trace_piece(const Grad<R> &g, R &l0, R &l1, R &l2,
+                                                double s0, double s1, double s2, int r, R rx,
+                                                R ry, int entry)
+{
+    Piece<R> pc;
+    const R d0 = g.x0 * rx + g.y0 * ry;
+    const R d1 = g.x1 * rx + g.y1 * ry;
+    const R d2 = g.x2 * rx + g.y2 * ry;
+    exit_edge(l0, l1, l2, d0, d1, d2, entry, pc.ks, pc.ts);
+    pc.done = pc.ks < 0 || pc.ts >= R(1);
+    // end inside: every coordinate advanced, the derived slot re-derived in FP64
+    const R n0 = l0 + d0, n1 = l1 + d1, n2 = l2 + d2;
+    const int rp = next3(r), rq = prev3(r);
+    const double dp = double(pick(rp, n0, n1, n2)), dq = double(pick(rq, n0, n1, n2));
+    const double dr = (1.0 - dp) - dq;
+    double e0 = r == 0 ? dr : double(n0);
+    double e1 = r == 1 ? dr : double(n1);
+    double e2 = r == 2 ? dr : double(n2);
+    // exit through edge ks: l_ks = 0, l_a = l_a + ts dL_a, l_b = 1 - l_a
+    const int ka = next3(pc.ks < 0 ? 0 : pc.ks);
+    pc.la = pick(ka, l0, l1, l2) + pc.ts * pick(ka, d0, d1, d2);
+    const double xa = double(pc.la), xb = 1.0 - xa;
+    if (!pc.done) {
+        e0 = pc.ks == 0 ? 0.0 : (ka == 0 ? xa : xb);
+        e1 = pc.ks == 1 ? 0.0 : (ka == 1 ? xa : xb);
+        e2 = pc.ks == 2 ? 0.0 : (ka == 2 ? xa : xb);
+    } else {
+        l0 = n0;
+        l1 = n1;
+        l2 = n2;
+    }
+    pc.w0 = s1 * e2 - e1 * s2;
+    pc.w1 = s2 * e0 - e2 * s0;
+    pc.w2 = s0 * e1 - e0 * s1;
+    return pc;
+}
+
+// Continue a particle past the edge it is leaving: move into the
+// neighbour, trace the next piece and deposit it, until the move ends
+// inside a triangle (returns true), meets a wall (lost) or exceeds the
+// crossing cap.  On return (f, r, l) hold the end triangle, derived slot
+// and barycentrics.
+template <typename R>
+__device__ __forceinline__ bool continue_track(const MeshView &m, const LdsCurrent &dep, double q,
+                                               int cap, uint32_t &f, int &r, Piece<R> pc, R &l0,
+                                               R &l1, R &l2, R rx, R ry, unsigned long long &nseg,
+                                               bool &capped)
+{
+    for (int it = 1; !pc.done; ++it) {
+        const int4 nb = ld<int4>(m.tri_nbr, f * 16u);
+        const int nbf = pick(pc.ks, nb.x, nb.y, nb.z);
+        if (nbf < 0) return false;  // wall
+        if (it >= cap) {
+            capped = true;
+            return false;
+        }
+        // CCW neighbours traverse the shared edge in opposite directions:
+        // node ks+1 of f is node kk+2 of the neighbour and vice versa.
+        const int kk = (nb.w >> (2 * pc.ks)) & 3;
+        const int b2 = prev3(kk);
+        const R la = pc.la;
+        l0 = kk == 0 ? R(0) : (b2 == 0 ? la : R(1) - la);
+        l1 = kk == 1 ? R(0) : (b2 == 1 ? la : R(1) - la);
+        l2 = kk == 2 ? R(0) : (b2 == 2 ? la : R(1) - la);
+        const double xa = double(la), xb = 1.0 - xa;
+        const double s0 = kk == 0 ? 0.0 : (b2 == 0 ? xa : xb);
+        const double s1 = kk == 1 ? 0.0 : (b2 == 1 ? xa : xb);
+        const double s2 = kk == 2 ? 0.0 : (b2 == 2 ? xa : xb);
+        r = next3(kk);
+        f = uint32_t(nbf);
+        const R sc = R(1) - pc.ts;
+        rx = rx * sc;
+        ry = ry * sc;
+        pc = trace_piece(load_grad(m, f, R(0)), l0, l1, l2, s0, s1, s2, r, rx, ry, kk);
+        nseg += 1;
+        const int4 te = ld<int4>(m.tri_edge, f * 16u);
+        dep.add(te.x, ((te.w & 1) ? -q : q) * pc.w0);
+        dep.add(te.y, ((te.w & 2) ? -q : q) * pc.w1);
+        dep.add(te.z, ((te.w & 4) ? -q : q) * pc.w2);
+    }
+    return true;
+}
+
+// Store the end state of a particle (or mark it lost) and count it.
+template <typename R>
+__device__ __forceinline__ void finish_particle(const StepArgs &a, uint32_t i, uint32_t f, int r,
+                                                R l0, R l1, R l2, bool ok, bool capped,
+                                                unsigned long long &nlost)
+{
+    using R2 = typename Vec2<R>::type;
+    uint32_t key = kLost;
+    if (capped) {
+        atomicOr(a.counters + 2, 1ull);
+        atomicMin(a.counters + 3, (unsigned long long)(a.pid ? a.pid[i] : i));
+    }
+    if (ok) {
+        key = f | (uint32_t(r) << 30);
+        R2 np2;
+        np2.x = pick(next3(r), l0, l1, l2);
+        np2.y = pick(prev3(r), l0, l1, l2);
+        st<R2>(a.lam, i * uint32_t(sizeof(R2)), np2);
+    } else {
+        nlost += 1;
+    }
+    st<uint32_t>(a.key, i * 4u, key);
+}
+
+// ---------------------------------------------------------------------
+// Fused particle stage.  Each block owns kPPT * kBlock consecutive
+// (triangle-sorted) particles.  Phase 1, one particle per thread per pass:
+// gather, push, move and the first straight piece (most particles stay in
+// their triangle); the particles that leave it are queued in LDS.  Phase 2
+// finishes the queued particles with all lanes busy.  Currents go to the
+// block's LDS edge table and are flushed once per block.
+// ---------------------------------------------------------------------
+constexpr int kQueue = 512;
+
+template <typename R>
+struct Queue {
+    uint32_t idx[kQueue];   // particle index
+    uint32_t fk[kQueue];    // triangle | exit edge << 30
+    R ts[kQueue], la[kQueue], rx[kQueue], ry[kQueue];
+};
+
 template <int P, typename R>
 __global__ __launch_bounds__(kBlock) void k_particle_step(MeshView m, StepArgs a)
 {
     using R2 = typename Vec2<R>::type;
+    constexpr uint32_t kR2 = sizeof(R2);
     __shared__ int s_key[kHash];
     __shared__ double s_val[kHash];
+    __shared__ Queue<R> s_q;
+    __shared__ int s_qn;
     __shared__ unsigned long long red[2][kBlock / 64];
     for (int t = threadIdx.x; t < kHash; t += kBlock) {
         s_key[t] = -1;
         s_val[t] = 0.0;
     }
+    if (threadIdx.x == 0) s_qn = 0;
     __syncthreads();
     const LdsCurrent dep{s_key, s_val, a.cur};
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t tile = uint32_t(xcd_tile(blockIdx.x, gridDim.x));
     const int lane = threadIdx.x & 63;
     unsigned long long nseg = 0, nlost = 0;
+    const double q = a.qdt;
 
     for (int pass = 0; pass < kPPT; ++pass) {
-        const int64_t i = (tile * kPPT + pass) * kBlock + threadIdx.x;
-        const bool in_range = i < a.n;
-        uint32_t key = in_range ? a.key[i] : kLost;
+        const uint32_t i = (tile * kPPT + pass) * kBlock + threadIdx.x;
+        const bool in_range = int64_t(i) < a.n;
+        const uint32_t key = in_range ? ld<uint32_t>(a.key, i * 4u) : kLost;
         const bool alive = key != kLost;
 
         int f0 = -1;
         double c0 = 0.0, c1 = 0.0, c2 = 0.0;  // first path piece (cross terms)
+        bool leaving = false;
+        uint32_t f = 0;
+        int r = 0;
+        R l0 = R(0), l1 = R(0), l2 = R(0), rx = R(0), ry = R(0);
+        Piece<R> pc{};
 
         if (alive) {
-            R2 *lamp = reinterpret_cast<R2 *>(a.lam);
-            R2 *up = reinterpret_cast<R2 *>(a.u);
-            R2 pr = lamp[i];
-            R2 uu = up[i];
-            int f = int(key & kTriMask);
-            int r = int(key >> 30);
-            f0 = f;
-
-            Tri3<R> L;
-            L.set(next3(r), pr.x);
-            L.set(prev3(r), pr.y);
-            L.set(r, (R(1) - pr.x) - pr.y);
-            Tri3<double> Ls;  // FP64 start point of the current path piece
-            Ls.set(next3(r), double(pr.x));
-            Ls.set(prev3(r), double(pr.y));
-            Ls.set(r, (1.0 - double(pr.x)) - double(pr.y));
+            const R2 pr = ld<R2>(a.lam, i * kR2);
+            const R2 uu = ld<R2>(a.u, i * kR2);
+            f = key & kTriMask;
+            r = int(key >> 30);
+            f0 = int(f);
+            // local barycentrics: slot r derived from the stored pair
+            const R dR = (R(1) - pr.x) - pr.y;
+            l0 = r == 0 ? dR : (r == 1 ? pr.y : pr.x);
+            l1 = r == 0 ? pr.x : (r == 1 ? dR : pr.y);
+            l2 = r == 0 ? pr.y : (r == 1 ? pr.x : dR);
+            const double dD = (1.0 - double(pr.x)) - double(pr.y);
+            const double s0 = r == 0 ? dD : double(l0);
+            const double s1 = r == 1 ? dD : double(l1);
+            const double s2 = r == 2 ? dD : double(l2);
 
             // Gather (Sec. II.B): E = sum_n l_n V_n from the triangle record.
-            const R *rec = reinterpret_cast<const R *>(a.rec) + size_t(f) * 8;
-            R ex = L.v0 * rec[0] + L.v1 * rec[2] + L.v2 * rec[4];
-            R ey = L.v0 * rec[1] + L.v1 * rec[3] + L.v2 * rec[5];
-            const R bzf = rec[6];
+            R ex, ey, bzf;
+            if constexpr (sizeof(R) == 4) {
+                const Rec<float> rc = load_rec(a.rec, f);
+                ex = l0 * rc.v0x + l1 * rc.v1x + l2 * rc.v2x;
+                ey = l0 * rc.v0y + l1 * rc.v1y + l2 * rc.v2y;
+                bzf = rc.bz;
+            } else {
+                const Rec<double> rc = load_rec64(a.rec, f);
+                ex = l0 * rc.v0x + l1 * rc.v1x + l2 * rc.v2x;
+                ey = l0 * rc.v0y + l1 * rc.v1y + l2 * rc.v2y;
+                bzf = rc.bz;
+            }
             if (a.has_affine) {
                 R x, y;
                 if constexpr (sizeof(R) == 4) {
-                    const float *v = m.vxy32 + size_t(f) * 8;
-                    x = L.v0 * v[0] + L.v1 * v[2] + L.v2 * v[4];
-                    y = L.v0 * v[1] + L.v1 * v[3] + L.v2 * v[5];
+                    const float4 va = ld<float4>(m.vxy32, f * 32u), vb = ld<float4>(m.vxy32, f * 32u + 16u);
+                    x = l0 * va.x + l1 * va.z + l2 * vb.x;
+                    y = l0 * va.y + l1 * va.w + l2 * vb.y;
                 } else {
-                    const double *v = m.vxy64 + size_t(f) * 6;
-                    x = L.v0 * v[0] + L.v1 * v[2] + L.v2 * v[4];
-                    y = L.v0 * v[1] + L.v1 * v[3] + L.v2 * v[5];
+                    const double2 va = ld<double2>(m.vxy64, f * 48u), vb = ld<double2>(m.vxy64, f * 48u + 16u);
+                    const double2 vc = ld<double2>(m.vxy64, f * 48u + 32u);
+                    x = l0 * va.x + l1 * vb.x + l2 * vc.x;
+                    y = l0 * va.y + l1 * vb.y + l2 * vc.y;
                 }
                 ex += R(a.aff[0]) + R(a.aff[2]) * x + R(a.aff[3]) * y;
                 ey += R(a.aff[1]) + R(a.aff[4]) * x + R(a.aff[5]) * y;
@@ -219,131 +498,56 @@ __global__ __launch_bounds__(kBlock) void k_particle_step(MeshView m, StepArgs a
             R ux = uu.x, uy = uu.y;
             push2<P, R>(ux, uy, alpha * ex, alpha * ey, alpha * bzf, R(a.inv_c2));
             const bool finite = isfinite(ux) && isfinite(uy);
-
-            // Move: dr = dt u / gamma (Sec. II.C eq. eq.motion.dis).
-            const R ginv = R(1) / sqrt(R(1) + (ux * ux + uy * uy) * R(a.inv_c2));
-            R rx = R(a.dt) * ux * ginv;
-            R ry = R(a.dt) * uy * ginv;
-            if (!finite) {
-                rx = R(0);
-                ry = R(0);
-            }
-
-            // Track across edges, depositing every straight piece (Sec. II.D).
-            int entry = -1;
-            bool lost = false, capped = false;
-            for (int it = 0;; ++it) {
-                if (it >= a.cap) {
-                    capped = true;
-                    break;
-                }
-                const R *g;
-                if constexpr (sizeof(R) == 4) g = m.grad32 + size_t(f) * 8;
-                else g = m.grad64 + size_t(f) * 6;
-                Tri3<R> dL;
-                dL.v0 = g[0] * rx + g[1] * ry;
-                dL.v1 = g[2] * rx + g[3] * ry;
-                dL.v2 = g[4] * rx + g[5] * ry;
-                int ks = -1;
-                R ts = R(0);
-                if (entry != 0 && dL.v0 < R(0)) {
-                    ks = 0;
-                    ts = (L.v0 > R(0) ? L.v0 : R(0)) / (-dL.v0);
-                }
-                if (entry != 1 && dL.v1 < R(0)) {
-                    const R tk = (L.v1 > R(0) ? L.v1 : R(0)) / (-dL.v1);
-                    if (ks < 0 || tk < ts) {
-                        ks = 1;
-                        ts = tk;
-                    }
-                }
-                if (entry != 2 && dL.v2 < R(0)) {
-                    const R tk = (L.v2 > R(0) ? L.v2 : R(0)) / (-dL.v2);
-                    if (ks < 0 || tk < ts) {
-                        ks = 2;
-                        ts = tk;
-                    }
-                }
-                const bool done = ks < 0 || ts >= R(1);
-                Tri3<double> Lf;
-                R la = R(0);
-                if (done) {
-                    const int p = next3(r), q = prev3(r);
-                    const R np = L.get(p) + dL.get(p);
-                    const R nq = L.get(q) + dL.get(q);
-                    L.set(p, np);
-                    L.set(q, nq);
-                    Lf.set(p, double(np));
-                    Lf.set(q, double(nq));
-                    Lf.set(r, (1.0 - double(np)) - double(nq));
-                } else {
-                    const int ia = next3(ks);
-                    la = L.get(ia) + ts * dL.get(ia);
-                    Lf.set(ks, 0.0);
-                    Lf.set(ia, double(la));
-                    Lf.set(prev3(ks), 1.0 - double(la));
-                }
-                // eq. I.assign for the three local edges (a, b) = (k+1, k+2).
-                const double w0 = Ls.v1 * Lf.v2 - Lf.v1 * Ls.v2;
-                const double w1 = Ls.v2 * Lf.v0 - Lf.v2 * Ls.v0;
-                const double w2 = Ls.v0 * Lf.v1 - Lf.v0 * Ls.v1;
-                ++nseg;
-                if (it == 0) {
-                    c0 = w0;
-                    c1 = w1;
-                    c2 = w2;
-                } else {
-                    const int4 te = m.tri_edge[f];
-                    const double q = a.qdt;
-                    dep.add(te.x, ((te.w & 1) ? -q : q) * w0);
-                    dep.add(te.y, ((te.w & 2) ? -q : q) * w1);
-                    dep.add(te.z, ((te.w & 4) ? -q : q) * w2);
-                }
-                if (done) break;
-                const int4 nb = m.tri_nbr[f];
-                const int nbf = ks == 0 ? nb.x : (ks == 1 ? nb.y : nb.z);
-                if (nbf < 0) {
-                    lost = true;
-                    break;
-                }
-                // CCW neighbours traverse the shared edge in opposite
-                // directions: node (ks+1) of f is node (kk+2) of the
-                // neighbour and vice versa.
-                const int kk = (nb.w >> (2 * ks)) & 3;
-                const int a2 = next3(kk), b2 = prev3(kk);
-                L.set(kk, R(0));
-                L.set(b2, la);
-                L.set(a2, R(1) - la);
-                Ls.set(kk, 0.0);
-                Ls.set(b2, double(la));
-                Ls.set(a2, 1.0 - double(la));
-                r = a2;
-                f = nbf;
-                entry = kk;
-                const R sc = R(1) - ts;
-                rx = rx * sc;
-                ry = ry * sc;
-            }
-            if (capped || !finite) {
-                atomicOr(a.counters + 2, capped ? 1ull : 2ull);
-                atomicMin(a.counters + 3, (unsigned long long)(a.pid ? a.pid[i] : i));
-                lost = true;
-            }
-            if (lost) {
-                key = kLost;
-                nlost += 1;
-            } else {
-                key = uint32_t(f) | (uint32_t(r) << 30);
-                R2 np2;
-                np2.x = L.get(next3(r));
-                np2.y = L.get(prev3(r));
-                lamp[i] = np2;
-            }
             R2 un;
             un.x = ux;
             un.y = uy;
-            up[i] = un;
-            a.key[i] = key;
+            st<R2>(a.u, i * kR2, un);
+
+            // Move: dr = dt u / gamma (Sec. II.C eq. eq.motion.dis).
+            const R ginv = rsqrt_(R(1) + (ux * ux + uy * uy) * R(a.inv_c2));
+            rx = finite ? R(a.dt) * ux * ginv : R(0);
+            ry = finite ? R(a.dt) * uy * ginv : R(0);
+
+            // First straight piece, in the start triangle (Sec. II.D).
+            pc = trace_piece(load_grad(m, f, R(0)), l0, l1, l2, s0, s1, s2, r, rx, ry, -1);
+            c0 = pc.w0;
+            c1 = pc.w1;
+            c2 = pc.w2;
+            nseg += 1;
+            if (!finite) {
+                atomicOr(a.counters + 2, 2ull);
+                atomicMin(a.counters + 3, (unsigned long long)(a.pid ? a.pid[i] : i));
+                finish_particle<R>(a, i, f, r, l0, l1, l2, false, false, nlost);
+            } else if (pc.done) {
+                finish_particle<R>(a, i, f, r, l0, l1, l2, true, false, nlost);
+            } else {
+                leaving = true;
+            }
+        }
+
+        // Queue the particles leaving their triangle (one LDS atomic per
+        // wavefront); overflow is finished in place.
+        const unsigned long long lm = __ballot(leaving);
+        if (lm) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_qn, __popcll(lm));
+            base = __shfl(base, 0, 64);
+            const int slot = base + __popcll(lm & ((1ull << lane) - 1ull));
+            if (leaving) {
+                if (slot < kQueue) {
+                    s_q.idx[slot] = i;
+                    s_q.fk[slot] = f | (uint32_t(pc.ks) << 30);
+                    s_q.ts[slot] = pc.ts;
+                    s_q.la[slot] = pc.la;
+                    s_q.rx[slot] = rx;
+                    s_q.ry[slot] = ry;
+                } else {
+                    bool capped = false;
+                    const bool ok = continue_track(m, dep, q, a.cap, f, r, pc, l0, l1, l2, rx, ry,
+                                                   nseg, capped);
+                    finish_particle<R>(a, i, f, r, l0, l1, l2, ok, capped, nlost);
+                }
+            }
         }
 
         // Wavefront segmented sum of the first-piece currents over runs of
@@ -353,25 +557,33 @@ __global__ __launch_bounds__(kBlock) void k_particle_step(MeshView m, StepArgs a
         const unsigned long long hm = __ballot(head);
         const unsigned long long below = hm & ((2ull << lane) - 1ull);
         const int seg_start = 63 - __clzll(below);
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const double o0 = __shfl_up(c0, off, 64);
-            const double o1 = __shfl_up(c1, off, 64);
-            const double o2 = __shfl_up(c2, off, 64);
-            if (lane - off >= seg_start) {
-                c0 += o0;
-                c1 += o1;
-                c2 += o2;
-            }
-        }
+        wave_segmented_sum(c0, c1, c2, lane, seg_start);
         const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
         if (tail && f0 >= 0) {
-            const int4 te = m.tri_edge[f0];
-            const double q = a.qdt;
+            const int4 te = ld<int4>(m.tri_edge, uint32_t(f0) * 16u);
             dep.add(te.x, ((te.w & 1) ? -q : q) * c0);
             dep.add(te.y, ((te.w & 2) ? -q : q) * c1);
             dep.add(te.z, ((te.w & 4) ? -q : q) * c2);
         }
+    }
+
+    // Phase 2: finish the queued particles, all lanes busy.
+    __syncthreads();
+    const int nq = s_qn < kQueue ? s_qn : kQueue;
+    for (int t = threadIdx.x; t < nq; t += kBlock) {
+        const uint32_t i = s_q.idx[t];
+        uint32_t f = s_q.fk[t] & kTriMask;
+        Piece<R> pc{};
+        pc.ks = int(s_q.fk[t] >> 30);
+        pc.ts = s_q.ts[t];
+        pc.la = s_q.la[t];
+        pc.done = false;
+        int r = 0;
+        R l0 = R(0), l1 = R(0), l2 = R(0);
+        bool capped = false;
+        const bool ok = continue_track(m, dep, q, a.cap, f, r, pc, l0, l1, l2, s_q.rx[t],
+                                       s_q.ry[t], nseg, capped);
+        finish_particle<R>(a, i, f, r, l0, l1, l2, ok, capped, nlost);
     }
 
     // Flush the block's currents: one global FP64 atomic per distinct edge.
