@@ -210,6 +210,32 @@ fetd_status fetd_profile(fetd_sim *sim, int32_t enable);
 #define FETD_N_STAGES 5
 fetd_status fetd_stage_times(fetd_sim *sim, double *ms, int64_t *launches);
 
+/* Autotune the re-sort cadence: sort now, advance trial_steps real PIC
+ * steps with the given pusher while timing the particle stage of every step
+ * and the sort with HIP events, then set the re-sort interval K that
+ * minimises (T_sort + sum_{j<K} T_particles(j)) / K over the candidates
+ * 5, 10, 20, 40, 80, 160 (up to trial_steps).  *chosen gets K.  The
+ * simulation advances by trial_steps steps. */
+fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps, int32_t *chosen);
+
+/* Set the re-sort interval directly (k >= 1). */
+fetd_status fetd_set_resort(fetd_sim *sim, int32_t every);
+
+/* Batched stepping of many independent simulations (parameter sweeps):
+ * every phase of a step (Faraday, particle stage, Ampere, SpMV) is one
+ * persistent launch over the flattened work of all runs; with use_graph
+ * the launch sequence of a full re-sort cycle is captured once in a HIP
+ * graph and replayed.  All simulations must live on the same device and
+ * stream and have the same precision; they stay individually usable
+ * (fields_get, particles_get, diagnostics) between batch steps.  The batch
+ * keeps pointers to the simulations: destroy it before them.  Re-sorting
+ * follows resort_every of the first simulation. */
+typedef struct fetd_batch fetd_batch;
+fetd_status fetd_batch_create(fetd_sim *const *sims, int32_t n, int32_t use_graph,
+                              fetd_batch **out);
+fetd_status fetd_batch_step(fetd_batch *batch, int32_t n_steps, int32_t pusher);
+void fetd_batch_destroy(fetd_batch *batch);
+
 /* Sizes and SPAI quality. */
 fetd_status fetd_info_get(fetd_sim *sim, fetd_info *out);
 

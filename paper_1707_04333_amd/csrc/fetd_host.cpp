@@ -30,7 +30,10 @@ struct Species {
     int64_t n_loaded = 0;  // ids 0..n_loaded-1
     int64_t n = 0;         // slots in use (alive + lost-but-not-yet-dropped)
     int64_t offset = 0;    // first slot in the particle arrays
+    int64_t bc_offset = 0; // first per-tile counter slot (pairs) of the species
 };
+
+int64_t tiles_of(int64_t n) { return (n + int64_t(kBlock) * kPPT - 1) / (int64_t(kBlock) * kPPT); }
 
 struct Csr {
     std::vector<int32_t> ptr, col;
@@ -73,8 +76,8 @@ struct fetd_sim {
     double *d_sl_val = nullptr;
     // device: fields
     double *d_b = nullptr, *d_h = nullptr, *d_d = nullptr, *d_e = nullptr;
-    double *d_cur[2] = {nullptr, nullptr};
-    int cur_active = 0;
+    double *d_cur = nullptr;       // current accumulator of the step in progress
+    double *d_cur_last = nullptr;  // current of the last completed step
     void *d_rec = nullptr;
     double *d_bz_ext = nullptr, *d_e_ext = nullptr, *d_damp = nullptr;
     bool has_affine = false;
@@ -658,8 +661,8 @@ fetd_status upload_mesh(fetd_sim *s)
     if ((st = alloc_zero(s, &s->d_h, nf))) return st;
     if ((st = alloc_zero(s, &s->d_d, ne))) return st;
     if ((st = alloc_zero(s, &s->d_e, ne))) return st;
-    if ((st = alloc_zero(s, &s->d_cur[0], ne))) return st;
-    if ((st = alloc_zero(s, &s->d_cur[1], ne))) return st;
+    if ((st = alloc_zero(s, &s->d_cur, ne))) return st;
+    if ((st = alloc_zero(s, &s->d_cur_last, ne))) return st;
     void *rec = nullptr;
     if (!s->dev_alloc(&rec, 8 * s->real_bytes() * size_t(nf)))
         return s->fail(FETD_E_OOM, "device allocation failed");
@@ -706,22 +709,21 @@ fetd_status download(fetd_sim *s, void *dst, const void *src, size_t bytes);
 
 fetd_status grow_block_counts(fetd_sim *s, int64_t extra)
 {
-    // per-block counter slots for the largest particle launch (one species)
-    int64_t max_n = extra;
-    for (const Species &sp : s->species) max_n = std::max(max_n, sp.n);
-    const int64_t blocks = (max_n + int64_t(kBlock) * kPPT - 1) / (int64_t(kBlock) * kPPT) + 1;
-    if (blocks > s->block_count_cap) {
-        std::vector<unsigned long long> old(2 * size_t(s->block_count_cap), 0ull);
+    // per-tile counter pairs: one region per species, the new one appended
+    int64_t used = 0;
+    for (const Species &sp : s->species) used = std::max(used, sp.bc_offset + tiles_of(sp.n));
+    const int64_t need = used + tiles_of(extra) + 1;
+    if (need > s->block_count_cap) {
+        std::vector<unsigned long long> old(2 * size_t(need), 0ull);
         if (s->block_count_cap > 0) {
             fetd_status st = download(s, old.data(), s->d_block_counts, 16 * size_t(s->block_count_cap));
             if (st) return st;
         }
-        old.resize(2 * size_t(blocks), 0ull);
         s->dev_free(s->d_block_counts);
         s->d_block_counts = nullptr;
         fetd_status st = upload(s, &s->d_block_counts, old.data(), old.size());
         if (st) return st;
-        s->block_count_cap = blocks;
+        s->block_count_cap = need;
     }
     return FETD_OK;
 }
@@ -797,10 +799,8 @@ fetd_status sort_all(fetd_sim *s)
         a.offsets = s->d_offsets;
         a.block_sums = s->d_block_sums;
         a.elem_bytes = int(2 * rb);
-        // slots past the alive count keep the lost key
-        hipError_t e = hipMemsetAsync(a.key_out, 0xFF, sizeof(uint32_t) * size_t(sp.n), s->stream);
-        if (e != hipSuccess) return s->hip_fail(e, "sort");
-        e = launch_sort(s->stream, a);
+        // launch_sort fills key_out with the lost key first (slots past the alive count)
+        hipError_t e = launch_sort(s->stream, a);
         if (e != hipSuccess) return s->hip_fail(e, "sort");
     }
     s->pbuf = ob;
@@ -1002,6 +1002,8 @@ fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, 
     sp.n_loaded = n;
     sp.n = n;
     sp.offset = s->species.empty() ? 0 : s->species.back().offset + s->species.back().n;
+    sp.bc_offset = s->species.empty() ? 0 :
+        s->species.back().bc_offset + tiles_of(s->species.back().n);
     const size_t rb = s->real_bytes();
     std::vector<uint32_t> key(n);
     std::vector<int32_t> pid(n);
@@ -1146,7 +1148,7 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
                                       s->d_grad64, s->d_rec, s->fp32(), s->dt);
         }
         if (e != hipSuccess) return s->hip_fail(e, "faraday");
-        double *cur = s->d_cur[s->cur_active];
+        double *cur = s->d_cur;
         for (const Species &sp : s->species) {
             StepArgs a;
             a.n = sp.n;
@@ -1165,15 +1167,14 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
             a.has_affine = s->has_affine ? 1 : 0;
             for (int k = 0; k < 6; ++k) a.aff[k] = s->affine[k];
             a.counters = s->d_counters;
-            a.block_counts = s->d_block_counts;
+            a.block_counts = s->d_block_counts + 2 * sp.bc_offset;
             fetd_sim::Timer t(s, 1);
             e = launch_particles(s->stream, mv, a, pusher, s->fp32());
             if (e != hipSuccess) return s->hip_fail(e, "particle step");
         }
-        double *next = s->d_cur[1 - s->cur_active];
         {
             fetd_sim::Timer t(s, 2);
-            e = launch_ampere(s->stream, s->ne, s->d_edge_face, s->d_h, cur, next, s->d_d,
+            e = launch_ampere(s->stream, s->ne, s->d_edge_face, s->d_h, cur, s->d_cur_last, s->d_d,
                               s->d_damp, s->dt);
         }
         if (e != hipSuccess) return s->hip_fail(e, "ampere");
@@ -1183,7 +1184,6 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
                             s->d_d, s->d_e);
         }
         if (e != hipSuccess) return s->hip_fail(e, "spmv");
-        s->cur_active = 1 - s->cur_active;
         ++s->step;
         ++s->steps_since_sort;
     }
@@ -1212,7 +1212,7 @@ fetd_status fetd_fields_get(fetd_sim *s, int32_t which, void *dst, int64_t capac
     case FETD_FIELD_E: src = s->d_e; bytes = 8 * size_t(s->ne); break;
     case FETD_FIELD_D: src = s->d_d; bytes = 8 * size_t(s->ne); break;
     case FETD_FIELD_B: src = s->d_b; bytes = 8 * size_t(s->nf); break;
-    case FETD_FIELD_J: src = s->d_cur[1 - s->cur_active]; bytes = 8 * size_t(s->ne); break;
+    case FETD_FIELD_J: src = s->d_cur_last; bytes = 8 * size_t(s->ne); break;
     case FETD_FIELD_Q:
         if ((st = compute_charge(s))) return st;
         src = s->d_q;
@@ -1317,7 +1317,7 @@ fetd_status fetd_diagnostics(fetd_sim *s, fetd_diag *out)
     if ((st = download(s, e.data(), s->d_e, 8 * size_t(ne)))) return st;
     if ((st = download(s, d.data(), s->d_d, 8 * size_t(ne)))) return st;
     if ((st = download(s, b.data(), s->d_b, 8 * size_t(s->nf)))) return st;
-    if ((st = download(s, jl.data(), s->d_cur[1 - s->cur_active], 8 * size_t(ne)))) return st;
+    if ((st = download(s, jl.data(), s->d_cur_last, 8 * size_t(ne)))) return st;
     double gmax = 0, qmax = 0;
     for (int n = 0; n < nn; ++n) {
         qmax = std::max(qmax, std::max(std::fabs(q[n]), std::fabs(s->q0[n])));
@@ -1423,6 +1423,64 @@ fetd_status fetd_stage_times(fetd_sim *s, double *ms, int64_t *launches)
     return FETD_OK;
 }
 
+fetd_status fetd_set_resort(fetd_sim *s, int32_t every)
+{
+    if (!s || every < 1) return FETD_E_ARG;
+    s->resort_every = every;
+    return FETD_OK;
+}
+
+fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int32_t *chosen)
+{
+    if (!s || trial_steps < 2 || pusher < 0 || pusher > 3) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    fetd_status st;
+    const bool was_profiling = s->profiling;
+    const int saved = s->resort_every;
+    // one timed sort
+    if ((st = fetd_profile(s, 1))) return st;
+    {
+        fetd_sim::Timer t(s, 4);
+        if ((st = sort_all(s))) return st;
+    }
+    double ms[FETD_N_STAGES];
+    int64_t n[FETD_N_STAGES];
+    if ((st = fetd_stage_times(s, ms, n))) return st;
+    const double t_sort = ms[4];
+    // particle-stage time per step as the order decays after the sort
+    s->resort_every = std::numeric_limits<int>::max();
+    const int nsp = int(std::count_if(s->species.begin(), s->species.end(),
+                                      [](const Species &x) { return x.n > 0; }));
+    std::vector<double> tp(trial_steps, 0.0);
+    if ((st = fetd_profile(s, 1))) return st;
+    if ((st = fetd_pic_step(s, trial_steps, pusher))) return st;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "autotune");
+    const auto &ev = s->timed[1];
+    for (size_t k = 0; k < ev.size(); ++k) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[k].first, ev[k].second) == hipSuccess && nsp > 0)
+            tp[std::min<size_t>(k / nsp, size_t(trial_steps) - 1)] += double(t);
+    }
+    int best = saved;
+    double best_cost = std::numeric_limits<double>::max();
+    for (int K : {5, 10, 20, 40, 80, 160}) {
+        if (K > trial_steps) break;
+        double sum = t_sort;
+        for (int j = 0; j < K; ++j) sum += tp[j];
+        const double cost = sum / K;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = K;
+        }
+    }
+    s->resort_every = best;
+    s->steps_since_sort = trial_steps;  // the order has decayed: sort at the next step
+    if ((st = fetd_profile(s, was_profiling ? 1 : 0))) return st;
+    if (chosen) *chosen = best;
+    return FETD_OK;
+}
+
 fetd_status fetd_info_get(fetd_sim *s, fetd_info *out)
 {
     if (!s || !out) return FETD_E_ARG;
@@ -1436,6 +1494,307 @@ fetd_status fetd_info_get(fetd_sim *s, fetd_info *out)
     out->n_species = int32_t(s->species.size());
     out->device_bytes = s->device_bytes;
     return FETD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------
+// Batched stepping.
+// ---------------------------------------------------------------------
+struct fetd_batch {
+    std::vector<fetd_sim *> sims;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool fp32 = false;
+    bool use_graph = false;
+    int nrun = 0, nseg = 0;
+    uint32_t tri_blocks = 0, edge_blocks = 0, tiles = 0;
+    FieldDesc *d_fields = nullptr;
+    uint32_t *d_tri_prefix = nullptr, *d_edge_prefix = nullptr, *d_seg_prefix = nullptr;
+    SegDesc *d_segs[2] = {nullptr, nullptr};  // [parity of sorts since creation]
+    std::vector<int> pbuf0;                   // particle buffer of each run at creation
+    int parity = 0;
+    int steps_since_sort = 0;
+    int resort_every = 20;
+    hipGraphExec_t graph = nullptr;
+    int graph_pusher = -1;
+    std::string err;
+};
+
+namespace {
+
+fetd_status batch_fail(fetd_batch *b, fetd_status st, const std::string &msg)
+{
+    b->err = msg;
+    g_last_error = msg;
+    return st;
+}
+
+template <typename T>
+bool batch_upload(fetd_batch *b, T **dst, const std::vector<T> &v)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * std::max<size_t>(1, v.size())) != hipSuccess) return false;
+    *dst = static_cast<T *>(p);
+    if (v.empty()) return true;
+    return hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, b->stream) ==
+               hipSuccess &&
+           hipStreamSynchronize(b->stream) == hipSuccess;
+}
+
+SegDesc seg_desc(fetd_sim *s, const Species &sp, int pbuf)
+{
+    SegDesc d{};
+    d.m.tri_edge = s->d_tri_edge;
+    d.m.tri_nbr = s->d_tri_nbr;
+    d.m.grad64 = s->d_grad64;
+    d.m.grad32 = s->d_grad32;
+    d.m.vxy64 = s->d_vxy64;
+    d.m.vxy32 = s->d_vxy32;
+    const size_t rb = s->real_bytes();
+    StepArgs &a = d.a;
+    a.n = sp.n;
+    a.key = s->d_key[pbuf] + sp.offset;
+    a.lam = static_cast<char *>(s->d_lam[pbuf]) + 2 * rb * sp.offset;
+    a.u = static_cast<char *>(s->d_u[pbuf]) + 2 * rb * sp.offset;
+    a.pid = s->d_pid[pbuf] + sp.offset;
+    a.rec = s->d_rec;
+    a.cur = s->d_cur;
+    a.qdt = sp.q * sp.w / s->dt;
+    a.alpha = sp.q * s->dt / (2.0 * sp.m);
+    a.dt = s->dt;
+    a.c = s->c;
+    a.inv_c2 = 1.0 / (s->c * s->c);
+    a.cap = s->cap;
+    a.has_affine = s->has_affine ? 1 : 0;
+    for (int k = 0; k < 6; ++k) a.aff[k] = s->affine[k];
+    a.counters = s->d_counters;
+    a.block_counts = s->d_block_counts + 2 * sp.bc_offset;
+    return d;
+}
+
+fetd_status batch_build(fetd_batch *b)
+{
+    std::vector<FieldDesc> fd;
+    std::vector<uint32_t> tp(1, 0), ep(1, 0), sp(1, 0);
+    std::vector<SegDesc> seg[2];
+    for (fetd_sim *s : b->sims) {
+        FieldDesc d{};
+        d.nf = s->nf;
+        d.ne = s->ne;
+        d.tri_edge = s->d_tri_edge;
+        d.e = s->d_e;
+        d.e_ext = s->d_e_ext;
+        d.b = s->d_b;
+        d.h = s->d_h;
+        d.inv_mu_area = s->d_inv_mu_area;
+        d.inv_2area = s->d_inv_2area;
+        d.bz_ext = s->d_bz_ext;
+        d.grad64 = s->d_grad64;
+        d.rec = s->d_rec;
+        d.rec_fp32 = s->fp32() ? 1 : 0;
+        d.dt = s->dt;
+        d.edge_face = s->d_edge_face;
+        d.cur = s->d_cur;
+        d.cur_last = s->d_cur_last;
+        d.d = s->d_d;
+        d.damp = s->d_damp;
+        d.sl_ptr = s->d_sl_ptr;
+        d.sl_w = s->d_sl_w;
+        d.sl_col = s->d_sl_col;
+        d.sl_val = s->d_sl_val;
+        d.e_out = s->d_e;
+        fd.push_back(d);
+        tp.push_back(tp.back() + uint32_t((s->nf + 255) / 256));
+        ep.push_back(ep.back() + uint32_t((s->ne + 255) / 256));
+        for (const Species &x : s->species) {
+            if (x.n == 0) continue;
+            for (int par = 0; par < 2; ++par) seg[par].push_back(seg_desc(s, x, s->pbuf ^ par));
+            sp.push_back(sp.back() + uint32_t(tiles_of(x.n)));
+        }
+    }
+    b->nrun = int(b->sims.size());
+    b->nseg = int(seg[0].size());
+    b->tri_blocks = tp.back();
+    b->edge_blocks = ep.back();
+    b->tiles = sp.back();
+    b->pbuf0.clear();
+    for (fetd_sim *s : b->sims) b->pbuf0.push_back(s->pbuf);
+    b->parity = 0;
+    if (!batch_upload(b, &b->d_fields, fd) || !batch_upload(b, &b->d_tri_prefix, tp) ||
+        !batch_upload(b, &b->d_edge_prefix, ep) || !batch_upload(b, &b->d_seg_prefix, sp) ||
+        !batch_upload(b, &b->d_segs[0], seg[0]) || !batch_upload(b, &b->d_segs[1], seg[1]))
+        return batch_fail(b, FETD_E_OOM, "batch descriptors");
+    return FETD_OK;
+}
+
+void batch_release(fetd_batch *b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    for (void *p : {(void *)b->d_fields, (void *)b->d_tri_prefix, (void *)b->d_edge_prefix,
+                    (void *)b->d_seg_prefix, (void *)b->d_segs[0], (void *)b->d_segs[1]})
+        if (p) (void)hipFree(p);
+    b->d_fields = nullptr;
+    b->d_tri_prefix = b->d_edge_prefix = b->d_seg_prefix = nullptr;
+    b->d_segs[0] = b->d_segs[1] = nullptr;
+}
+
+// Enqueue n batched steps (re-sorting when due) on the batch stream.
+fetd_status batch_enqueue(fetd_batch *b, int n, int pusher)
+{
+    for (int it = 0; it < n; ++it) {
+        if (b->steps_since_sort >= b->resort_every) {
+            for (fetd_sim *s : b->sims)
+                if (fetd_status st = sort_all(s)) return batch_fail(b, st, s->err);
+            b->parity ^= 1;
+            b->steps_since_sort = 0;
+        }
+        hipError_t e = launch_faraday_batched(b->stream, b->d_fields, b->d_tri_prefix, b->nrun,
+                                              b->tri_blocks);
+        if (e == hipSuccess)
+            e = launch_particles_batched(b->stream, b->d_segs[b->parity], b->d_seg_prefix, b->nseg,
+                                         b->tiles, pusher, b->fp32);
+        if (e == hipSuccess)
+            e = launch_ampere_batched(b->stream, b->d_fields, b->d_edge_prefix, b->nrun,
+                                      b->edge_blocks);
+        if (e == hipSuccess)
+            e = launch_spmv_batched(b->stream, b->d_fields, b->d_edge_prefix, b->nrun,
+                                    b->edge_blocks);
+        if (e != hipSuccess) return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
+        ++b->steps_since_sort;
+        for (fetd_sim *s : b->sims) {
+            ++s->step;
+            s->steps_since_sort = b->steps_since_sort;
+        }
+    }
+    return FETD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fetd_status fetd_batch_create(fetd_sim *const *sims, int32_t n, int32_t use_graph,
+                              fetd_batch **out)
+{
+    if (!out || !sims || n <= 0) {
+        g_last_error = "invalid batch arguments";
+        return FETD_E_ARG;
+    }
+    *out = nullptr;
+    fetd_batch *b = new (std::nothrow) fetd_batch();
+    if (!b) return FETD_E_OOM;
+    b->sims.assign(sims, sims + n);
+    b->stream = sims[0]->stream;
+    b->device = sims[0]->device;
+    b->fp32 = sims[0]->fp32();
+    b->use_graph = use_graph != 0;
+    b->resort_every = sims[0]->resort_every;
+    for (fetd_sim *s : b->sims) {
+        if (!s || s->stream != b->stream || s->device != b->device || s->fp32() != b->fp32) {
+            delete b;
+            g_last_error = "batch members must share device, stream and precision";
+            return FETD_E_ARG;
+        }
+    }
+    DeviceGuard g(b->device);
+    for (fetd_sim *s : b->sims)
+        if (!s->have_baseline)
+            if (fetd_status st = take_baseline(s)) {
+                delete b;
+                g_last_error = s->err;
+                return st;
+            }
+    b->steps_since_sort = 0;
+    for (fetd_sim *s : b->sims) b->steps_since_sort = std::max<int>(b->steps_since_sort, int(s->steps_since_sort));
+    if (fetd_status st = batch_build(b)) {
+        batch_release(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return FETD_OK;
+}
+
+fetd_status fetd_batch_step(fetd_batch *b, int32_t n_steps, int32_t pusher)
+{
+    if (!b || n_steps < 0 || pusher < 0 || pusher > 3) return FETD_E_ARG;
+    DeviceGuard g(b->device);
+    // the members may have been sorted or reloaded individually: rebuild
+    bool stale = false;
+    for (size_t r = 0; r < b->sims.size(); ++r)
+        if ((b->sims[r]->pbuf ^ b->parity) != b->pbuf0[r]) stale = true;
+    if (stale) {
+        batch_release(b);
+        if (fetd_status st = batch_build(b)) return st;
+    }
+    if (!b->use_graph) return batch_enqueue(b, n_steps, pusher);
+    // Graph mode: one captured cycle = 2 re-sort intervals starting right
+    // before a sort (the particle buffers and parity return to their state).
+    const int K = b->resort_every;
+    int left = n_steps;
+    // eager steps up to the next sort
+    const int lead = std::min(left, std::max(0, K - b->steps_since_sort));
+    if (fetd_status st = batch_enqueue(b, lead, pusher)) return st;
+    left -= lead;
+    const int cycle = 2 * K;
+    if (left >= cycle) {
+        if (!b->graph || b->graph_pusher != pusher) {
+            if (b->graph) (void)hipGraphExecDestroy(b->graph);
+            b->graph = nullptr;
+            // capture with the host counters advanced as during replay
+            const int save_parity = b->parity, save_since = b->steps_since_sort;
+            std::vector<int64_t> save_step, save_since_sim;
+            std::vector<int> save_pbuf;
+            for (fetd_sim *s : b->sims) {
+                save_step.push_back(s->step);
+                save_since_sim.push_back(s->steps_since_sort);
+                save_pbuf.push_back(s->pbuf);
+            }
+            hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
+            fetd_status st = batch_enqueue(b, cycle, pusher);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(b->stream, &graph);
+            b->parity = save_parity;
+            b->steps_since_sort = save_since;
+            for (size_t r = 0; r < b->sims.size(); ++r) {
+                b->sims[r]->step = save_step[r];
+                b->sims[r]->steps_since_sort = save_since_sim[r];
+                b->sims[r]->pbuf = save_pbuf[r];
+            }
+            if (st) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
+            e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
+            b->graph_pusher = pusher;
+        }
+        while (left >= cycle) {
+            hipError_t e = hipGraphLaunch(b->graph, b->stream);
+            if (e != hipSuccess) return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
+            for (fetd_sim *s : b->sims) {
+                s->step += cycle;
+                s->steps_since_sort = K;
+            }
+            b->steps_since_sort = K;
+            left -= cycle;
+        }
+    }
+    return batch_enqueue(b, left, pusher);
+}
+
+void fetd_batch_destroy(fetd_batch *b)
+{
+    if (!b) return;
+    DeviceGuard g(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    batch_release(b);
+    delete b;
 }
 
 }  // extern "C"

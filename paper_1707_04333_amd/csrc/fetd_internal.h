@@ -11,7 +11,10 @@ namespace fetd {
 constexpr uint32_t kLost = 0xFFFFFFFFu;   // key of a removed particle
 constexpr uint32_t kTriMask = 0x3FFFFFFFu; // triangle id bits of a key
 constexpr int kBlock = 256;                // threads per block of the particle kernels
-constexpr int kPPT = 4;                    // particles per thread of the particle kernel
+#ifndef FETD_PPT
+#define FETD_PPT 4
+#endif
+constexpr int kPPT = FETD_PPT;             // particles per thread of the particle kernel
 constexpr int kSlice = 64;                 // rows per SELL slice of the SpMV
 
 // Per-triangle tables (device).
@@ -45,8 +48,41 @@ struct StepArgs {
     int has_affine;
     double aff[6];
     unsigned long long *counters;  // [2] error flags, [3] first bad id (rarely written)
-    unsigned long long *block_counts;  // [2 * grid]: per-block running sums (segments, lost)
+    unsigned long long *block_counts;  // [2 * tiles]: per-tile running sums (segments, lost)
     const int32_t *pid;            // load ids (for error reports)
+};
+
+// One (run, species) segment of a batched particle launch.
+struct SegDesc {
+    MeshView m;
+    StepArgs a;
+};
+
+// Per-run field-stage descriptor of a batched launch.
+struct FieldDesc {
+    int nf, ne;
+    const int4 *tri_edge;
+    const double *e;
+    const double *e_ext;
+    double *b;
+    double *h;
+    const double *inv_mu_area;
+    const double *inv_2area;
+    const double *bz_ext;
+    const double *grad64;
+    void *rec;
+    int rec_fp32;
+    double dt;
+    const int4 *edge_face;
+    double *cur;
+    double *cur_last;
+    double *d;
+    const double *damp;
+    const int32_t *sl_ptr;
+    const int32_t *sl_w;
+    const int32_t *sl_col;
+    const double *sl_val;
+    double *e_out;
 };
 
 // Host-callable launchers (fetd_kernels.hip).
@@ -57,8 +93,7 @@ hipError_t launch_faraday(hipStream_t s, int nf, const int4 *tri_edge, const dou
 hipError_t launch_particles(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
                             bool fp32);
 hipError_t launch_ampere(hipStream_t s, int ne, const int4 *edge_face, const double *h,
-                         const double *cur, double *cur_next, double *d, const double *damp,
-                         double dt);
+                         double *cur, double *cur_last, double *d, const double *damp, double dt);
 hipError_t launch_spmv(hipStream_t s, int ne, const int32_t *slice_ptr, const int32_t *slice_w,
                        const int32_t *col, const double *val, const double *d, double *e);
 
@@ -81,6 +116,17 @@ struct SortArgs {
     int elem_bytes;    // 8 (float2) or 16 (double2)
 };
 hipError_t launch_sort(hipStream_t s, const SortArgs &a);
+
+// Batched launches over many runs (one launch per phase).
+hipError_t launch_faraday_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,
+                                  int nrun, uint32_t total_blocks);
+hipError_t launch_particles_batched(hipStream_t s, const SegDesc *segs, const uint32_t *prefix,
+                                    int nseg, uint32_t total_tiles, int pusher, bool fp32);
+hipError_t launch_ampere_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,
+                                 int nrun, uint32_t total_blocks);
+hipError_t launch_spmv_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,
+                               int nrun, uint32_t total_blocks);
+hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n);
 
 // Diagnostics.
 hipError_t launch_charge(hipStream_t s, int64_t n, const uint32_t *key, const void *lam,

@@ -412,16 +412,28 @@ struct Queue {
     R ts[kQueue], la[kQueue], rx[kQueue], ry[kQueue];
 };
 
+template <typename R>
+struct TileShared {
+    int key[kHash];
+    double val[kHash];
+    Queue<R> q;
+    int qn;
+    unsigned long long red[2][kBlock / 64];
+};
+
+// One tile of kPPT * kBlock particles of one species (tile index `tile`
+// within the species), processed by the whole block.
 template <int P, typename R>
-__global__ __launch_bounds__(kBlock) void k_particle_step(MeshView m, StepArgs a)
+__device__ __forceinline__ void particle_tile(const MeshView &m, const StepArgs &a, uint32_t tile,
+                                              TileShared<R> &sh)
 {
     using R2 = typename Vec2<R>::type;
     constexpr uint32_t kR2 = sizeof(R2);
-    __shared__ int s_key[kHash];
-    __shared__ double s_val[kHash];
-    __shared__ Queue<R> s_q;
-    __shared__ int s_qn;
-    __shared__ unsigned long long red[2][kBlock / 64];
+    int *s_key = sh.key;
+    double *s_val = sh.val;
+    Queue<R> &s_q = sh.q;
+    int &s_qn = sh.qn;
+    auto &red = sh.red;
     for (int t = threadIdx.x; t < kHash; t += kBlock) {
         s_key[t] = -1;
         s_val[t] = 0.0;
@@ -429,16 +441,32 @@ __global__ __launch_bounds__(kBlock) void k_particle_step(MeshView m, StepArgs a
     if (threadIdx.x == 0) s_qn = 0;
     __syncthreads();
     const LdsCurrent dep{s_key, s_val, a.cur};
-    const uint32_t tile = uint32_t(xcd_tile(blockIdx.x, gridDim.x));
     const int lane = threadIdx.x & 63;
     unsigned long long nseg = 0, nlost = 0;
     const double q = a.qdt;
 
+    // The particle streams of the next pass are loaded while the current
+    // pass computes.
+    uint32_t i_next = tile * kPPT * kBlock + threadIdx.x;
+    uint32_t key_next = int64_t(i_next) < a.n ? ld<uint32_t>(a.key, i_next * 4u) : kLost;
+    R2 pr_next{}, uu_next{};
+    if (key_next != kLost) {
+        pr_next = ld<R2>(a.lam, i_next * kR2);
+        uu_next = ld<R2>(a.u, i_next * kR2);
+    }
     for (int pass = 0; pass < kPPT; ++pass) {
-        const uint32_t i = (tile * kPPT + pass) * kBlock + threadIdx.x;
-        const bool in_range = int64_t(i) < a.n;
-        const uint32_t key = in_range ? ld<uint32_t>(a.key, i * 4u) : kLost;
+        const uint32_t i = i_next;
+        const uint32_t key = key_next;
+        const R2 pr = pr_next, uu = uu_next;
         const bool alive = key != kLost;
+        if (pass + 1 < kPPT) {
+            i_next = i + kBlock;
+            key_next = int64_t(i_next) < a.n ? ld<uint32_t>(a.key, i_next * 4u) : kLost;
+            if (key_next != kLost) {
+                pr_next = ld<R2>(a.lam, i_next * kR2);
+                uu_next = ld<R2>(a.u, i_next * kR2);
+            }
+        }
 
         int f0 = -1;
         double c0 = 0.0, c1 = 0.0, c2 = 0.0;  // first path piece (cross terms)
@@ -449,8 +477,6 @@ __global__ __launch_bounds__(kBlock) void k_particle_step(MeshView m, StepArgs a
         Piece<R> pc{};
 
         if (alive) {
-            const R2 pr = ld<R2>(a.lam, i * kR2);
-            const R2 uu = ld<R2>(a.u, i * kR2);
             f = key & kTriMask;
             r = int(key >> 30);
             f0 = int(f);
@@ -612,8 +638,40 @@ __global__ __launch_bounds__(kBlock) void k_particle_step(MeshView m, StepArgs a
             s0 += red[0][wv];
             s1 += red[1][wv];
         }
-        a.block_counts[2 * blockIdx.x] += s0;
-        a.block_counts[2 * blockIdx.x + 1] += s1;
+        a.block_counts[2 * tile] += s0;
+        a.block_counts[2 * tile + 1] += s1;
+    }
+    __syncthreads();
+}
+
+#ifndef FETD_WAVES_PER_EU
+#define FETD_WAVES_PER_EU 1
+#endif
+template <int P, typename R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FETD_WAVES_PER_EU)))
+void k_particle_step(MeshView m, StepArgs a)
+{
+    __shared__ TileShared<R> sh;
+    particle_tile<P, R>(m, a, uint32_t(xcd_tile(blockIdx.x, gridDim.x)), sh);
+}
+
+// Batched particle stage: many (run, species) segments in one persistent
+// launch; blocks walk the flattened tile list.
+template <int P, typename R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FETD_WAVES_PER_EU)))
+void k_particle_batched(const SegDesc *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
+                        int nseg, uint32_t total_tiles)
+{
+    __shared__ TileShared<R> sh;
+    for (uint32_t g = blockIdx.x; g < total_tiles; g += gridDim.x) {
+        int lo = 0, hi = nseg - 1;  // last segment with tile_prefix[s] <= g
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_prefix[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        const SegDesc &sd = segs[lo];
+        particle_tile<P, R>(sd.m, sd.a, g - tile_prefix[lo], sh);
     }
 }
 
@@ -621,18 +679,16 @@ __global__ __launch_bounds__(kBlock) void k_particle_step(MeshView m, StepArgs a
 // Faraday half step and per-triangle gather record.
 // ---------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(256) void k_faraday(int nf, const int4 *__restrict__ tri_edge,
-                                                 const double *__restrict__ e,
-                                                 const double *__restrict__ e_ext,
-                                                 double *__restrict__ b, double *__restrict__ h,
-                                                 const double *__restrict__ inv_mu_area,
-                                                 const double *__restrict__ inv_2area,
-                                                 const double *__restrict__ bz_ext,
-                                                 const double *__restrict__ grad,
-                                                 R *__restrict__ rec, double dt)
+__device__ __forceinline__ void faraday_tri(int f, const int4 *__restrict__ tri_edge,
+                                            const double *__restrict__ e,
+                                            const double *__restrict__ e_ext,
+                                            double *__restrict__ b, double *__restrict__ h,
+                                            const double *__restrict__ inv_mu_area,
+                                            const double *__restrict__ inv_2area,
+                                            const double *__restrict__ bz_ext,
+                                            const double *__restrict__ grad, R *__restrict__ rec,
+                                            double dt)
 {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
     const int4 te = tri_edge[f];
     const double e0 = e[te.x], e1 = e[te.y], e2 = e[te.z];
     const double s0 = (te.w & 1) ? -e0 : e0;
@@ -665,38 +721,91 @@ __global__ __launch_bounds__(256) void k_faraday(int nf, const int4 *__restrict_
     o[7] = R(0);
 }
 
+template <typename R>
+__global__ __launch_bounds__(256) void k_faraday(int nf, const int4 *__restrict__ tri_edge,
+                                                 const double *__restrict__ e,
+                                                 const double *__restrict__ e_ext,
+                                                 double *__restrict__ b, double *__restrict__ h,
+                                                 const double *__restrict__ inv_mu_area,
+                                                 const double *__restrict__ inv_2area,
+                                                 const double *__restrict__ bz_ext,
+                                                 const double *__restrict__ grad,
+                                                 R *__restrict__ rec, double dt)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < nf)
+        faraday_tri<R>(f, tri_edge, e, e_ext, b, h, inv_mu_area, inv_2area, bz_ext, grad, rec, dt);
+}
+
+// Run of a batched field-stage block: the last run whose block prefix is
+// <= g (runs hold ceil(n/256) blocks each).
+__device__ __forceinline__ int run_of(const uint32_t *__restrict__ prefix, int nrun, uint32_t g)
+{
+    int lo = 0, hi = nrun - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_faraday_batched(const FieldDesc *__restrict__ runs,
+                                                         const uint32_t *__restrict__ prefix,
+                                                         int nrun, uint32_t total_blocks)
+{
+    for (uint32_t g = blockIdx.x; g < total_blocks; g += gridDim.x) {
+        const int r = run_of(prefix, nrun, g);
+        const FieldDesc &d = runs[r];
+        const int f = int(g - prefix[r]) * 256 + int(threadIdx.x);
+        if (f >= d.nf) continue;
+        if (d.rec_fp32)
+            faraday_tri<float>(f, d.tri_edge, d.e, d.e_ext, d.b, d.h, d.inv_mu_area, d.inv_2area,
+                               d.bz_ext, d.grad64, static_cast<float *>(d.rec), d.dt);
+        else
+            faraday_tri<double>(f, d.tri_edge, d.e, d.e_ext, d.b, d.h, d.inv_mu_area, d.inv_2area,
+                                d.bz_ext, d.grad64, static_cast<double *>(d.rec), d.dt);
+    }
+}
+
 // ---------------------------------------------------------------------
 // Ampere half step on the primary state d (FP64).
 // edge_face[e] = {f0, f1 (-1 on a wall), sign0, sign1}.
 // ---------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ampere(int ne, const int4 *__restrict__ edge_face,
-                                                const double *__restrict__ h,
-                                                const double *__restrict__ cur,
-                                                double *__restrict__ cur_next,
-                                                double *__restrict__ d,
-                                                const double *__restrict__ damp, double dt)
+__device__ __forceinline__ void ampere_edge(int ed, const int4 *__restrict__ edge_face,
+                                            const double *__restrict__ h, double *__restrict__ cur,
+                                            double *__restrict__ cur_last, double *__restrict__ d,
+                                            const double *__restrict__ damp, double dt)
 {
-    const int ed = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ed >= ne) return;
-    cur_next[ed] = 0.0;
+    const double ie = cur[ed];
+    cur_last[ed] = ie;
+    cur[ed] = 0.0;
     const int4 ef = edge_face[ed];
     if (ef.y < 0) return;  // wall edge: not a free DoF, d stays 0
     const double curl = double(ef.z) * h[ef.x] + double(ef.w) * h[ef.y];
-    double dn = d[ed] + dt * (curl - cur[ed]);
+    double dn = d[ed] + dt * (curl - ie);
     if (damp) dn *= damp[ed];
     d[ed] = dn;
 }
 
-// e = M~ d, M~ in SELL-64 (slices of 64 rows, column-major inside a slice).
-__global__ __launch_bounds__(256) void k_spmv(int ne, const int32_t *__restrict__ slice_ptr,
-                                              const int32_t *__restrict__ slice_w,
-                                              const int32_t *__restrict__ col,
-                                              const double *__restrict__ val,
-                                              const double *__restrict__ d,
-                                              double *__restrict__ e)
+__global__ __launch_bounds__(256) void k_ampere(int ne, const int4 *__restrict__ edge_face,
+                                                const double *__restrict__ h,
+                                                double *__restrict__ cur,
+                                                double *__restrict__ cur_last,
+                                                double *__restrict__ d,
+                                                const double *__restrict__ damp, double dt)
 {
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= ne) return;
+    const int ed = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ed < ne) ampere_edge(ed, edge_face, h, cur, cur_last, d, damp, dt);
+}
+
+// e = M~ d, M~ in SELL-64 (slices of 64 rows, column-major inside a slice).
+__device__ __forceinline__ void spmv_row(int row, const int32_t *__restrict__ slice_ptr,
+                                         const int32_t *__restrict__ slice_w,
+                                         const int32_t *__restrict__ col,
+                                         const double *__restrict__ val,
+                                         const double *__restrict__ d, double *__restrict__ e)
+{
     const int sl = row / kSlice, ln = row % kSlice;
     const int base = slice_ptr[sl], w = slice_w[sl];
     double acc = 0.0;
@@ -705,6 +814,47 @@ __global__ __launch_bounds__(256) void k_spmv(int ne, const int32_t *__restrict_
         acc += val[q] * d[col[q]];
     }
     e[row] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_spmv(int ne, const int32_t *__restrict__ slice_ptr,
+                                              const int32_t *__restrict__ slice_w,
+                                              const int32_t *__restrict__ col,
+                                              const double *__restrict__ val,
+                                              const double *__restrict__ d,
+                                              double *__restrict__ e)
+{
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row < ne) spmv_row(row, slice_ptr, slice_w, col, val, d, e);
+}
+
+__global__ __launch_bounds__(256) void k_ampere_batched(const FieldDesc *__restrict__ runs,
+                                                        const uint32_t *__restrict__ prefix,
+                                                        int nrun, uint32_t total_blocks)
+{
+    for (uint32_t g = blockIdx.x; g < total_blocks; g += gridDim.x) {
+        const int r = run_of(prefix, nrun, g);
+        const FieldDesc &d = runs[r];
+        const int ed = int(g - prefix[r]) * 256 + int(threadIdx.x);
+        if (ed < d.ne) ampere_edge(ed, d.edge_face, d.h, d.cur, d.cur_last, d.d, d.damp, d.dt);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_spmv_batched(const FieldDesc *__restrict__ runs,
+                                                      const uint32_t *__restrict__ prefix,
+                                                      int nrun, uint32_t total_blocks)
+{
+    for (uint32_t g = blockIdx.x; g < total_blocks; g += gridDim.x) {
+        const int r = run_of(prefix, nrun, g);
+        const FieldDesc &d = runs[r];
+        const int row = int(g - prefix[r]) * 256 + int(threadIdx.x);
+        if (row < d.ne) spmv_row(row, d.sl_ptr, d.sl_w, d.sl_col, d.sl_val, d.d, d.e_out);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------
@@ -922,12 +1072,11 @@ hipError_t launch_particles(hipStream_t s, const MeshView &m, const StepArgs &a,
 }
 
 hipError_t launch_ampere(hipStream_t s, int ne, const int4 *edge_face, const double *h,
-                         const double *cur, double *cur_next, double *d, const double *damp,
-                         double dt)
+                         double *cur, double *cur_last, double *d, const double *damp, double dt)
 {
     if (ne <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ampere, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, edge_face, h, cur,
-                       cur_next, d, damp, dt);
+                       cur_last, d, damp, dt);
     return hipGetLastError();
 }
 
@@ -940,9 +1089,19 @@ hipError_t launch_spmv(hipStream_t s, int ne, const int32_t *slice_ptr, const in
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_sort(hipStream_t s, const SortArgs &a)
 {
-    hipError_t err = hipMemsetAsync(a.counts, 0, sizeof(int32_t) * size_t(a.nf + 1), s);
+    // fill kernels rather than memsets, so the sort can sit in a captured graph
+    hipError_t err = launch_fill_u32(s, reinterpret_cast<uint32_t *>(a.counts), 0u, a.nf + 1);
+    if (err != hipSuccess) return err;
+    err = launch_fill_u32(s, a.key_out, kLost, a.n);
     if (err != hipSuccess) return err;
     if (a.n > 0)
         hipLaunchKernelGGL(k_sort_hist, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a.n, a.key_in,
@@ -952,7 +1111,7 @@ hipError_t launch_sort(hipStream_t s, const SortArgs &a)
                        a.block_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, nb, a.block_sums);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, s, a.nf, a.offsets, a.block_sums, nb);
-    err = hipMemsetAsync(a.counts, 0, sizeof(int32_t) * size_t(a.nf + 1), s);
+    err = launch_fill_u32(s, reinterpret_cast<uint32_t *>(a.counts), 0u, a.nf + 1);
     if (err != hipSuccess) return err;
     if (a.n > 0) {
         if (a.elem_bytes == 8)
@@ -961,6 +1120,66 @@ hipError_t launch_sort(hipStream_t s, const SortArgs &a)
         else
             hipLaunchKernelGGL(k_sort_scatter<double2>, dim3(grid_for(a.n, 256)), dim3(256), 0, s,
                                a);
+    }
+    return hipGetLastError();
+}
+
+static unsigned persistent_grid(uint32_t total, unsigned per_cu)
+{
+    const uint32_t cap = 256u * per_cu;
+    return total < cap ? (total > 0 ? total : 1u) : cap;
+}
+
+hipError_t launch_faraday_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,
+                                  int nrun, uint32_t total_blocks)
+{
+    if (total_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_faraday_batched, dim3(persistent_grid(total_blocks, 8)), dim3(256), 0, s,
+                       d, prefix, nrun, total_blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_ampere_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,
+                                 int nrun, uint32_t total_blocks)
+{
+    if (total_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ampere_batched, dim3(persistent_grid(total_blocks, 8)), dim3(256), 0, s,
+                       d, prefix, nrun, total_blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,
+                               int nrun, uint32_t total_blocks)
+{
+    if (total_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spmv_batched, dim3(persistent_grid(total_blocks, 8)), dim3(256), 0, s,
+                       d, prefix, nrun, total_blocks);
+    return hipGetLastError();
+}
+
+template <int P>
+static void launch_particles_batched_p(hipStream_t s, const SegDesc *segs, const uint32_t *prefix,
+                                       int nseg, uint32_t total, bool fp32)
+{
+    const unsigned grid = persistent_grid(total, 6);
+    if (fp32)
+        hipLaunchKernelGGL((k_particle_batched<P, float>), dim3(grid), dim3(kBlock), 0, s, segs,
+                           prefix, nseg, total);
+    else
+        hipLaunchKernelGGL((k_particle_batched<P, double>), dim3(grid), dim3(kBlock), 0, s, segs,
+                           prefix, nseg, total);
+}
+
+hipError_t launch_particles_batched(hipStream_t s, const SegDesc *segs, const uint32_t *prefix,
+                                    int nseg, uint32_t total_tiles, int pusher, bool fp32)
+{
+    if (total_tiles == 0) return hipSuccess;
+    switch (pusher) {
+    case 0: launch_particles_batched_p<0>(s, segs, prefix, nseg, total_tiles, fp32); break;
+    case 1: launch_particles_batched_p<1>(s, segs, prefix, nseg, total_tiles, fp32); break;
+    case 2: launch_particles_batched_p<2>(s, segs, prefix, nseg, total_tiles, fp32); break;
+    case 3: launch_particles_batched_p<3>(s, segs, prefix, nseg, total_tiles, fp32); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

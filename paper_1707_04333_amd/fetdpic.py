@@ -94,14 +94,24 @@ def lib():
         L.fetd_info_get.argtypes = [P, P]
         L.fetd_last_error.argtypes = [P]
         L.fetd_last_error.restype = ctypes.c_char_p
-        L.fetd_profile.argtypes = [P, ctypes.c_int32]
-        L.fetd_stage_times.argtypes = [P, P, P]
+        optional = {"fetd_profile": [P, ctypes.c_int32], "fetd_stage_times": [P, P, P],
+                    "fetd_autotune": [P, ctypes.c_int32, ctypes.c_int32, P],
+                    "fetd_set_resort": [P, ctypes.c_int32],
+                    "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
+                    "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32]}
+        for name, args in optional.items():
+            if hasattr(L, name):
+                getattr(L, name).argtypes = args
+                getattr(L, name).restype = ctypes.c_int
+        if hasattr(L, "fetd_batch_destroy"):
+            L.fetd_batch_destroy.argtypes = [P]
+            L.fetd_batch_destroy.restype = None
         L.fetd_destroy.argtypes = [P]
         L.fetd_destroy.restype = None
         for name in ("fetd_mesh_create", "fetd_fields_set", "fetd_particles_load_bary",
                      "fetd_particles_load", "fetd_pic_step", "fetd_sort", "fetd_sync",
                      "fetd_fields_get", "fetd_particles_get", "fetd_diagnostics",
-                     "fetd_info_get", "fetd_profile", "fetd_stage_times"):
+                     "fetd_info_get"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -255,6 +265,17 @@ def info(h):
 STAGES = ("faraday", "particles", "ampere", "spmv", "sort")
 
 
+def autotune(h, pusher="boris", trial_steps=160):
+    pid = PUSHERS[pusher] if isinstance(pusher, str) else int(pusher)
+    out = ctypes.c_int32()
+    _check(lib().fetd_autotune(h, pid, int(trial_steps), ctypes.byref(out)), h)
+    return out.value
+
+
+def set_resort(h, every):
+    _check(lib().fetd_set_resort(h, int(every)), h)
+
+
 def profile(h, enable=True):
     _check(lib().fetd_profile(h, 1 if enable else 0), h)
 
@@ -321,8 +342,54 @@ class Sim:
     def profile(self, enable=True):
         profile(self.h, enable)
 
+    def autotune(self, pusher="boris", trial_steps=160):
+        return autotune(self.h, pusher, trial_steps)
+
+    def set_resort(self, every):
+        set_resort(self.h, every)
+
     def stage_times(self):
         return stage_times(self.h)
+
+
+def batch_create(sims, use_graph=True):
+    """fetd_batch_create over a list of Sim objects (same device, stream,
+    precision)."""
+    arr = (ctypes.c_void_p * len(sims))(*[sm.h.value for sm in sims])
+    h = ctypes.c_void_p()
+    _check(lib().fetd_batch_create(arr, len(sims), 1 if use_graph else 0, ctypes.byref(h)))
+    return h
+
+
+def batch_step(b, n_steps, pusher="boris"):
+    pid = PUSHERS[pusher] if isinstance(pusher, str) else int(pusher)
+    _check(lib().fetd_batch_step(b, int(n_steps), pid))
+
+
+def batch_destroy(b):
+    lib().fetd_batch_destroy(b)
+
+
+class Batch:
+    """Owning wrapper of a batch; keeps its member Sims alive."""
+
+    def __init__(self, sims, use_graph=True):
+        self.sims = list(sims)
+        self.h = batch_create(self.sims, use_graph)
+
+    def step(self, n=1, pusher="boris"):
+        batch_step(self.h, n, pusher)
+
+    def close(self):
+        if self.h:
+            batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def from_workload(w, precision=None, **kw):
