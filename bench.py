@@ -1,24 +1,27 @@
 """Benchmark: particle-steps/s of the full PIC step on one MI355X.
 
-Workload: relativistic pair-plasma Bernstein configuration — doubly
-periodic 0.5 m x 0.5 m mesh of 199,712 triangles (316 x 316 torus),
-8M electrons + 8M positrons in collocated pairs, in-plane
-Maxwell-Juttner momenta (kT/mc^2 = theta), uniform B0 = 1 T with
+Default workload (the ``value`` line): relativistic pair-plasma Bernstein
+configuration — doubly periodic 0.5 m x 0.5 m mesh of 199,712 triangles
+(316 x 316 torus), 8M electrons + 8M positrons in collocated pairs,
+in-plane Maxwell-Juttner momenta (kT/mc^2 = theta), uniform B0 = 1 T with
 omega_c/omega_p = 2, dt = 0.2/omega_c, mixed precision (FP32 positions,
 momenta, gather/push/track; FP64 deposit, field update and Gauss
-accounting), particles re-sorted by triangle every 20 steps.
+accounting), re-sort interval chosen by the autotuner during warm-up.
 
 A step is one pass of the whole path: Faraday + gather record, the fused
 gather/push/track/deposit stage for both species, Ampere, the SPAI SpMV,
-and (every 20th step) the counting sort.  The same workload in FP64 is
-timed beside it, the Gauss residual is reported for both, the fused
-particle kernel is placed on the HBM roofline from HIP-event timings of
-its launches inside the timed region, and the FP64 CPU oracle is timed on
+and the counting sort when due.  Beside it: the same workload in FP64, the
+batched sweep (64 independent uneven runs, one launch per phase per step,
+graph replay) against the same runs stepped one by one, the Gauss residual
+of each, the fused particle kernel on the HBM roofline from HIP-event
+timings of its launches inside the timed region, and the FP64 CPU oracle on
 a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--workload pair|large|boosted|cyclotron]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,8 +32,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = ("particle-steps/sec + achieved HBM GB/s; mixed/batched vs FP64 at Gauss residual")
+METRIC = "particle-steps/sec + achieved HBM GB/s; mixed/batched vs FP64 at Gauss residual"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particle_step_pair_plasma_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def particle_launch_bytes(n_particles, nf, ne, fp32):
@@ -45,16 +54,33 @@ def particle_launch_bytes(n_particles, nf, ne, fp32):
     return n_particles * per_particle + nf * per_tri + ne * 16
 
 
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def run_gpu(w, precision, steps, warmup, pusher):
+def measured_traffic(precision):
+    """HBM bytes per particle launch from the committed rocprofv3 counter
+    runs (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when
+    the kernel source changed since they were taken."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return rec.get(precision, {}).get("hbm_bytes_per_launch")
+
+
+def run_gpu(w, precision, steps, warmup, pusher, autotune=True):
     from paper_1707_04333_amd import fetdpic as fp
     log(f"{precision}: creating simulation ({w.n_particles} particles)")
     sim = fp.from_workload(w, precision=precision, spai_level=w.spai_level, device=0)
     info = sim.info()
     sim.diagnostics()  # Gauss baseline at step 0
+    resort = None
+    if autotune:
+        resort = sim.autotune(pusher, trial_steps=160)
+        log(f"{precision}: autotuned re-sort interval {resort}")
     sim.step(warmup, pusher)
     sim.sync()
     sim.profile(True)
@@ -67,13 +93,56 @@ def run_gpu(w, precision, steps, warmup, pusher):
     diag = sim.diagnostics()
     sim.close()
     log(f"{precision}: {steps} steps in {t1 - t0:.3f} s")
-    return dict(elapsed=t1 - t0, stages=stages, diag=diag, info=info)
+    return dict(elapsed=t1 - t0, stages=stages, diag=diag, info=info, resort=resort)
 
 
-def cpu_baseline(w_full, pusher, sample_pairs=500_000, sample_steps=25):
+def run_batched(steps, warmup, pusher):
+    """64 uneven pair-plasma runs: batched (graph replay) vs one by one."""
+    from paper_1707_04333_amd import fetdpic as fp
+    from paper_1707_04333_amd import inputs as I
+    log("batched: generating 64 runs")
+    wls = I.batched_sweep()
+    n_p = sum(w.n_particles for w in wls)
+    n_f = sum(w.mesh.n_tris for w in wls)
+    sims = [fp.from_workload(w, precision="mixed", spai_level=1, device=0) for w in wls]
+    del wls
+    ks = []
+    for s in sims:
+        s.diagnostics()
+        ks.append(s.autotune(pusher, trial_steps=80))
+    K = int(np.median(ks))
+    for s in sims:
+        s.set_resort(K)
+    log(f"batched: {n_p} particles on {n_f} triangles, re-sort every {K}")
+    b = fp.Batch(sims, use_graph=True)
+    b.step(max(warmup, 2 * K + 2), pusher)
+    sims[0].sync()
+    t0 = time.perf_counter()
+    b.step(steps, pusher)
+    sims[0].sync()
+    t_b = time.perf_counter() - t0
+    b.close()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for s in sims:
+            s.step(1, pusher)
+    sims[0].sync()
+    t_s = time.perf_counter() - t0
+    gauss = max(s.diagnostics()["gauss_rel"] for s in sims)
+    for s in sims:
+        s.close()
+    log(f"batched: {steps} steps in {t_b:.3f} s, separate {t_s:.3f} s")
+    return {"workload": "batched_sweep_64", "n_runs": len(sims), "n_particles": n_p,
+            "n_tris": n_f, "precision": "mixed", "value": n_p * steps / t_b,
+            "ms_per_step": t_b / steps * 1e3, "separate_value": n_p * steps / t_s,
+            "batched_vs_separate": t_s / t_b, "resort_every": K, "gauss_rel": gauss}
+
+
+def cpu_baseline(theta, n_full, pusher, sample_pairs=500_000, sample_steps=25):
+    """The FP64 oracle on the same mesh with a bounded particle sample."""
     import oracle
     from paper_1707_04333_amd import inputs as I
-    w = I.pair_plasma(n_pairs=sample_pairs, theta=w_full.extra["theta"], precision="fp64")
+    w = I.pair_plasma(n_pairs=sample_pairs, theta=theta, precision="fp64")
     sp = [(s.q, s.m, s.w, s.tri, s.lam, s.u) for s in w.species]
     osim = oracle.OracleSim(w.mesh, w.dt, sp, I.EPS0, I.MU0, I.C_LIGHT,
                             spai_level=w.spai_level, bz_ext=w.bz_ext)
@@ -85,9 +154,24 @@ def cpu_baseline(w_full, pusher, sample_pairs=500_000, sample_steps=25):
     return {"value": n * sample_steps / el, "unit": "particle-steps/s", "cores": 1,
             "kind": "oracle",
             "sample": (f"same mesh ({w.mesh.n_tris} triangles, FP64 field update), "
-                       f"{n} of the {w_full.n_particles} particles, {sample_steps} steps "
-                       f"after 1 warm-up step, single-threaded FP64 C oracle; "
-                       f"{el:.1f} s")}
+                       f"{n} of the {n_full} particles, {sample_steps} steps after 1 warm-up "
+                       f"step, single-threaded FP64 C oracle; {el:.1f} s")}
+
+
+def make_workload(name, args, precision):
+    from paper_1707_04333_amd import inputs as I
+    if name == "pair":
+        return I.pair_plasma(n_pairs=args.pairs, theta=args.theta, precision=precision)
+    if name == "large":
+        return I.large_run(precision=precision)
+    if name == "boosted":
+        w = I.boosted_oscillator()
+    elif name == "cyclotron":
+        w = I.cyclotron()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    w.precision = precision
+    return w
 
 
 def main():
@@ -95,11 +179,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="pair")
     ap.add_argument("--theta", type=float, default=0.1)
-    ap.add_argument("--pusher", default="boris")
+    ap.add_argument("--pusher", default=None)
     ap.add_argument("--pairs", type=int, default=8_000_000)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device with torch (a plain copy kernel "
                          "of known size, for scaling HBM counters)")
@@ -108,7 +195,6 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
-
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -117,18 +203,22 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("copied 1 GiB device-to-device")
-    from paper_1707_04333_amd import inputs as I
-    log("generating workload")
-    w = I.pair_plasma(n_pairs=args.pairs, theta=args.theta, precision="mixed")
+
+    log(f"generating workload {args.workload}")
+    w = make_workload(args.workload, args, "mixed")
+    pusher = args.pusher or ("boris" if args.workload == "pair" else w.pusher)
     n_p = w.n_particles
-    mixed = run_gpu(w, "mixed", args.steps, args.warmup, args.pusher)
+    species_n = [s.n for s in w.species]
+    mixed = run_gpu(w, "mixed", args.steps, args.warmup, pusher, not args.no_autotune)
+    del w
     value = n_p * args.steps / mixed["elapsed"]
     info = mixed["info"]
+    nf, ne = info["n_tris"], info["n_edges"]
     ms, launches = mixed["stages"]["particles"]
-    per_launch_bytes = np.mean([particle_launch_bytes(s.n, info["n_tris"], info["n_edges"], True)
-                                for s in w.species])
+    per_launch_bytes = float(np.mean([particle_launch_bytes(n, nf, ne, True) for n in species_n]))
     avg_s = ms / 1e3 / max(launches, 1)
     achieved = per_launch_bytes / avg_s / 1e9
+    traffic = measured_traffic("mixed") if args.workload == "pair" else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -142,39 +232,40 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 particle state/push/track, f64 deposit+fields",
         "data": "synthetic",
-        "config": {"workload": "pair_plasma_bernstein", "n_tris": info["n_tris"],
-                   "n_edges": info["n_edges"], "n_particles": n_p, "theta": args.theta,
-                   "pusher": args.pusher, "precision": "mixed", "resort_every": 20,
-                   "spai_level": w.spai_level, "dt": w.dt},
+        "config": {"workload": args.workload, "n_tris": nf, "n_edges": ne,
+                   "n_particles": n_p, "theta": args.theta if args.workload == "pair" else None,
+                   "pusher": pusher, "precision": "mixed", "resort_every": mixed["resort"],
+                   "spai_level": 1},
         "roofline": {"bound": "hbm", "kernel": "k_particle_step", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_ms": avg_s * 1e3,
+                     "traffic": traffic, "avg_launch_ms": avg_s * 1e3,
                      "algorithmic_bytes_per_launch": per_launch_bytes},
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in mixed["stages"].items()},
         "gauss_rel": mixed["diag"]["gauss_rel"],
-        "hbm_gbs_step": None,
+        "hbm_gbs_step": sum(particle_launch_bytes(n, nf, ne, True) for n in species_n)
+        / (mixed["elapsed"] / args.steps) / 1e9,
     }
-    # whole-step effective bandwidth (particle stage + field stages)
-    step_bytes = sum(particle_launch_bytes(s.n, info["n_tris"], info["n_edges"], True)
-                     for s in w.species)
-    out["hbm_gbs_step"] = step_bytes / (mixed["elapsed"] / args.steps) / 1e9
     if not args.no_fp64:
-        w64 = I.pair_plasma(n_pairs=args.pairs, theta=args.theta, precision="fp64")
-        r64 = run_gpu(w64, "fp64", args.steps, args.warmup, args.pusher)
+        w64 = make_workload(args.workload, args, "fp64")
+        r64 = run_gpu(w64, "fp64", args.steps, args.warmup, pusher, not args.no_autotune)
+        del w64
         ms64, l64 = r64["stages"]["particles"]
-        b64 = np.mean([particle_launch_bytes(s.n, info["n_tris"], info["n_edges"], False)
-                       for s in w64.species])
+        b64 = float(np.mean([particle_launch_bytes(n, nf, ne, False) for n in species_n]))
         a64 = b64 / (ms64 / 1e3 / max(l64, 1)) / 1e9
         out["fp64"] = {"value": n_p * args.steps / r64["elapsed"],
                        "ms_per_step": r64["elapsed"] / args.steps * 1e3,
-                       "gauss_rel": r64["diag"]["gauss_rel"],
+                       "gauss_rel": r64["diag"]["gauss_rel"], "resort_every": r64["resort"],
                        "particle_kernel_gbs": a64, "particle_kernel_frac": a64 / HBM_PEAK_GBS,
+                       "particle_kernel_traffic": (measured_traffic("fp64")
+                                                   if args.workload == "pair" else None),
                        "stage_ms_per_step": {k: v[0] / args.steps
                                              for k, v in r64["stages"].items()}}
         out["mixed_vs_fp64"] = value / out["fp64"]["value"]
-    if not args.no_cpu:
+    if not args.no_batched and args.workload == "pair":
+        out["batched"] = run_batched(min(args.steps, 100), args.warmup, pusher)
+    if not args.no_cpu and args.workload == "pair":
         log("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(w, args.pusher)
+        out["cpu_baseline"] = cpu_baseline(args.theta, n_p, pusher)
     print(json.dumps(out))
 
 

@@ -157,6 +157,14 @@ fetd_status fetd_mesh_create(const fetd_mesh_desc *mesh, const fetd_opts *opts,
 fetd_status fetd_fields_set(fetd_sim *sim, const double *bz_ext, const double *e_ext,
                             const double *e_affine);
 
+/* Absorbing layer (not part of the paper, which uses a PML): a per-
+ * triangle conductivity sigma_tri [S/m] (NULL clears).  Each edge takes the
+ * mean conductivity of its triangles and its d is multiplied after every
+ * Ampere update by (1 - x)/(1 + x), x = sigma dt / (2 eps0), a conduction
+ * loss.  Nodes touching a lossy edge are left out of the Gauss residual of
+ * fetd_diagnostics. */
+fetd_status fetd_set_absorber(fetd_sim *sim, const double *sigma_tri);
+
 /* Append a species of n macro particles given in barycentric form
  * (tri[n], slot[n] or NULL for slot 0, lam[2n], u[2n]).  Load order
  * defines particle ids 0..n-1 within the species.  *species_out gets the

@@ -412,6 +412,25 @@ class OracleSim:
         return WE, WB, WK
 
 
+def absorber_damp(T: Topology, sigma_tri, dt: float, eps0: float):
+    """Conduction loss of the absorbing layer (the build's own stand-in for
+    the paper's PML): edge conductivity = mean over its triangles; d is
+    multiplied by (1 - x)/(1 + x), x = sigma dt/(2 eps0), after each Ampere
+    update.  Returns (damp per edge, nodes kept in the Gauss residual)."""
+    sg = np.asarray(sigma_tri, dtype=np.float64)
+    f0, f1 = T.edge_tri[:, 0], T.edge_tri[:, 1]
+    se = sg[f0].copy()
+    two = f1 >= 0
+    se[two] = 0.5 * (sg[f0[two]] + sg[f1[two]])
+    x = se * dt / (2.0 * eps0)
+    damp = np.where(se > 0, (1.0 - x) / (1.0 + x), 1.0)
+    keep = T.node_free.astype(bool).copy()
+    lossy = se > 0
+    keep[T.edge_lo[lossy]] = False
+    keep[T.edge_hi[lossy]] = False
+    return damp, keep
+
+
 def push(pusher, u, E, B, q, m, dt, c):
     """Single 3-D momentum update through the oracle pusher."""
     alpha = q * dt / (2.0 * m)

@@ -64,6 +64,7 @@ struct fetd_sim {
     std::vector<int32_t> edge_f;  // [2 ne]
     std::vector<int8_t> edge_s;   // [2 ne]
     std::vector<uint8_t> edge_free, node_free;
+    std::vector<uint8_t> node_gauss;  // free and not touching a lossy edge
     Csr meps, mt;
     double spai_fro = 0;
 
@@ -297,6 +298,7 @@ fetd_status build_topology(fetd_sim *s, const fetd_mesh_desc *md)
     }
     s->n_free_n = 0;
     for (int n = 0; n < nn; ++n) s->n_free_n += s->node_free[n];
+    s->node_gauss = s->node_free;
     return FETD_OK;
 }
 
@@ -981,6 +983,40 @@ fetd_status fetd_fields_set(fetd_sim *s, const double *bz_ext, const double *e_e
     return FETD_OK;
 }
 
+fetd_status fetd_set_absorber(fetd_sim *s, const double *sigma_tri)
+{
+    if (!s) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    s->node_gauss = s->node_free;
+    if (!sigma_tri) {
+        s->dev_free(s->d_damp);
+        s->d_damp = nullptr;
+        return FETD_OK;
+    }
+    std::vector<double> damp(s->ne, 1.0);
+    for (int e = 0; e < s->ne; ++e) {
+        const int f0 = s->edge_f[2 * e], f1 = s->edge_f[2 * e + 1];
+        double sg = sigma_tri[f0];
+        if (f1 >= 0) sg = 0.5 * (sigma_tri[f0] + sigma_tri[f1]);
+        if (!(sg >= 0.0)) return s->fail(FETD_E_ARG, "conductivity must be >= 0");
+        if (sg > 0.0) {
+            const double x = sg * s->dt / (2.0 * s->eps0);
+            damp[e] = (1.0 - x) / (1.0 + x);
+            s->node_gauss[s->edge_lo[e]] = 0;
+            s->node_gauss[s->edge_hi[e]] = 0;
+        }
+    }
+    if (!s->d_damp) {
+        if (fetd_status st = upload(s, &s->d_damp, damp.data(), damp.size())) return st;
+    } else {
+        hipError_t e = hipMemcpyAsync(s->d_damp, damp.data(), 8 * damp.size(),
+                                      hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "set_absorber");
+    }
+    return FETD_OK;
+}
+
 fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, int64_t n,
                                      const int32_t *tri, const int8_t *slot, const double *lam,
                                      const double *u, int32_t *species_out)
@@ -1321,7 +1357,7 @@ fetd_status fetd_diagnostics(fetd_sim *s, fetd_diag *out)
     double gmax = 0, qmax = 0;
     for (int n = 0; n < nn; ++n) {
         qmax = std::max(qmax, std::max(std::fabs(q[n]), std::fabs(s->q0[n])));
-        if (!s->node_free[n]) continue;
+        if (!s->node_gauss[n]) continue;
         gmax = std::max(gmax, std::fabs((dv[n] - s->divd0[n]) - (q[n] - s->q0[n])));
     }
     out->gauss_abs = gmax;
@@ -1337,7 +1373,7 @@ fetd_status fetd_diagnostics(fetd_sim *s, fetd_diag *out)
         double dm = 0, qm = 0;
         for (int n = 0; n < nn; ++n) {
             qm = std::max(qm, std::max(std::fabs(q[n]), std::fabs(s->q_last[n])));
-            if (!s->node_free[n]) continue;
+            if (!s->node_gauss[n]) continue;
             dm = std::max(dm, std::fabs((q[n] - s->q_last[n]) + s->dt * divj[n]));
         }
         out->dce_abs = dm;
@@ -1739,6 +1775,12 @@ fetd_status fetd_batch_step(fetd_batch *b, int32_t n_steps, int32_t pusher)
     if (fetd_status st = batch_enqueue(b, lead, pusher)) return st;
     left -= lead;
     const int cycle = 2 * K;
+    if (left >= cycle && (!b->graph || b->graph_pusher != pusher)) {
+        // one eager cycle first: every kernel of the cycle is then loaded
+        // (a first launch may load code objects, which a capture forbids)
+        if (fetd_status st = batch_enqueue(b, cycle, pusher)) return st;
+        left -= cycle;
+    }
     if (left >= cycle) {
         if (!b->graph || b->graph_pusher != pusher) {
             if (b->graph) (void)hipGraphExecDestroy(b->graph);

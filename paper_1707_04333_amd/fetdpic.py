@@ -98,7 +98,8 @@ def lib():
                     "fetd_autotune": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_set_resort": [P, ctypes.c_int32],
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
-                    "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32]}
+                    "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32],
+                    "fetd_set_absorber": [P, P]}
         for name, args in optional.items():
             if hasattr(L, name):
                 getattr(L, name).argtypes = args
@@ -189,6 +190,11 @@ def fields_set(h, bz_ext=None, e_ext=None, e_affine=None):
     ee = None if e_ext is None else np.ascontiguousarray(e_ext, dtype=np.float64)
     af = None if e_affine is None else np.ascontiguousarray(e_affine, dtype=np.float64)
     _check(lib().fetd_fields_set(h, _p(bz), _p(ee), _p(af)), h)
+
+
+def set_absorber(h, sigma_tri):
+    sg = None if sigma_tri is None else np.ascontiguousarray(sigma_tri, dtype=np.float64)
+    _check(lib().fetd_set_absorber(h, _p(sg)), h)
 
 
 def particles_load_bary(h, q, m, w, tri, lam, u, slot=None):
@@ -312,6 +318,9 @@ class Sim:
     def fields_set(self, **kw):
         fields_set(self.h, **kw)
 
+    def set_absorber(self, sigma_tri):
+        set_absorber(self.h, sigma_tri)
+
     def load(self, q, m, w, tri, lam, u, slot=None):
         return particles_load_bary(self.h, q, m, w, tri, lam, u, slot)
 
@@ -401,6 +410,8 @@ def from_workload(w, precision=None, **kw):
     if w.bz_ext or w.e_affine is not None:
         bz = np.full(w.mesh.n_tris, float(w.bz_ext)) if w.bz_ext else None
         sim.fields_set(bz_ext=bz, e_affine=w.e_affine)
+    if "sigma_tri" in w.extra:
+        sim.set_absorber(w.extra["sigma_tri"])
     for s in w.species:
         sim.load(s.q, s.m, s.w, s.tri, s.lam, s.u)
     return sim

@@ -464,7 +464,8 @@ def pair_plasma(n_side: int = 316, length: float = 0.5, n_pairs: int = 8_000_000
     """Relativistic pair-plasma Bernstein workload: doubly periodic square,
     electrons and positrons in collocated pairs with opposite momenta (zero
     initial charge and current), in-plane Maxwell-Juttner momenta of
-    temperature theta = kT/(m c^2), uniform B0 with omega_c/omega_p = 2."""
+    temperature theta = kT/(m c^2), uniform B0 with omega_c/omega_p = 2,
+    dt = min(0.2/omega_c, 0.22 h/c)."""
     mesh = grid_mesh(n_side, n_side, length, length, periodic_x=True, periodic_y=True)
     rng = np.random.default_rng(PARTICLE_SEED + seed_offset)
     tri, lam = sample_in_triangles(mesh, n_pairs, rng)
@@ -475,7 +476,9 @@ def pair_plasma(n_side: int = 316, length: float = 0.5, n_pairs: int = 8_000_000
     wp = wc / 2.0
     n0 = wp * wp * EPS0 * M_E / (E_CHARGE * E_CHARGE)   # per species [m^-3]
     weight = n0 * length * length / n_pairs            # per metre of depth
-    dt = 0.2 / wc
+    # 0.2/omega_c, capped by the leapfrog limit of the mesh (c dt/h <= 0.22;
+    # the measured limit with SPAI(1) is about 0.27)
+    dt = min(0.2 / wc, 0.22 * (length / n_side) / C_LIGHT)
     el = Species("electron", -E_CHARGE, M_E, weight, tri, lam, u)
     po = Species("positron", E_CHARGE, M_E, weight, tri.copy(), lam.copy(), -u)
     return Workload("pair_plasma_bernstein", mesh, [el, po], dt, steps, "boris", precision,
@@ -489,3 +492,69 @@ def pair_plasma_small(**kw) -> Workload:
     args = dict(n_side=79, length=0.125, n_pairs=500_000)
     args.update(kw)
     return pair_plasma(**args)
+
+
+def batched_sweep(n_runs: int = 64, cell: float = 1.58e-3, seed: int = 10000,
+                  tri_range=(2_000, 100_000), particle_range=(50_000, 4_000_000),
+                  precision: str = "mixed") -> list:
+    """Parameter sweep of independent pair-plasma runs with uneven sizes:
+    run r (seed 10000 + r) draws its triangle count and particle count
+    log-uniformly from the given ranges, B0 log-uniform in [0.5, 2] T and
+    theta log-uniform in [0.05, 1]; omega_c/omega_p = 2 and dt = 0.2/omega_c
+    per run; doubly periodic squares of cell size ``cell``."""
+    out = []
+    for r in range(n_runs):
+        rng = np.random.default_rng(seed + r)
+        nf = float(np.exp(rng.uniform(np.log(tri_range[0]), np.log(tri_range[1]))))
+        npart = float(np.exp(rng.uniform(np.log(particle_range[0]), np.log(particle_range[1]))))
+        B0 = float(np.exp(rng.uniform(np.log(0.5), np.log(2.0))))
+        theta = float(np.exp(rng.uniform(np.log(0.05), np.log(1.0))))
+        n_side = max(4, int(round(np.sqrt(nf / 2.0))))
+        w = pair_plasma(n_side=n_side, length=n_side * cell, n_pairs=max(1, int(npart) // 2),
+                        theta=theta, B0=B0, seed_offset=seed + r - PARTICLE_SEED,
+                        precision=precision)
+        w.name = f"sweep_{r}"
+        out.append(w)
+    return out
+
+
+def large_run(n_side: int = 708, n_particles: int = 128_000_000, grade: float = 10.0,
+              layer: float = 0.1, beam_fraction: float = 0.05, beam_gamma: float = 20.0,
+              theta: float = 0.5, B0: float = 1.0, precision: str = "mixed") -> Workload:
+    """Large single run: graded jittered mesh of the unit square (spacing
+    ratio ``grade``, finest at the centre) with PEC walls and an absorbing
+    outer layer of width ``layer`` whose conductivity rises as (depth/w)^3;
+    electrons with positions uniform by area, 95% in-plane Maxwell-Juttner
+    at theta and 5% a beam of gamma 20 along +x; B0 uniform with
+    omega_c/omega_p = 2; dt the smaller of 0.2/omega_c and 0.2 h_min/c.
+    Immobile neutralising ions sit at the electrons' initial positions: with
+    d^0 = 0 they are the initial charge q^0 of the Gauss accounting."""
+    mesh = grid_mesh(n_side, n_side, 1.0, 1.0, grade=grade)
+    rng = np.random.default_rng(PARTICLE_SEED + 4)
+    tri, lam = sample_in_triangles(mesh, n_particles, rng)
+    nb = int(round(beam_fraction * n_particles))
+    p = sample_mj2d(n_particles - nb, theta, rng)
+    ang = rng.uniform(0.0, 2.0 * math.pi, n_particles - nb)
+    u = np.empty((n_particles, 2))
+    u[:n_particles - nb, 0] = C_LIGHT * p * np.cos(ang)
+    u[:n_particles - nb, 1] = C_LIGHT * p * np.sin(ang)
+    u[n_particles - nb:, 0] = C_LIGHT * math.sqrt(beam_gamma ** 2 - 1.0)
+    u[n_particles - nb:, 1] = 0.0
+    wc = E_CHARGE * B0 / M_E
+    wp = wc / 2.0
+    n0 = wp * wp * EPS0 * M_E / (E_CHARGE * E_CHARGE)
+    weight = n0 * 1.0 / n_particles
+    area = mesh.tri_area()
+    h_min = float(np.sqrt(2.0 * area.min()))
+    dt = min(0.2 / wc, 0.2 * h_min / C_LIGHT)
+    # absorbing layer conductivity per triangle, graded cubically with depth
+    cen = mesh.centroids()
+    depth = np.maximum(0.0, layer - np.minimum.reduce([cen[:, 0], 1.0 - cen[:, 0],
+                                                      cen[:, 1], 1.0 - cen[:, 1]]))
+    sigma_max = 0.5 * EPS0 / dt  # sigma dt / (2 eps0) reaches 1/4 at the wall
+    sigma = sigma_max * (depth / layer) ** 3
+    sp = Species("electron", -E_CHARGE, M_E, weight, tri, lam, u)
+    return Workload("large_graded_absorbing", mesh, [sp], dt, 500, "hc", precision,
+                    bz_ext=B0, spai_level=1,
+                    extra={"omega_c": wc, "omega_p": wp, "sigma_tri": sigma, "theta": theta,
+                           "h_min": h_min})

@@ -284,3 +284,20 @@ def test_batched_runs_match_separate_runs(oracle_lib, use_graph):
     b.close()
     for s in batched + single:
         s.close()
+
+
+def test_graded_absorbing_hc_parity(oracle_lib):
+    """Graded mesh (10:1 spacing), PEC walls with an absorbing layer, beam
+    plus thermal electrons, Higuera-Cary: FP64 parity with the oracle."""
+    w = I.large_run(n_side=60, n_particles=20_000, precision="fp64")
+    osim = _oracle_sim(oracle_lib, w, 1)
+    damp, keep = oracle_lib.absorber_damp(osim.T, w.extra["sigma_tri"], w.dt, I.EPS0)
+    osim.damp = np.ascontiguousarray(damp)
+    g = _gpu_sim(w, 1)
+    osim.step(40, "hc")
+    g.step(40, "hc")
+    _compare_particles(osim, g)
+    _compare_fields(osim, g, tol=1e-11)
+    d = g.diagnostics()
+    assert d["gauss_rel"] <= 1e-12 and d["n_lost"] == osim.lost
+    g.close()

@@ -157,3 +157,27 @@ def test_exact_inverse_gauss_literal(oracle_lib):
     free = sim.T.node_free.astype(bool)
     r = lhs - (q - q0)
     assert np.abs(r[free]).max() / np.abs(q).max() < 1e-11
+
+
+def test_absorbing_layer_gauss_and_loss(oracle_lib):
+    """The conduction loss of the absorbing layer: with it, field energy
+    injected by a particle burst decays instead of ringing in the cavity,
+    and Gauss's law still holds at every node away from lossy edges."""
+    w = I.large_run(n_side=30, n_particles=4000, grade=3.0)
+    sp = w.species[0]
+    runs = {}
+    for lossy in (False, True):
+        sim = oracle_lib.OracleSim(w.mesh, w.dt, [(sp.q, sp.m, sp.w * 1e-3, sp.tri, sp.lam, sp.u)],
+                                   I.EPS0, I.MU0, I.C_LIGHT, spai_level=1, bz_ext=w.bz_ext)
+        keep = sim.T.node_free.astype(bool)
+        if lossy:
+            damp, keep = oracle_lib.absorber_damp(sim.T, w.extra["sigma_tri"], w.dt, I.EPS0)
+            sim.damp = np.ascontiguousarray(damp)
+            assert damp.min() < 1.0 and damp.max() == 1.0
+        q0, s0 = sim.charge(), sim.T.divergence(sim.d)
+        sim.step(200, "hc")
+        q, s = sim.charge(), sim.T.divergence(sim.d)
+        r = (s - s0) - (q - q0)
+        assert np.abs(r[keep]).max() <= 1e-12 * max(np.abs(q).max(), np.abs(q0).max())
+        runs[lossy] = sim.energies()[0] + sim.energies()[1]
+    assert runs[True] < runs[False]
