@@ -138,7 +138,7 @@ def run_batched(steps, warmup, pusher):
             "batched_vs_separate": t_s / t_b, "resort_every": K, "gauss_rel": gauss}
 
 
-def cpu_baseline(theta, n_full, pusher, sample_pairs=500_000, sample_steps=25):
+def cpu_baseline(theta, n_full, pusher, sample_pairs=500_000, sample_steps=100):
     """The FP64 oracle on the same mesh with a bounded particle sample."""
     import oracle
     from paper_1707_04333_amd import inputs as I
