@@ -65,12 +65,19 @@ struct fetd_sim {
     std::vector<int8_t> edge_s;   // [2 ne]
     std::vector<uint8_t> edge_free, node_free;
     std::vector<uint8_t> node_gauss;  // free and not touching a lossy edge
+    // Device edge numbering: order of first appearance along the triangle
+    // order (edges of nearby triangles get nearby ids).  Host tables and the
+    // C-ABI use the canonical (low, high) lexicographic numbering.
+    std::vector<int32_t> edev;       // canonical -> device id
+    std::vector<int32_t> ecan;       // device id -> canonical
+    std::vector<uint32_t> tri_ebase; // device edges first met before triangle f
     Csr meps, mt;
     double spai_fro = 0;
 
     // device: mesh
     int4 *d_tri_edge = nullptr, *d_tri_nbr = nullptr, *d_tri_node = nullptr, *d_edge_face = nullptr;
     int2 *d_edge_nodes = nullptr;
+    uint32_t *d_tri_ebase = nullptr;
     double *d_grad64 = nullptr, *d_vxy64 = nullptr, *d_inv_mu_area = nullptr, *d_inv_2area = nullptr;
     float *d_grad32 = nullptr, *d_vxy32 = nullptr;
     int32_t *d_sl_ptr = nullptr, *d_sl_w = nullptr, *d_sl_col = nullptr;
@@ -95,6 +102,7 @@ struct fetd_sim {
     int32_t *d_counts = nullptr, *d_offsets = nullptr, *d_block_sums = nullptr;
     unsigned long long *d_counters = nullptr;
     unsigned long long *d_block_counts = nullptr;
+    uint32_t *d_tile_home = nullptr;  // per tile, same slots as d_block_counts
     int64_t block_count_cap = 0;  // blocks covered by d_block_counts
     double *d_q = nullptr, *d_divd = nullptr, *d_partial = nullptr;
     static constexpr int kPartial = 1024;
@@ -298,6 +306,21 @@ fetd_status build_topology(fetd_sim *s, const fetd_mesh_desc *md)
     }
     s->n_free_n = 0;
     for (int n = 0; n < nn; ++n) s->n_free_n += s->node_free[n];
+    s->edev.assign(s->ne, -1);
+    s->ecan.assign(s->ne, -1);
+    s->tri_ebase.assign(nf, 0);
+    int next = 0;
+    for (int f = 0; f < nf; ++f) {
+        s->tri_ebase[f] = uint32_t(next);
+        for (int k = 0; k < 3; ++k) {
+            const int ed = s->tri_edge[3 * f + k];
+            if (s->edev[ed] < 0) {
+                s->edev[ed] = next;
+                s->ecan[next] = ed;
+                ++next;
+            }
+        }
+    }
     s->node_gauss = s->node_free;
     return FETD_OK;
 }
@@ -594,16 +617,18 @@ fetd_status upload_mesh(fetd_sim *s)
             if (s->tri_sign[3 * f + k] < 0) sb |= 1 << k;
             if (s->tri_nbrk[3 * f + k] >= 0) kb |= int(s->tri_nbrk[3 * f + k]) << (2 * k);
         }
-        te[f] = make_int4(s->tri_edge[3 * f], s->tri_edge[3 * f + 1], s->tri_edge[3 * f + 2], sb);
+        te[f] = make_int4(s->edev[s->tri_edge[3 * f]], s->edev[s->tri_edge[3 * f + 1]],
+                          s->edev[s->tri_edge[3 * f + 2]], sb);
         tn[f] = make_int4(s->tri_nbr[3 * f], s->tri_nbr[3 * f + 1], s->tri_nbr[3 * f + 2], kb);
         tno[f] = make_int4(s->tri_node[3 * f], s->tri_node[3 * f + 1], s->tri_node[3 * f + 2], 0);
     }
     std::vector<int4> ef(ne);
     std::vector<int2> en(ne);
-    for (int e = 0; e < ne; ++e) {
-        ef[e] = make_int4(s->edge_f[2 * e], s->edge_f[2 * e + 1], s->edge_s[2 * e],
+    for (int r = 0; r < ne; ++r) {
+        const int e = s->ecan[r];
+        ef[r] = make_int4(s->edge_f[2 * e], s->edge_f[2 * e + 1], s->edge_s[2 * e],
                           s->edge_s[2 * e + 1]);
-        en[e] = make_int2(s->edge_lo[e], s->edge_hi[e]);
+        en[r] = make_int2(s->edge_lo[e], s->edge_hi[e]);
     }
     std::vector<float> g32(8 * size_t(nf), 0.f), v32(8 * size_t(nf), 0.f);
     std::vector<double> imua(nf), i2a(nf);
@@ -621,19 +646,20 @@ fetd_status upload_mesh(fetd_sim *s)
     if ((st = upload(s, &s->d_tri_node, tno.data(), nf))) return st;
     if ((st = upload(s, &s->d_edge_face, ef.data(), ne))) return st;
     if ((st = upload(s, &s->d_edge_nodes, en.data(), ne))) return st;
+    if ((st = upload(s, &s->d_tri_ebase, s->tri_ebase.data(), s->tri_ebase.size()))) return st;
     if ((st = upload(s, &s->d_grad64, s->grad.data(), s->grad.size()))) return st;
     if ((st = upload(s, &s->d_vxy64, s->vxy.data(), s->vxy.size()))) return st;
     if ((st = upload(s, &s->d_grad32, g32.data(), g32.size()))) return st;
     if ((st = upload(s, &s->d_vxy32, v32.data(), v32.size()))) return st;
     if ((st = upload(s, &s->d_inv_mu_area, imua.data(), imua.size()))) return st;
     if ((st = upload(s, &s->d_inv_2area, i2a.data(), i2a.size()))) return st;
-    // SELL-64 of M~ (wall rows are empty: e = 0 there)
+    // SELL-64 of M~ in device edge order (wall rows are empty: e = 0 there)
     const int nsl = (ne + kSlice - 1) / kSlice;
     std::vector<int32_t> sp(nsl + 1, 0), sw(nsl, 0);
     for (int sl = 0; sl < nsl; ++sl) {
         int w = 0;
         for (int r = sl * kSlice; r < std::min(ne, (sl + 1) * kSlice); ++r)
-            w = std::max(w, s->mt.ptr[r + 1] - s->mt.ptr[r]);
+            w = std::max(w, s->mt.ptr[s->ecan[r] + 1] - s->mt.ptr[s->ecan[r]]);
         sw[sl] = w;
         sp[sl + 1] = sp[sl] + w * kSlice;
     }
@@ -645,9 +671,10 @@ fetd_status upload_mesh(fetd_sim *s)
             for (int j = 0; j < sw[sl]; ++j) {
                 const int q = sp[sl] + j * kSlice + ln;
                 const int rr = std::min(r, ne - 1);
-                if (r < ne && s->mt.ptr[r] + j < s->mt.ptr[r + 1]) {
-                    scol[q] = s->mt.col[s->mt.ptr[r] + j];
-                    sval[q] = s->mt.val[s->mt.ptr[r] + j];
+                const int rc = s->ecan[rr];
+                if (r < ne && s->mt.ptr[rc] + j < s->mt.ptr[rc + 1]) {
+                    scol[q] = s->edev[s->mt.col[s->mt.ptr[rc] + j]];
+                    sval[q] = s->mt.val[s->mt.ptr[rc] + j];
                 } else {
                     scol[q] = rr;
                     sval[q] = 0.0;
@@ -709,6 +736,28 @@ fetd_status check_device_errors(fetd_sim *s)
 
 fetd_status download(fetd_sim *s, void *dst, const void *src, size_t bytes);
 
+// Edge arrays cross the C-ABI in canonical order and live on the device in
+// device order.
+fetd_status download_edges(fetd_sim *s, double *dst, const double *d_src)
+{
+    std::vector<double> tmp(size_t(s->ne));
+    if (fetd_status st = download(s, tmp.data(), d_src, 8 * tmp.size())) return st;
+    for (int e = 0; e < s->ne; ++e) dst[e] = tmp[s->edev[e]];
+    return FETD_OK;
+}
+
+fetd_status upload_edges(fetd_sim *s, double **d_dst, const double *src)
+{
+    std::vector<double> tmp(size_t(s->ne));
+    for (int r = 0; r < s->ne; ++r) tmp[r] = src[s->ecan[r]];
+    if (!*d_dst) return upload(s, d_dst, tmp.data(), tmp.size());
+    hipError_t e = hipMemcpyAsync(*d_dst, tmp.data(), 8 * tmp.size(), hipMemcpyHostToDevice,
+                                  s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "edge upload");
+    return FETD_OK;
+}
+
 fetd_status grow_block_counts(fetd_sim *s, int64_t extra)
 {
     // per-tile counter pairs: one region per species, the new one appended
@@ -717,13 +766,18 @@ fetd_status grow_block_counts(fetd_sim *s, int64_t extra)
     const int64_t need = used + tiles_of(extra) + 1;
     if (need > s->block_count_cap) {
         std::vector<unsigned long long> old(2 * size_t(need), 0ull);
+        std::vector<uint32_t> home(size_t(need), 0u);
         if (s->block_count_cap > 0) {
             fetd_status st = download(s, old.data(), s->d_block_counts, 16 * size_t(s->block_count_cap));
+            if (!st) st = download(s, home.data(), s->d_tile_home, 4 * size_t(s->block_count_cap));
             if (st) return st;
         }
         s->dev_free(s->d_block_counts);
         s->d_block_counts = nullptr;
+        s->dev_free(s->d_tile_home);
+        s->d_tile_home = nullptr;
         fetd_status st = upload(s, &s->d_block_counts, old.data(), old.size());
+        if (!st) st = upload(s, &s->d_tile_home, home.data(), home.size());
         if (st) return st;
         s->block_count_cap = need;
     }
@@ -801,6 +855,7 @@ fetd_status sort_all(fetd_sim *s)
         a.offsets = s->d_offsets;
         a.block_sums = s->d_block_sums;
         a.elem_bytes = int(2 * rb);
+        a.tile_home = s->d_tile_home + sp.bc_offset;
         // launch_sort fills key_out with the lost key first (slots past the alive count)
         hipError_t e = launch_sort(s->stream, a);
         if (e != hipSuccess) return s->hip_fail(e, "sort");
@@ -969,11 +1024,7 @@ fetd_status fetd_fields_set(fetd_sim *s, const double *bz_ext, const double *e_e
         s->d_bz_ext = nullptr;
     }
     if (e_ext) {
-        if (!s->d_e_ext && (st = alloc_zero(s, &s->d_e_ext, s->ne))) return st;
-        hipError_t e = hipMemcpyAsync(s->d_e_ext, e_ext, sizeof(double) * s->ne,
-                                      hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) return s->hip_fail(e, "fields_set");
+        if ((st = upload_edges(s, &s->d_e_ext, e_ext))) return st;
     } else if (s->d_e_ext) {
         s->dev_free(s->d_e_ext);
         s->d_e_ext = nullptr;
@@ -1006,15 +1057,7 @@ fetd_status fetd_set_absorber(fetd_sim *s, const double *sigma_tri)
             s->node_gauss[s->edge_hi[e]] = 0;
         }
     }
-    if (!s->d_damp) {
-        if (fetd_status st = upload(s, &s->d_damp, damp.data(), damp.size())) return st;
-    } else {
-        hipError_t e = hipMemcpyAsync(s->d_damp, damp.data(), 8 * damp.size(),
-                                      hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) return s->hip_fail(e, "set_absorber");
-    }
-    return FETD_OK;
+    return upload_edges(s, &s->d_damp, damp.data());
 }
 
 fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, int64_t n,
@@ -1170,6 +1213,7 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
     mv.grad32 = s->d_grad32;
     mv.vxy64 = s->d_vxy64;
     mv.vxy32 = s->d_vxy32;
+    mv.tri_ebase = s->d_tri_ebase;
     const size_t rb = s->real_bytes();
     for (int it = 0; it < n_steps; ++it) {
         if (s->steps_since_sort >= s->resort_every) {
@@ -1204,6 +1248,7 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
             for (int k = 0; k < 6; ++k) a.aff[k] = s->affine[k];
             a.counters = s->d_counters;
             a.block_counts = s->d_block_counts + 2 * sp.bc_offset;
+            a.tile_home = s->d_tile_home + sp.bc_offset;
             fetd_sim::Timer t(s, 1);
             e = launch_particles(s->stream, mv, a, pusher, s->fp32());
             if (e != hipSuccess) return s->hip_fail(e, "particle step");
@@ -1242,13 +1287,13 @@ fetd_status fetd_fields_get(fetd_sim *s, int32_t which, void *dst, int64_t capac
     if (st) return st;
     const void *src = nullptr;
     size_t bytes = 0;
-    bool host = false;
+    bool host = false, edge = false;
     std::vector<int32_t> tmp;
     switch (which) {
-    case FETD_FIELD_E: src = s->d_e; bytes = 8 * size_t(s->ne); break;
-    case FETD_FIELD_D: src = s->d_d; bytes = 8 * size_t(s->ne); break;
+    case FETD_FIELD_E: src = s->d_e; bytes = 8 * size_t(s->ne); edge = true; break;
+    case FETD_FIELD_D: src = s->d_d; bytes = 8 * size_t(s->ne); edge = true; break;
     case FETD_FIELD_B: src = s->d_b; bytes = 8 * size_t(s->nf); break;
-    case FETD_FIELD_J: src = s->d_cur_last; bytes = 8 * size_t(s->ne); break;
+    case FETD_FIELD_J: src = s->d_cur_last; bytes = 8 * size_t(s->ne); edge = true; break;
     case FETD_FIELD_Q:
         if ((st = compute_charge(s))) return st;
         src = s->d_q;
@@ -1282,6 +1327,7 @@ fetd_status fetd_fields_get(fetd_sim *s, int32_t which, void *dst, int64_t capac
         std::memcpy(dst, src, bytes);
         return FETD_OK;
     }
+    if (edge) return download_edges(s, static_cast<double *>(dst), static_cast<const double *>(src));
     return download(s, dst, src, bytes);
 }
 
@@ -1350,10 +1396,10 @@ fetd_status fetd_diagnostics(fetd_sim *s, fetd_diag *out)
     std::vector<double> q(nn), dv(nn), e(ne), d(ne), b(s->nf), jl(ne);
     if ((st = download(s, q.data(), s->d_q, 8 * size_t(nn)))) return st;
     if ((st = download(s, dv.data(), s->d_divd, 8 * size_t(nn)))) return st;
-    if ((st = download(s, e.data(), s->d_e, 8 * size_t(ne)))) return st;
-    if ((st = download(s, d.data(), s->d_d, 8 * size_t(ne)))) return st;
+    if ((st = download_edges(s, e.data(), s->d_e))) return st;
+    if ((st = download_edges(s, d.data(), s->d_d))) return st;
     if ((st = download(s, b.data(), s->d_b, 8 * size_t(s->nf)))) return st;
-    if ((st = download(s, jl.data(), s->d_cur_last, 8 * size_t(ne)))) return st;
+    if ((st = download_edges(s, jl.data(), s->d_cur_last))) return st;
     double gmax = 0, qmax = 0;
     for (int n = 0; n < nn; ++n) {
         qmax = std::max(qmax, std::max(std::fabs(q[n]), std::fabs(s->q0[n])));
@@ -1587,6 +1633,7 @@ SegDesc seg_desc(fetd_sim *s, const Species &sp, int pbuf)
     d.m.grad32 = s->d_grad32;
     d.m.vxy64 = s->d_vxy64;
     d.m.vxy32 = s->d_vxy32;
+    d.m.tri_ebase = s->d_tri_ebase;
     const size_t rb = s->real_bytes();
     StepArgs &a = d.a;
     a.n = sp.n;
@@ -1606,6 +1653,7 @@ SegDesc seg_desc(fetd_sim *s, const Species &sp, int pbuf)
     for (int k = 0; k < 6; ++k) a.aff[k] = s->affine[k];
     a.counters = s->d_counters;
     a.block_counts = s->d_block_counts + 2 * sp.bc_offset;
+    a.tile_home = s->d_tile_home + sp.bc_offset;
     return d;
 }
 

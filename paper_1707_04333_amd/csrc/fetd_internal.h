@@ -29,7 +29,17 @@ struct MeshView {
     const float *grad32;   // [nf*8]: same in FP32, padded to 32 B
     const double *vxy64;   // [nf*6]: image-consistent vertex coordinates
     const float *vxy32;    // [nf*8]
+    // Edges are numbered on the device in order of first appearance along
+    // the triangle order; tri_ebase[f] = number of edges first met before
+    // triangle f (the edges of f and of its near successors lie at or above).
+    const uint32_t *tri_ebase;
 };
+
+// LDS current window of a particle tile: kWin consecutive device edge ids
+// starting at the edges of the triangle kWinBack before the tile's home
+// triangle (the triangle of its first particle at the last sort).
+constexpr int kWin = 2048;
+constexpr uint32_t kWinBack = 512;
 
 // Arguments of one particle-stage launch (one species).
 struct StepArgs {
@@ -49,6 +59,7 @@ struct StepArgs {
     double aff[6];
     unsigned long long *counters;  // [2] error flags, [3] first bad id (rarely written)
     unsigned long long *block_counts;  // [2 * tiles]: per-tile running sums (segments, lost)
+    const uint32_t *tile_home;     // [tiles]: home triangle of each tile (set by the sort)
     const int32_t *pid;            // load ids (for error reports)
 };
 
@@ -114,6 +125,7 @@ struct SortArgs {
     int32_t *offsets;  // [nf + 1]
     int32_t *block_sums;
     int elem_bytes;    // 8 (float2) or 16 (double2)
+    uint32_t *tile_home;  // [tiles of n]: triangle of each tile's first particle after the sort
 };
 hipError_t launch_sort(hipStream_t s, const SortArgs &a);
 

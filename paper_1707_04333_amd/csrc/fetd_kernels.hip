@@ -156,41 +156,24 @@ __device__ __forceinline__ void push2(R &ux, R &uy, R ex, R ey, R bz, R inv_c2)
 }
 
 // ---------------------------------------------------------------------
-// Block-local FP64 current accumulation: an open-addressing hash table in
-// LDS keyed by edge id.  A block deposits every path piece of its
-// particles here (LDS FP64 atomics) and flushes one global atomic per
-// distinct edge at the end; the sorted order keeps the distinct edges of a
-// block few.
+// Block-local FP64 current accumulation: a window of kWin consecutive
+// device edge ids in LDS, placed by the tile's home triangle.  Triangle-
+// sorted tiles touch a few dozen edges, almost all inside the window; an
+// edge outside it (a neighbour far away in the triangle order) goes
+// straight to the global accumulator.  Neither path waits for a result.
 // ---------------------------------------------------------------------
-constexpr int kHashLog2 = 10;
-constexpr int kHash = 1 << kHashLog2;
-constexpr int kProbe = 32;
-
 struct LdsCurrent {
-    int *key;
-    double *val;
-    double *global;  // fallback when the table is congested
+    double *acc;     // [kWin]
+    double *global;  // current accumulator of the step
+    uint32_t base;   // first edge id of the window
 
     __device__ __forceinline__ void add(int edge, double v) const
     {
-        unsigned h = (unsigned(edge) * 2654435761u) >> (32 - kHashLog2);
-#pragma nounroll
-        for (int probe = 0; probe < kProbe; ++probe) {
-            int k = __hip_atomic_load(key + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (k == -1) {
-                int expected = -1;
-                __hip_atomic_compare_exchange_strong(key + h, &expected, edge, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-                k = expected == -1 ? edge : expected;
-            }
-            if (k == edge) {
-                __hip_atomic_fetch_add(val + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                return;
-            }
-            h = (h + 1) & (kHash - 1);
-        }
-        atomic_add_f64(global + edge, v);
+        const uint32_t j = uint32_t(edge) - base;
+        if (j < uint32_t(kWin))
+            __hip_atomic_fetch_add(acc + j, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            atomic_add_f64(global + edge, v);
     }
 };
 
@@ -325,30 +308,33 @@ __device__ __forceinline__ Piece<R> trace_piece(const Grad<R> &g, R &l0, R &l1, 
     return pc;
 }
 
-// Continue a particle past the edge it is leaving: move into the
-// neighbour, trace the next piece and deposit it, until the move ends
-// inside a triangle (returns true), meets a wall (lost) or exceeds the
-// crossing cap.  On return (f, r, l) hold the end triangle, derived slot
-// and barycentrics.
+// Continue a particle past the edge it is leaving: it enters triangle nbf
+// (-1 = wall) through that triangle's local edge kk at the point where
+// l_{kk+2} = la, with the fraction ts of its move done.  Trace and deposit
+// piece after piece until the move ends inside a triangle (returns true),
+// meets a wall (lost) or exceeds the crossing cap.  The tables of each new
+// triangle are loaded together, neighbours included, so every crossing
+// costs one round trip to the cache.  On return (f, r, l) hold the end
+// triangle, derived slot and barycentrics.
 template <typename R>
 __device__ __forceinline__ bool continue_track(const MeshView &m, const LdsCurrent &dep, double q,
-                                               int cap, uint32_t &f, int &r, Piece<R> pc, R &l0,
-                                               R &l1, R &l2, R rx, R ry, unsigned long long &nseg,
-                                               bool &capped)
+                                               int cap, uint32_t &f, int &r, int nbf, int kk,
+                                               R la, R ts, R &l0, R &l1, R &l2, R rx, R ry,
+                                               unsigned long long &nseg, bool &capped)
 {
-    for (int it = 1; !pc.done; ++it) {
-        const int4 nb = ld<int4>(m.tri_nbr, f * 16u);
-        const int nbf = pick(pc.ks, nb.x, nb.y, nb.z);
+    for (int it = 1;; ++it) {
         if (nbf < 0) return false;  // wall
         if (it >= cap) {
             capped = true;
             return false;
         }
+        f = uint32_t(nbf);
+        const Grad<R> g = load_grad(m, f, R(0));
+        const int4 te = ld<int4>(m.tri_edge, f * 16u);
+        const int4 nb = ld<int4>(m.tri_nbr, f * 16u);
         // CCW neighbours traverse the shared edge in opposite directions:
-        // node ks+1 of f is node kk+2 of the neighbour and vice versa.
-        const int kk = (nb.w >> (2 * pc.ks)) & 3;
+        // node ks+1 of the old triangle is node kk+2 here and vice versa.
         const int b2 = prev3(kk);
-        const R la = pc.la;
         l0 = kk == 0 ? R(0) : (b2 == 0 ? la : R(1) - la);
         l1 = kk == 1 ? R(0) : (b2 == 1 ? la : R(1) - la);
         l2 = kk == 2 ? R(0) : (b2 == 2 ? la : R(1) - la);
@@ -357,18 +343,20 @@ __device__ __forceinline__ bool continue_track(const MeshView &m, const LdsCurre
         const double s1 = kk == 1 ? 0.0 : (b2 == 1 ? xa : xb);
         const double s2 = kk == 2 ? 0.0 : (b2 == 2 ? xa : xb);
         r = next3(kk);
-        f = uint32_t(nbf);
-        const R sc = R(1) - pc.ts;
+        const R sc = R(1) - ts;
         rx = rx * sc;
         ry = ry * sc;
-        pc = trace_piece(load_grad(m, f, R(0)), l0, l1, l2, s0, s1, s2, r, rx, ry, kk);
+        const Piece<R> pc = trace_piece(g, l0, l1, l2, s0, s1, s2, r, rx, ry, kk);
         nseg += 1;
-        const int4 te = ld<int4>(m.tri_edge, f * 16u);
         dep.add(te.x, ((te.w & 1) ? -q : q) * pc.w0);
         dep.add(te.y, ((te.w & 2) ? -q : q) * pc.w1);
         dep.add(te.z, ((te.w & 4) ? -q : q) * pc.w2);
+        if (pc.done) return true;
+        nbf = pick(pc.ks, nb.x, nb.y, nb.z);
+        kk = (nb.w >> (2 * pc.ks)) & 3;
+        la = pc.la;
+        ts = pc.ts;
     }
-    return true;
 }
 
 // Store the end state of a particle (or mark it lost) and count it.
@@ -414,8 +402,7 @@ struct Queue {
 
 template <typename R>
 struct TileShared {
-    int key[kHash];
-    double val[kHash];
+    double acc[kWin];
     Queue<R> q;
     int qn;
     unsigned long long red[2][kBlock / 64];
@@ -429,127 +416,117 @@ __device__ __forceinline__ void particle_tile(const MeshView &m, const StepArgs 
 {
     using R2 = typename Vec2<R>::type;
     constexpr uint32_t kR2 = sizeof(R2);
-    int *s_key = sh.key;
-    double *s_val = sh.val;
+    double *s_acc = sh.acc;
     Queue<R> &s_q = sh.q;
     int &s_qn = sh.qn;
     auto &red = sh.red;
-    for (int t = threadIdx.x; t < kHash; t += kBlock) {
-        s_key[t] = -1;
-        s_val[t] = 0.0;
+    // The particle streams of the next pass are loaded while the current
+    // pass computes (unconditionally: the loads never wait for the key).
+    uint32_t i_next = tile * kPPT * kBlock + threadIdx.x;
+    uint32_t key_next = kLost;
+    R2 pr_next{}, uu_next{};
+    if (int64_t(i_next) < a.n) {
+        key_next = ld<uint32_t>(a.key, i_next * 4u);
+        pr_next = ld<R2>(a.lam, i_next * kR2);
+        uu_next = ld<R2>(a.u, i_next * kR2);
     }
+    uint32_t wbase = 0;
+    if (a.tile_home) {
+        const uint32_t home = a.tile_home[tile];
+        wbase = m.tri_ebase[home > kWinBack ? home - kWinBack : 0u];
+    }
+    for (int t = threadIdx.x; t < kWin; t += kBlock) s_acc[t] = 0.0;
     if (threadIdx.x == 0) s_qn = 0;
     __syncthreads();
-    const LdsCurrent dep{s_key, s_val, a.cur};
+    const LdsCurrent dep{s_acc, a.cur, wbase};
     const int lane = threadIdx.x & 63;
     unsigned long long nseg = 0, nlost = 0;
     const double q = a.qdt;
 
-    // The particle streams of the next pass are loaded while the current
-    // pass computes.
-    uint32_t i_next = tile * kPPT * kBlock + threadIdx.x;
-    uint32_t key_next = int64_t(i_next) < a.n ? ld<uint32_t>(a.key, i_next * 4u) : kLost;
-    R2 pr_next{}, uu_next{};
-    if (key_next != kLost) {
-        pr_next = ld<R2>(a.lam, i_next * kR2);
-        uu_next = ld<R2>(a.u, i_next * kR2);
-    }
     for (int pass = 0; pass < kPPT; ++pass) {
         const uint32_t i = i_next;
         const uint32_t key = key_next;
         const R2 pr = pr_next, uu = uu_next;
         const bool alive = key != kLost;
+        // Dead lanes (removed particles, tail of the last tile) compute on
+        // triangle 0 and store nothing.
+        const uint32_t f = alive ? (key & kTriMask) : 0u;
+        const int r = alive ? int(key >> 30) : 0;
+        // The pass's triangle tables are requested before the next pass's
+        // particle streams.
+        Rec<R> rc;
+        if constexpr (sizeof(R) == 4) rc = load_rec(a.rec, f);
+        else rc = load_rec64(a.rec, f);
+        const Grad<R> g = load_grad(m, f, R(0));
+        const int4 te = ld<int4>(m.tri_edge, f * 16u);
+        const int4 nb = ld<int4>(m.tri_nbr, f * 16u);
         if (pass + 1 < kPPT) {
             i_next = i + kBlock;
-            key_next = int64_t(i_next) < a.n ? ld<uint32_t>(a.key, i_next * 4u) : kLost;
-            if (key_next != kLost) {
+            key_next = kLost;
+            if (int64_t(i_next) < a.n) {
+                key_next = ld<uint32_t>(a.key, i_next * 4u);
                 pr_next = ld<R2>(a.lam, i_next * kR2);
                 uu_next = ld<R2>(a.u, i_next * kR2);
             }
         }
 
-        int f0 = -1;
-        double c0 = 0.0, c1 = 0.0, c2 = 0.0;  // first path piece (cross terms)
-        bool leaving = false;
-        uint32_t f = 0;
-        int r = 0;
-        R l0 = R(0), l1 = R(0), l2 = R(0), rx = R(0), ry = R(0);
-        Piece<R> pc{};
+        // local barycentrics: slot r derived from the stored pair
+        const R dR = (R(1) - pr.x) - pr.y;
+        R l0 = r == 0 ? dR : (r == 1 ? pr.y : pr.x);
+        R l1 = r == 0 ? pr.x : (r == 1 ? dR : pr.y);
+        R l2 = r == 0 ? pr.y : (r == 1 ? pr.x : dR);
+        const double dD = (1.0 - double(pr.x)) - double(pr.y);
+        const double s0 = r == 0 ? dD : double(l0);
+        const double s1 = r == 1 ? dD : double(l1);
+        const double s2 = r == 2 ? dD : double(l2);
 
-        if (alive) {
-            f = key & kTriMask;
-            r = int(key >> 30);
-            f0 = int(f);
-            // local barycentrics: slot r derived from the stored pair
-            const R dR = (R(1) - pr.x) - pr.y;
-            l0 = r == 0 ? dR : (r == 1 ? pr.y : pr.x);
-            l1 = r == 0 ? pr.x : (r == 1 ? dR : pr.y);
-            l2 = r == 0 ? pr.y : (r == 1 ? pr.x : dR);
-            const double dD = (1.0 - double(pr.x)) - double(pr.y);
-            const double s0 = r == 0 ? dD : double(l0);
-            const double s1 = r == 1 ? dD : double(l1);
-            const double s2 = r == 2 ? dD : double(l2);
-
-            // Gather (Sec. II.B): E = sum_n l_n V_n from the triangle record.
-            R ex, ey, bzf;
+        // Gather (Sec. II.B): E = sum_n l_n V_n from the triangle record.
+        R ex = l0 * rc.v0x + l1 * rc.v1x + l2 * rc.v2x;
+        R ey = l0 * rc.v0y + l1 * rc.v1y + l2 * rc.v2y;
+        if (a.has_affine) {
+            R x, y;
             if constexpr (sizeof(R) == 4) {
-                const Rec<float> rc = load_rec(a.rec, f);
-                ex = l0 * rc.v0x + l1 * rc.v1x + l2 * rc.v2x;
-                ey = l0 * rc.v0y + l1 * rc.v1y + l2 * rc.v2y;
-                bzf = rc.bz;
+                const float4 va = ld<float4>(m.vxy32, f * 32u), vb = ld<float4>(m.vxy32, f * 32u + 16u);
+                x = l0 * va.x + l1 * va.z + l2 * vb.x;
+                y = l0 * va.y + l1 * va.w + l2 * vb.y;
             } else {
-                const Rec<double> rc = load_rec64(a.rec, f);
-                ex = l0 * rc.v0x + l1 * rc.v1x + l2 * rc.v2x;
-                ey = l0 * rc.v0y + l1 * rc.v1y + l2 * rc.v2y;
-                bzf = rc.bz;
+                const double2 va = ld<double2>(m.vxy64, f * 48u), vb = ld<double2>(m.vxy64, f * 48u + 16u);
+                const double2 vc = ld<double2>(m.vxy64, f * 48u + 32u);
+                x = l0 * va.x + l1 * vb.x + l2 * vc.x;
+                y = l0 * va.y + l1 * vb.y + l2 * vc.y;
             }
-            if (a.has_affine) {
-                R x, y;
-                if constexpr (sizeof(R) == 4) {
-                    const float4 va = ld<float4>(m.vxy32, f * 32u), vb = ld<float4>(m.vxy32, f * 32u + 16u);
-                    x = l0 * va.x + l1 * va.z + l2 * vb.x;
-                    y = l0 * va.y + l1 * va.w + l2 * vb.y;
-                } else {
-                    const double2 va = ld<double2>(m.vxy64, f * 48u), vb = ld<double2>(m.vxy64, f * 48u + 16u);
-                    const double2 vc = ld<double2>(m.vxy64, f * 48u + 32u);
-                    x = l0 * va.x + l1 * vb.x + l2 * vc.x;
-                    y = l0 * va.y + l1 * vb.y + l2 * vc.y;
-                }
-                ex += R(a.aff[0]) + R(a.aff[2]) * x + R(a.aff[3]) * y;
-                ey += R(a.aff[1]) + R(a.aff[4]) * x + R(a.aff[5]) * y;
-            }
+            ex += R(a.aff[0]) + R(a.aff[2]) * x + R(a.aff[3]) * y;
+            ey += R(a.aff[1]) + R(a.aff[4]) * x + R(a.aff[5]) * y;
+        }
 
-            // Push (Sec. II.C).
-            const R alpha = R(a.alpha);
-            R ux = uu.x, uy = uu.y;
-            push2<P, R>(ux, uy, alpha * ex, alpha * ey, alpha * bzf, R(a.inv_c2));
-            const bool finite = isfinite(ux) && isfinite(uy);
+        // Push (Sec. II.C).
+        const R alpha = R(a.alpha);
+        R ux = uu.x, uy = uu.y;
+        push2<P, R>(ux, uy, alpha * ex, alpha * ey, alpha * rc.bz, R(a.inv_c2));
+        const bool finite = isfinite(ux) && isfinite(uy);
+        if (alive) {
             R2 un;
             un.x = ux;
             un.y = uy;
             st<R2>(a.u, i * kR2, un);
-
-            // Move: dr = dt u / gamma (Sec. II.C eq. eq.motion.dis).
-            const R ginv = rsqrt_(R(1) + (ux * ux + uy * uy) * R(a.inv_c2));
-            rx = finite ? R(a.dt) * ux * ginv : R(0);
-            ry = finite ? R(a.dt) * uy * ginv : R(0);
-
-            // First straight piece, in the start triangle (Sec. II.D).
-            pc = trace_piece(load_grad(m, f, R(0)), l0, l1, l2, s0, s1, s2, r, rx, ry, -1);
-            c0 = pc.w0;
-            c1 = pc.w1;
-            c2 = pc.w2;
-            nseg += 1;
-            if (!finite) {
-                atomicOr(a.counters + 2, 2ull);
-                atomicMin(a.counters + 3, (unsigned long long)(a.pid ? a.pid[i] : i));
-                finish_particle<R>(a, i, f, r, l0, l1, l2, false, false, nlost);
-            } else if (pc.done) {
-                finish_particle<R>(a, i, f, r, l0, l1, l2, true, false, nlost);
-            } else {
-                leaving = true;
-            }
         }
+
+        // Move: dr = dt u / gamma (Sec. II.C eq. eq.motion.dis).
+        const R ginv = rsqrt_(R(1) + (ux * ux + uy * uy) * R(a.inv_c2));
+        const R rx = finite ? R(a.dt) * ux * ginv : R(0);
+        const R ry = finite ? R(a.dt) * uy * ginv : R(0);
+
+        // First straight piece, in the start triangle (Sec. II.D).
+        const Piece<R> pc = trace_piece(g, l0, l1, l2, s0, s1, s2, r, rx, ry, -1);
+        nseg += alive ? 1 : 0;
+        if (alive && !finite) {
+            atomicOr(a.counters + 2, 2ull);
+            atomicMin(a.counters + 3, (unsigned long long)(a.pid ? a.pid[i] : i));
+        }
+        const bool leaving = alive && finite && !pc.done;
+        if (alive && !leaving) finish_particle<R>(a, i, f, r, l0, l1, l2, finite, false, nlost);
+        const int nbf = pick(pc.ks < 0 ? 0 : pc.ks, nb.x, nb.y, nb.z);
+        const int kk = (nb.w >> (2 * (pc.ks < 0 ? 0 : pc.ks))) & 3;
 
         // Queue the particles leaving their triangle (one LDS atomic per
         // wavefront); overflow is finished in place.
@@ -562,22 +539,27 @@ __device__ __forceinline__ void particle_tile(const MeshView &m, const StepArgs 
             if (leaving) {
                 if (slot < kQueue) {
                     s_q.idx[slot] = i;
-                    s_q.fk[slot] = f | (uint32_t(pc.ks) << 30);
+                    s_q.fk[slot] = nbf < 0 ? kLost : (uint32_t(nbf) | (uint32_t(kk) << 30));
                     s_q.ts[slot] = pc.ts;
                     s_q.la[slot] = pc.la;
                     s_q.rx[slot] = rx;
                     s_q.ry[slot] = ry;
                 } else {
                     bool capped = false;
-                    const bool ok = continue_track(m, dep, q, a.cap, f, r, pc, l0, l1, l2, rx, ry,
-                                                   nseg, capped);
-                    finish_particle<R>(a, i, f, r, l0, l1, l2, ok, capped, nlost);
+                    uint32_t fe = f;
+                    int re = r;
+                    R m0 = R(0), m1 = R(0), m2 = R(0);
+                    const bool ok = continue_track(m, dep, q, a.cap, fe, re, nbf, kk, pc.la, pc.ts,
+                                                   m0, m1, m2, rx, ry, nseg, capped);
+                    finish_particle<R>(a, i, fe, re, m0, m1, m2, ok, capped, nlost);
                 }
             }
         }
 
         // Wavefront segmented sum of the first-piece currents over runs of
         // equal start triangle, then one LDS add per edge and run.
+        const int f0 = alive ? int(f) : -1;
+        double c0 = alive ? pc.w0 : 0.0, c1 = alive ? pc.w1 : 0.0, c2 = alive ? pc.w2 : 0.0;
         const int kprev = __shfl_up(f0, 1, 64);
         const bool head = lane == 0 || kprev != f0;
         const unsigned long long hm = __ballot(head);
@@ -586,7 +568,6 @@ __device__ __forceinline__ void particle_tile(const MeshView &m, const StepArgs 
         wave_segmented_sum(c0, c1, c2, lane, seg_start);
         const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
         if (tail && f0 >= 0) {
-            const int4 te = ld<int4>(m.tri_edge, uint32_t(f0) * 16u);
             dep.add(te.x, ((te.w & 1) ? -q : q) * c0);
             dep.add(te.y, ((te.w & 2) ? -q : q) * c1);
             dep.add(te.z, ((te.w & 4) ? -q : q) * c2);
@@ -598,25 +579,24 @@ __device__ __forceinline__ void particle_tile(const MeshView &m, const StepArgs 
     const int nq = s_qn < kQueue ? s_qn : kQueue;
     for (int t = threadIdx.x; t < nq; t += kBlock) {
         const uint32_t i = s_q.idx[t];
-        uint32_t f = s_q.fk[t] & kTriMask;
-        Piece<R> pc{};
-        pc.ks = int(s_q.fk[t] >> 30);
-        pc.ts = s_q.ts[t];
-        pc.la = s_q.la[t];
-        pc.done = false;
+        const uint32_t fk = s_q.fk[t];
+        const int nbf = fk == kLost ? -1 : int(fk & kTriMask);
+        const int kk = int(fk >> 30);
+        uint32_t f = 0;
         int r = 0;
         R l0 = R(0), l1 = R(0), l2 = R(0);
         bool capped = false;
-        const bool ok = continue_track(m, dep, q, a.cap, f, r, pc, l0, l1, l2, s_q.rx[t],
-                                       s_q.ry[t], nseg, capped);
+        const bool ok = continue_track(m, dep, q, a.cap, f, r, nbf, kk, s_q.la[t], s_q.ts[t], l0, l1,
+                                       l2, s_q.rx[t], s_q.ry[t], nseg, capped);
         finish_particle<R>(a, i, f, r, l0, l1, l2, ok, capped, nlost);
     }
 
-    // Flush the block's currents: one global FP64 atomic per distinct edge.
+    // Flush the block's currents: one global FP64 atomic per touched edge
+    // of the window (a slot is non-zero only if an edge in range was added).
     __syncthreads();
-    for (int t = threadIdx.x; t < kHash; t += kBlock) {
-        const int e = s_key[t];
-        if (e >= 0) atomic_add_f64(a.cur + e, s_val[t]);
+    for (int t = threadIdx.x; t < kWin; t += kBlock) {
+        const double v = s_acc[t];
+        if (v != 0.0) atomic_add_f64(a.cur + wbase + uint32_t(t), v);
     }
 
     // Counters: per-block running sums in the block's own slot (launches on
@@ -644,11 +624,14 @@ __device__ __forceinline__ void particle_tile(const MeshView &m, const StepArgs 
     __syncthreads();
 }
 
-#ifndef FETD_WAVES_PER_EU
-#define FETD_WAVES_PER_EU 1
-#endif
+// Occupancy target of the single-run particle kernel: 5 wavefronts per
+// SIMD in FP32 (fits without spilling), 4 in FP64.  The batched kernel
+// (more live state per tile) targets 4.
+template <typename R>
+constexpr int kWavesPerEU = sizeof(R) == 4 ? 5 : 4;
+
 template <int P, typename R>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FETD_WAVES_PER_EU)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<R>)))
 void k_particle_step(MeshView m, StepArgs a)
 {
     __shared__ TileShared<R> sh;
@@ -658,7 +641,7 @@ void k_particle_step(MeshView m, StepArgs a)
 // Batched particle stage: many (run, species) segments in one persistent
 // launch; blocks walk the flattened tile list.
 template <int P, typename R>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FETD_WAVES_PER_EU)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_particle_batched(const SegDesc *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
                         int nseg, uint32_t total_tiles)
 {
@@ -964,6 +947,17 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs a)
     a.pid_out[dst] = a.pid_in[i];
 }
 
+// Home triangle of every tile of the sorted segment (its first particle).
+__global__ __launch_bounds__(256) void k_tile_home(int64_t n, const uint32_t *__restrict__ key,
+                                                   uint32_t *__restrict__ home, int64_t tiles)
+{
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= tiles) return;
+    const int64_t i = t * int64_t(kPPT * kBlock);
+    const uint32_t k = i < n ? key[i] : kLost;
+    home[t] = k == kLost ? 0u : (k & kTriMask);
+}
+
 // ---------------------------------------------------------------------
 // Diagnostics.
 // ---------------------------------------------------------------------
@@ -1120,6 +1114,11 @@ hipError_t launch_sort(hipStream_t s, const SortArgs &a)
         else
             hipLaunchKernelGGL(k_sort_scatter<double2>, dim3(grid_for(a.n, 256)), dim3(256), 0, s,
                                a);
+    }
+    if (a.tile_home && a.n > 0) {
+        const int64_t tiles = (a.n + int64_t(kPPT * kBlock) - 1) / int64_t(kPPT * kBlock);
+        hipLaunchKernelGGL(k_tile_home, dim3(grid_for(tiles, 256)), dim3(256), 0, s, a.n,
+                           a.key_out, a.tile_home, tiles);
     }
     return hipGetLastError();
 }
