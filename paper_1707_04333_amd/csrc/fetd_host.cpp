@@ -1196,6 +1196,7 @@ fetd_status fetd_sort(fetd_sim *s)
 {
     if (!s) return FETD_E_ARG;
     DeviceGuard g(s->device);
+    fetd_sim::Timer t(s, 4);
     return sort_all(s);
 }
 

@@ -841,21 +841,47 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint
 }
 
 // ---------------------------------------------------------------------
-// Counting sort by triangle.
+// Counting sort by triangle, aggregated per block.  Between sorts the
+// particles move to nearby triangles, so a block of kSortB consecutive
+// particles covers a short triangle range: the block counts in an LDS
+// histogram over kSortBins triangles anchored kSortBack before the home
+// triangle of its first tile (from the previous sort) and adds one global
+// count per touched triangle; triangles outside the window are counted
+// directly.  The scatter ranks particles in the same LDS bins, reserves one
+// global range per touched triangle and writes the block's particles out in
+// triangle order (consecutive threads, consecutive destinations).
 // ---------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_sort_hist(int64_t n, const uint32_t *__restrict__ key,
-                                                   int32_t *__restrict__ counts)
+constexpr int kSortPer = 8;
+constexpr int kSortB = 256 * kSortPer;
+constexpr int kSortBins = 1024;
+constexpr uint32_t kSortBack = 256;
+
+__device__ __forceinline__ uint32_t sort_window(const SortArgs &a, int64_t blk)
 {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const uint32_t k = i < n ? key[i] : kLost;
-    const int lane = threadIdx.x & 63;
-    const uint32_t kp = __shfl_up(k, 1, 64);
-    const bool head = lane == 0 || kp != k;
-    const unsigned long long hm = __ballot(head);
-    const unsigned long long below = hm & ((2ull << lane) - 1ull);
-    const int seg_start = 63 - __clzll(below);
-    const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
-    if (tail && k != kLost) atomicAdd(counts + (k & kTriMask), lane - seg_start + 1);
+    if (!a.tile_home) return 0u;
+    const uint32_t h = a.tile_home[(blk * kSortB) / (kPPT * kBlock)];
+    return h > kSortBack ? h - kSortBack : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_sort_hist(SortArgs a)
+{
+    __shared__ int32_t h[kSortBins];
+    for (int t = threadIdx.x; t < kSortBins; t += 256) h[t] = 0;
+    const uint32_t wb = sort_window(a, blockIdx.x);
+    __syncthreads();
+    const int64_t b0 = int64_t(blockIdx.x) * kSortB;
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+        const int64_t i = b0 + j * 256 + int(threadIdx.x);
+        const uint32_t k = i < a.n ? a.key_in[i] : kLost;
+        if (k == kLost) continue;
+        const uint32_t f = k & kTriMask, bin = f - wb;
+        if (bin < uint32_t(kSortBins)) atomicAdd(&h[bin], 1);
+        else atomicAdd(a.counts + f, 1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kSortBins; t += 256)
+        if (h[t]) atomicAdd(a.counts + wb + uint32_t(t), h[t]);
 }
 
 // Exclusive scan of counts[0..n) into offsets[0..n], three passes.
@@ -920,31 +946,86 @@ __global__ __launch_bounds__(1024) void k_scan_add(int n, int32_t *__restrict__ 
 template <typename E>
 __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs a)
 {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const uint32_t k = i < a.n ? a.key_in[i] : kLost;
-    const int lane = threadIdx.x & 63;
-    const uint32_t kp = __shfl_up(k, 1, 64);
-    const bool head = lane == 0 || kp != k;
-    const unsigned long long hm = __ballot(head);
-    const unsigned long long below = hm & ((2ull << lane) - 1ull);
-    const int seg_start = 63 - __clzll(below);
-    const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
-    int base = 0;
-    if (tail && k != kLost) {
-        const int f = int(k & kTriMask);
-        base = a.offsets[f] + atomicAdd(a.counts + f, lane - seg_start + 1);
+    __shared__ int32_t cnt[kSortBins];   // local count, then global base per bin
+    __shared__ int32_t loc[kSortBins];   // local exclusive offset per bin
+    __shared__ int32_t wsum[4];
+    __shared__ int32_t n_out;            // particles outside the window
+    __shared__ uint16_t s_src[kSortB];   // local slot -> block-local input index
+    __shared__ int32_t s_dst[kSortB];    // local slot -> destination
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int t = tid; t < kSortBins; t += 256) cnt[t] = 0;
+    if (tid == 0) n_out = 0;
+    const uint32_t wb = sort_window(a, blockIdx.x);
+    __syncthreads();
+    const int64_t b0 = int64_t(blockIdx.x) * kSortB;
+    // ranks within the block's bins (outside the window: a direct global slot)
+    int32_t bin[kSortPer], rank[kSortPer];
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+        const int64_t i = b0 + j * 256 + tid;
+        const uint32_t k = i < a.n ? a.key_in[i] : kLost;
+        bin[j] = -1;
+        rank[j] = -1;
+        if (k == kLost) continue;
+        const uint32_t f = k & kTriMask, b = f - wb;
+        if (b < uint32_t(kSortBins)) {
+            bin[j] = int32_t(b);
+            rank[j] = atomicAdd(&cnt[b], 1);
+        } else {
+            bin[j] = -2;
+            rank[j] = atomicAdd(&n_out, 1);
+            s_dst[kSortB - 1 - rank[j]] = a.offsets[f] + atomicAdd(a.counts + f, 1);
+            s_src[kSortB - 1 - rank[j]] = uint16_t(j * 256 + tid);
+        }
     }
-    // broadcast the run's base from its tail lane
-    const unsigned long long tails = __ballot(tail);
-    const unsigned long long at_or_above = tails & ~((1ull << lane) - 1ull);
-    const int tail_lane = __ffsll((long long)at_or_above) - 1;
-    base = __shfl(base, tail_lane, 64);
-    if (k == kLost) return;
-    const int64_t dst = int64_t(base) + (lane - seg_start);
-    a.key_out[dst] = k;
-    reinterpret_cast<E *>(a.lam_out)[dst] = reinterpret_cast<const E *>(a.lam_in)[i];
-    reinterpret_cast<E *>(a.u_out)[dst] = reinterpret_cast<const E *>(a.u_in)[i];
-    a.pid_out[dst] = a.pid_in[i];
+    __syncthreads();
+    // exclusive scan of the bin counts (4 per thread), then one global
+    // reservation per touched triangle
+    int32_t c4[4], run = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        c4[q] = cnt[4 * tid + q];
+        run += c4[q];
+    }
+    int32_t incl = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int32_t before = incl - run;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int b = 4 * tid + q;
+        loc[b] = before;
+        before += c4[q];
+        cnt[b] = c4[q] ? a.offsets[wb + uint32_t(b)] + atomicAdd(a.counts + wb + uint32_t(b), c4[q])
+                       : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+        if (bin[j] < 0) continue;
+        const int slot = loc[bin[j]] + rank[j];
+        s_src[slot] = uint16_t(j * 256 + tid);
+        s_dst[slot] = cnt[bin[j]] + rank[j];
+    }
+    __syncthreads();
+    // copy out in slot order: in-window slots [0, n_in), outside ones at the top
+    const int n_in = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    const int nout = n_out;
+    for (int s = tid; s < kSortB; s += 256) {
+        if (s >= n_in && s < kSortB - nout) continue;
+        const int64_t src = b0 + s_src[s];
+        const int64_t dst = s_dst[s];
+        a.key_out[dst] = a.key_in[src];
+        reinterpret_cast<E *>(a.lam_out)[dst] = reinterpret_cast<const E *>(a.lam_in)[src];
+        reinterpret_cast<E *>(a.u_out)[dst] = reinterpret_cast<const E *>(a.u_in)[src];
+        a.pid_out[dst] = a.pid_in[src];
+    }
 }
 
 // Home triangle of every tile of the sorted segment (its first particle).
@@ -1098,8 +1179,7 @@ hipError_t launch_sort(hipStream_t s, const SortArgs &a)
     err = launch_fill_u32(s, a.key_out, kLost, a.n);
     if (err != hipSuccess) return err;
     if (a.n > 0)
-        hipLaunchKernelGGL(k_sort_hist, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a.n, a.key_in,
-                           a.counts);
+        hipLaunchKernelGGL(k_sort_hist, dim3(grid_for(a.n, kSortB)), dim3(256), 0, s, a);
     const int nb = int((a.nf + 1023) / 1024);
     hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, a.nf, a.counts, a.offsets,
                        a.block_sums);
@@ -1109,11 +1189,11 @@ hipError_t launch_sort(hipStream_t s, const SortArgs &a)
     if (err != hipSuccess) return err;
     if (a.n > 0) {
         if (a.elem_bytes == 8)
-            hipLaunchKernelGGL(k_sort_scatter<float2>, dim3(grid_for(a.n, 256)), dim3(256), 0, s,
-                               a);
+            hipLaunchKernelGGL(k_sort_scatter<float2>, dim3(grid_for(a.n, kSortB)), dim3(256), 0,
+                               s, a);
         else
-            hipLaunchKernelGGL(k_sort_scatter<double2>, dim3(grid_for(a.n, 256)), dim3(256), 0, s,
-                               a);
+            hipLaunchKernelGGL(k_sort_scatter<double2>, dim3(grid_for(a.n, kSortB)), dim3(256), 0,
+                               s, a);
     }
     if (a.tile_home && a.n > 0) {
         const int64_t tiles = (a.n + int64_t(kPPT * kBlock) - 1) / int64_t(kPPT * kBlock);
