@@ -158,6 +158,29 @@ def cpu_baseline(theta, n_full, pusher, sample_pairs=500_000, sample_steps=100):
                        f"step, single-threaded FP64 C oracle; {el:.1f} s")}
 
 
+def run_synchro(args):
+    """The synchrocyclotron of Sec. III.A (one electron, RF gap driven from
+    the host every step): steps/s of the driven run, energy gained and the
+    Gauss residual.  --workload synchro[_synched|_unsynched|_nonrel]."""
+    from paper_1707_04333_amd import experiments as X
+    from paper_1707_04333_amd import inputs as I
+    case = args.workload.split("_", 1)[1] if "_" in args.workload else "synched"
+    w = I.synchrocyclotron(case)
+    steps = args.steps if args.steps != 200 else 5000
+    t0 = time.perf_counter()
+    r = X.run_synchrocyclotron(w, steps, record_every=max(steps // 10, 1))
+    el = time.perf_counter() - t0
+    return {"metric": METRIC, "value": steps / el, "unit": "particle-steps/s", "n_gpus": 1,
+            "steps": steps, "warmup": 0, "ms_per_step": el / steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "synchrocyclotron", "case": case, "n_tris": w.mesh.n_tris,
+                       "n_particles": 1, "pusher": "boris_tan", "precision": "fp64"},
+            "ekin_eV": [float(e / I.E_CHARGE) for e in r["ekin"]],
+            "gauss_rel": r["diag"]["gauss_rel"],
+            "note": "one electron; each step reads the electron back to drive the RF phase"}
+
+
 def make_workload(name, args, precision):
     from paper_1707_04333_amd import inputs as I
     if name == "pair":
@@ -204,6 +227,9 @@ def main():
         del src, dst
         log("copied 1 GiB device-to-device")
 
+    if args.workload.startswith("synchro"):
+        print(json.dumps(run_synchro(args)))
+        return
     log(f"generating workload {args.workload}")
     w = make_workload(args.workload, args, "mixed")
     pusher = args.pusher or ("boris" if args.workload == "pair" else w.pusher)

@@ -157,6 +157,14 @@ fetd_status fetd_mesh_create(const fetd_mesh_desc *mesh, const fetd_opts *opts,
 fetd_status fetd_fields_set(fetd_sim *sim, const double *bz_ext, const double *e_ext,
                             const double *e_affine);
 
+/* Time-dependent amplitude of the applied edge field: from the next step
+ * on, the gather uses e + scale * e_ext (a radio-frequency drive such as the
+ * accelerating gap of the synchrocyclotron, Sec. III.A, set by the caller
+ * each step as E0 sin(phase)).  The default is 1.  The applied field is not
+ * evolved by the field update.  A batch created with fetd_batch_create keeps
+ * the scale each run had at creation.  FETD_E_ARG if scale is not finite. */
+fetd_status fetd_set_ext_scale(fetd_sim *sim, double scale);
+
 /* Absorbing layer (not part of the paper, which uses a PML): a per-
  * triangle conductivity sigma_tri [S/m] (NULL clears).  Each edge takes the
  * mean conductivity of its triangles and its d is multiplied after every

@@ -89,6 +89,7 @@ struct fetd_sim {
     void *d_rec = nullptr;
     double *d_bz_ext = nullptr, *d_e_ext = nullptr, *d_damp = nullptr;
     bool has_affine = false;
+    double e_scale = 1.0;  // multiplier of the applied edge field
     double affine[6] = {0, 0, 0, 0, 0, 0};
     // device: particles
     std::vector<Species> species;
@@ -1034,6 +1035,14 @@ fetd_status fetd_fields_set(fetd_sim *s, const double *bz_ext, const double *e_e
     return FETD_OK;
 }
 
+fetd_status fetd_set_ext_scale(fetd_sim *s, double scale)
+{
+    if (!s) return FETD_E_ARG;
+    if (!std::isfinite(scale)) return s->fail(FETD_E_ARG, "scale must be finite");
+    s->e_scale = scale;
+    return FETD_OK;
+}
+
 fetd_status fetd_set_absorber(fetd_sim *s, const double *sigma_tri)
 {
     if (!s) return FETD_E_ARG;
@@ -1224,7 +1233,7 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
         hipError_t e;
         {
         fetd_sim::Timer t(s, 0);
-        e = launch_faraday(s->stream, s->nf, s->d_tri_edge, s->d_e, s->d_e_ext, s->d_b,
+        e = launch_faraday(s->stream, s->nf, s->d_tri_edge, s->d_e, s->d_e_ext, s->e_scale, s->d_b,
                                       s->d_h, s->d_inv_mu_area, s->d_inv_2area, s->d_bz_ext,
                                       s->d_grad64, s->d_rec, s->fp32(), s->dt);
         }
@@ -1670,6 +1679,7 @@ fetd_status batch_build(fetd_batch *b)
         d.tri_edge = s->d_tri_edge;
         d.e = s->d_e;
         d.e_ext = s->d_e_ext;
+        d.e_scale = s->e_scale;
         d.b = s->d_b;
         d.h = s->d_h;
         d.inv_mu_area = s->d_inv_mu_area;

@@ -75,6 +75,7 @@ struct FieldDesc {
     const int4 *tri_edge;
     const double *e;
     const double *e_ext;
+    double e_scale;   // multiplier of e_ext
     double *b;
     double *h;
     const double *inv_mu_area;
@@ -98,9 +99,10 @@ struct FieldDesc {
 
 // Host-callable launchers (fetd_kernels.hip).
 hipError_t launch_faraday(hipStream_t s, int nf, const int4 *tri_edge, const double *e,
-                          const double *e_ext, double *b, double *h, const double *inv_mu_area,
-                          const double *inv_2area, const double *bz_ext, const double *grad64,
-                          void *rec, bool rec_fp32, double dt);
+                          const double *e_ext, double e_scale, double *b, double *h,
+                          const double *inv_mu_area, const double *inv_2area,
+                          const double *bz_ext, const double *grad64, void *rec, bool rec_fp32,
+                          double dt);
 hipError_t launch_particles(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
                             bool fp32);
 hipError_t launch_ampere(hipStream_t s, int ne, const int4 *edge_face, const double *h,

@@ -664,7 +664,7 @@ void k_particle_batched(const SegDesc *__restrict__ segs, const uint32_t *__rest
 template <typename R>
 __device__ __forceinline__ void faraday_tri(int f, const int4 *__restrict__ tri_edge,
                                             const double *__restrict__ e,
-                                            const double *__restrict__ e_ext,
+                                            const double *__restrict__ e_ext, double e_scale,
                                             double *__restrict__ b, double *__restrict__ h,
                                             const double *__restrict__ inv_mu_area,
                                             const double *__restrict__ inv_2area,
@@ -685,7 +685,10 @@ __device__ __forceinline__ void faraday_tri(int f, const int4 *__restrict__ tri_
     if (bz_ext) bz += bz_ext[f];
     double t0 = s0, t1 = s1, t2 = s2;
     if (e_ext) {
-        const double x0 = e_ext[te.x], x1 = e_ext[te.y], x2 = e_ext[te.z];
+        // applied field scaled (rounded product, not fused into the sum)
+        const double x0 = __dmul_rn(e_scale, e_ext[te.x]);
+        const double x1 = __dmul_rn(e_scale, e_ext[te.y]);
+        const double x2 = __dmul_rn(e_scale, e_ext[te.z]);
         t0 = (te.w & 1) ? -(e0 + x0) : (e0 + x0);
         t1 = (te.w & 2) ? -(e1 + x1) : (e1 + x1);
         t2 = (te.w & 4) ? -(e2 + x2) : (e2 + x2);
@@ -707,7 +710,7 @@ __device__ __forceinline__ void faraday_tri(int f, const int4 *__restrict__ tri_
 template <typename R>
 __global__ __launch_bounds__(256) void k_faraday(int nf, const int4 *__restrict__ tri_edge,
                                                  const double *__restrict__ e,
-                                                 const double *__restrict__ e_ext,
+                                                 const double *__restrict__ e_ext, double e_scale,
                                                  double *__restrict__ b, double *__restrict__ h,
                                                  const double *__restrict__ inv_mu_area,
                                                  const double *__restrict__ inv_2area,
@@ -717,7 +720,8 @@ __global__ __launch_bounds__(256) void k_faraday(int nf, const int4 *__restrict_
 {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f < nf)
-        faraday_tri<R>(f, tri_edge, e, e_ext, b, h, inv_mu_area, inv_2area, bz_ext, grad, rec, dt);
+        faraday_tri<R>(f, tri_edge, e, e_ext, e_scale, b, h, inv_mu_area, inv_2area, bz_ext, grad,
+                       rec, dt);
 }
 
 // Run of a batched field-stage block: the last run whose block prefix is
@@ -743,10 +747,12 @@ __global__ __launch_bounds__(256) void k_faraday_batched(const FieldDesc *__rest
         const int f = int(g - prefix[r]) * 256 + int(threadIdx.x);
         if (f >= d.nf) continue;
         if (d.rec_fp32)
-            faraday_tri<float>(f, d.tri_edge, d.e, d.e_ext, d.b, d.h, d.inv_mu_area, d.inv_2area,
+            faraday_tri<float>(f, d.tri_edge, d.e, d.e_ext, d.e_scale, d.b, d.h, d.inv_mu_area,
+                               d.inv_2area,
                                d.bz_ext, d.grad64, static_cast<float *>(d.rec), d.dt);
         else
-            faraday_tri<double>(f, d.tri_edge, d.e, d.e_ext, d.b, d.h, d.inv_mu_area, d.inv_2area,
+            faraday_tri<double>(f, d.tri_edge, d.e, d.e_ext, d.e_scale, d.b, d.h, d.inv_mu_area,
+                                d.inv_2area,
                                 d.bz_ext, d.grad64, static_cast<double *>(d.rec), d.dt);
     }
 }
@@ -1106,19 +1112,20 @@ inline unsigned grid_for(int64_t n, int block) { return unsigned((n + block - 1)
 }  // namespace
 
 hipError_t launch_faraday(hipStream_t s, int nf, const int4 *tri_edge, const double *e,
-                          const double *e_ext, double *b, double *h, const double *inv_mu_area,
-                          const double *inv_2area, const double *bz_ext, const double *grad64,
-                          void *rec, bool rec_fp32, double dt)
+                          const double *e_ext, double e_scale, double *b, double *h,
+                          const double *inv_mu_area, const double *inv_2area,
+                          const double *bz_ext, const double *grad64, void *rec, bool rec_fp32,
+                          double dt)
 {
     if (nf <= 0) return hipSuccess;
     if (rec_fp32)
         hipLaunchKernelGGL(k_faraday<float>, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
-                           tri_edge, e, e_ext, b, h, inv_mu_area, inv_2area, bz_ext, grad64,
-                           static_cast<float *>(rec), dt);
+                           tri_edge, e, e_ext, e_scale, b, h, inv_mu_area, inv_2area, bz_ext,
+                           grad64, static_cast<float *>(rec), dt);
     else
         hipLaunchKernelGGL(k_faraday<double>, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
-                           tri_edge, e, e_ext, b, h, inv_mu_area, inv_2area, bz_ext, grad64,
-                           static_cast<double *>(rec), dt);
+                           tri_edge, e, e_ext, e_scale, b, h, inv_mu_area, inv_2area, bz_ext,
+                           grad64, static_cast<double *>(rec), dt);
     return hipGetLastError();
 }
 

@@ -99,7 +99,8 @@ def lib():
                     "fetd_set_resort": [P, ctypes.c_int32],
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32],
-                    "fetd_set_absorber": [P, P]}
+                    "fetd_set_absorber": [P, P],
+                    "fetd_set_ext_scale": [P, ctypes.c_double]}
         for name, args in optional.items():
             if hasattr(L, name):
                 getattr(L, name).argtypes = args
@@ -195,6 +196,10 @@ def fields_set(h, bz_ext=None, e_ext=None, e_affine=None):
 def set_absorber(h, sigma_tri):
     sg = None if sigma_tri is None else np.ascontiguousarray(sigma_tri, dtype=np.float64)
     _check(lib().fetd_set_absorber(h, _p(sg)), h)
+
+
+def set_ext_scale(h, scale):
+    _check(lib().fetd_set_ext_scale(h, float(scale)), h)
 
 
 def particles_load_bary(h, q, m, w, tri, lam, u, slot=None):
@@ -321,6 +326,9 @@ class Sim:
     def set_absorber(self, sigma_tri):
         set_absorber(self.h, sigma_tri)
 
+    def set_ext_scale(self, scale):
+        set_ext_scale(self.h, scale)
+
     def load(self, q, m, w, tri, lam, u, slot=None):
         return particles_load_bary(self.h, q, m, w, tri, lam, u, slot)
 
@@ -404,11 +412,13 @@ class Batch:
 def from_workload(w, precision=None, **kw):
     """Create a Sim from an inputs.Workload and load its species and fields."""
     from . import inputs as I
-    sim = Sim(w.mesh, w.dt, I.EPS0, I.MU0, I.C_LIGHT,
+    sim = Sim(w.mesh, w.dt, I.EPS0, I.MU0, w.extra.get("c", I.C_LIGHT),
               precision=precision or w.precision, spai_level=kw.pop("spai_level", w.spai_level),
               **kw)
-    if w.bz_ext or w.e_affine is not None:
-        bz = np.full(w.mesh.n_tris, float(w.bz_ext)) if w.bz_ext else None
+    bz = w.extra.get("bz_tri")
+    if bz is None and w.bz_ext:
+        bz = np.full(w.mesh.n_tris, float(w.bz_ext))
+    if bz is not None or w.e_affine is not None:
         sim.fields_set(bz_ext=bz, e_affine=w.e_affine)
     if "sigma_tri" in w.extra:
         sim.set_absorber(w.extra["sigma_tri"])

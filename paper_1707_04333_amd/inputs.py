@@ -354,6 +354,39 @@ def cyclotron(seed_offset: int = 0, n_particles: int = 64, n_side: int = 33) -> 
                     spai_level=2, extra={"gamma0": g})
 
 
+def synchrocyclotron(case: str = "synched", n_side: int = 50, steps: int = 5000,
+                     steps_per_period: int = 1000) -> Workload:
+    """Synchrocyclotron of Sec. III.A: one electron injected at (0.52, 0.5) m
+    with |v| = 1e7 m/s along +y on the PEC unit square; B_z = m v0/(e r0)
+    (r0 = 0.02 m, 2.84281e-3 T) over the magnet region, a disk of radius
+    0.45 m about the centre, and zero outside it; a vertical accelerating
+    gap of width 0.02 m centred at x = 0.5 carries the RF field
+    E_x = E0 sin(phase), E0 = 2e5 V/m, applied as edge DoFs whose amplitude
+    the driver sets each step.  case: "nonrel" (gamma held at 1, constant
+    frequency f0 = eB/(2 pi m)), "unsynched" (relativistic, f0) or "synched"
+    (relativistic, f0/gamma).  dt = 1/(f0 steps_per_period)."""
+    if case not in ("nonrel", "unsynched", "synched"):
+        raise ValueError(case)
+    mesh = grid_mesh(n_side, n_side, 1.0, 1.0)
+    v0, r0, e0, gap = 1.0e7, 0.02, 2.0e5, 0.02
+    B = M_E * v0 / (E_CHARGE * r0)
+    f0 = E_CHARGE * B / (2.0 * math.pi * M_E)
+    dt = 1.0 / (f0 * steps_per_period)
+    cen = mesh.centroids()
+    bz_tri = np.where(np.hypot(cen[:, 0] - 0.5, cen[:, 1] - 0.5) < 0.45, B, 0.0)
+    xy = np.array([[0.5 + r0, 0.5]])
+    tri, lam = locate_points(mesh, xy)
+    gamma = 1.0 if case == "nonrel" else 1.0 / math.sqrt(1.0 - (v0 / C_LIGHT) ** 2)
+    u = np.array([[0.0, gamma * v0]])
+    sp = Species("electron", -E_CHARGE, M_E, 1.0, tri, lam, u)
+    extra = {"bz_tri": bz_tri, "f0": f0, "e0": e0, "gap": gap, "gap_x": 0.5, "case": case,
+             "B": B}
+    if case == "nonrel":
+        extra["c"] = 1.0e30   # particle kinematics without relativistic mass
+    return Workload("synchrocyclotron_" + case, mesh, [sp], dt, steps, "boris_tan", "fp64",
+                    spai_level=1, extra=extra)
+
+
 def boosted_oscillator(n_particles: int = 1_000_000, n_side: int = 159,
                        amplitude: float = 1e-4) -> Workload:
     """Lorentz-boosted harmonic oscillation: 1 m square periodic in x, PEC

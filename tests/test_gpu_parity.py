@@ -301,3 +301,40 @@ def test_graded_absorbing_hc_parity(oracle_lib):
     d = g.diagnostics()
     assert d["gauss_rel"] <= 1e-12 and d["n_lost"] == osim.lost
     g.close()
+
+
+def test_synchrocyclotron_parity(oracle_lib):
+    """Sec. III.A synchrocyclotron, synchronised RF drive: the library's
+    driver (applied gap field scaled each step, frequency f0/gamma) against
+    the oracle stepped with the same drive; FP64, Boris with the tan
+    correction, 3000 steps (three turns, six gap crossings)."""
+    import math
+
+    from paper_1707_04333_amd import experiments as X
+    w = I.synchrocyclotron("synched")
+    steps = 3000
+    got = X.run_synchrocyclotron(w, steps, record_every=1000)
+    T = oracle_lib.Topology(w.mesh.node_xy, w.mesh.tri_nodes)
+    x = w.extra
+    xl, xh = w.mesh.node_xy[T.edge_lo, 0], w.mesh.node_xy[T.edge_hi, 0]
+    pattern = np.where(np.abs(0.5 * (xl + xh) - x["gap_x"]) < 0.5 * x["gap"],
+                       x["e0"] * (xh - xl), 0.0)
+    sp = [(s.q, s.m, s.w, s.tri, s.lam, s.u) for s in w.species]
+    osim = oracle_lib.OracleSim(T, w.dt, sp, I.EPS0, I.MU0, I.C_LIGHT, spai_level=1,
+                                bz_ext=x["bz_tri"], e_ext=pattern)
+    phase = 0.0
+    for _ in range(steps):
+        u = osim.species[0].u[0]
+        gamma = math.sqrt(1.0 + (u @ u) / I.C_LIGHT ** 2)
+        osim.e_ext = math.sin(phase) * pattern
+        osim.step(1, "boris_tan")
+        phase += 2.0 * math.pi * (x["f0"] / gamma) * w.dt
+    s = osim.species[0]
+    gp = got["particles"]
+    assert gp["tri"][0] == s.tri[0] and gp["slot"][0] == s.slot[0]
+    assert np.abs(gp["lam"][0] - s.lam[0]).max() <= 1e-12
+    assert np.abs(gp["u"][0] - s.u[0]).max() <= 1e-12 * np.abs(s.u[0]).max()
+    assert np.abs(got["e"] - osim.e).max() <= 1e-11 * np.abs(osim.e).max()
+    assert got["diag"]["gauss_rel"] <= 1e-12
+    # six in-phase gap crossings: the electron gained tens of keV
+    assert got["ekin"][-1] > 40.0 * got["ekin"][0]
