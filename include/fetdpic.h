@@ -252,6 +252,24 @@ fetd_status fetd_batch_create(fetd_sim *const *sims, int32_t n, int32_t use_grap
 fetd_status fetd_batch_step(fetd_batch *batch, int32_t n_steps, int32_t pusher);
 void fetd_batch_destroy(fetd_batch *batch);
 
+/* Field probes (Sec. III.C samples E along a line at every step to obtain
+ * the dispersion relation).  n points xy [2n] (metres; located like
+ * fetd_particles_load, FETD_E_ARG if one lies outside the mesh).  After
+ * every step the self-consistent field E (applied fields excluded) is
+ * evaluated at each point from the Whitney interpolant of e (Sec. II.B);
+ * the values of each window of `every` consecutive steps are averaged and
+ * stored as one sample, up to max_samples samples (later ones are
+ * dropped).  n = 0 removes the probes; a new call restarts the record.
+ * Steps taken through fetd_batch_step are not probed. */
+fetd_status fetd_probe_set(fetd_sim *sim, int64_t n, const double *xy, int32_t every,
+                           int64_t max_samples);
+
+/* Copy the recorded probe samples to dst: [samples][n][2] doubles (E_x,
+ * E_y in V/m).  *n_samples receives the count; dst may be NULL to query it.
+ * FETD_E_ARG if capacity_bytes is too small. */
+fetd_status fetd_probe_get(fetd_sim *sim, double *dst, int64_t capacity_bytes,
+                           int64_t *n_samples);
+
 /* Sizes and SPAI quality. */
 fetd_status fetd_info_get(fetd_sim *sim, fetd_info *out);
 

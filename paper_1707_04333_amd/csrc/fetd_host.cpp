@@ -106,6 +106,11 @@ struct fetd_sim {
     uint32_t *d_tile_home = nullptr;  // per tile, same slots as d_block_counts
     int64_t block_count_cap = 0;  // blocks covered by d_block_counts
     double *d_q = nullptr, *d_divd = nullptr, *d_partial = nullptr;
+    // field probes
+    int64_t probe_n = 0, probe_max = 0, probe_samples = 0;
+    int32_t probe_every = 1, probe_in_window = 0;
+    int32_t *d_probe_tri = nullptr;
+    double *d_probe_lam = nullptr, *d_probe_acc = nullptr, *d_probe_buf = nullptr;
     static constexpr int kPartial = 1024;
 
     // state
@@ -1133,12 +1138,13 @@ fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, 
     return FETD_OK;
 }
 
-fetd_status fetd_particles_load(fetd_sim *s, double q, double m, double w, int64_t n,
-                                const double *xy, const double *u, int32_t *species_out)
+// Point location: for each point the lowest-id triangle containing it (on
+// periodic axes, the point or an image one period away) and its barycentric
+// pair (lambda_1, lambda_2).  `what` names the points in the error message.
+fetd_status locate_points(fetd_sim *s, int64_t n, const double *xy, std::vector<int32_t> &tri,
+                          std::vector<double> &lam, const char *what)
 {
 #pragma clang fp contract(off)
-    if (!s) return FETD_E_ARG;
-    if (n < 0 || (n > 0 && (!xy || !u))) return s->fail(FETD_E_ARG, "invalid particle arguments");
     // uniform bucket grid over triangle bounding boxes
     double x0 = 1e300, y0 = 1e300, x1 = -1e300, y1 = -1e300;
     for (int f = 0; f < s->nf; ++f)
@@ -1166,8 +1172,8 @@ fetd_status fetd_particles_load(fetd_sim *s, double q, double m, double w, int64
     }
     // the point and, on periodic axes, its images one period away (triangle
     // frames of a periodic mesh extend past the period cell)
-    std::vector<int32_t> tri(n);
-    std::vector<double> lam(2 * n);
+    tri.assign(size_t(n), -1);
+    lam.assign(2 * size_t(n), 0.0);
     const int mx = s->period[0] > 0 ? 1 : 0, my = s->period[1] > 0 ? 1 : 0;
     for (int64_t p = 0; p < n; ++p) {
         int best = -1;
@@ -1193,11 +1199,24 @@ fetd_status fetd_particles_load(fetd_sim *s, double q, double m, double w, int64
                     }
                 }
             }
-        if (best < 0) return s->fail(FETD_E_ARG, "particle " + std::to_string(p) + " is outside the mesh");
+        if (best < 0)
+            return s->fail(FETD_E_ARG, std::string(what) + " " + std::to_string(p) +
+                                           " is outside the mesh");
         tri[p] = best;
         lam[2 * p] = bl1;
         lam[2 * p + 1] = bl2;
     }
+    return FETD_OK;
+}
+
+fetd_status fetd_particles_load(fetd_sim *s, double q, double m, double w, int64_t n,
+                                const double *xy, const double *u, int32_t *species_out)
+{
+    if (!s) return FETD_E_ARG;
+    if (n < 0 || (n > 0 && (!xy || !u))) return s->fail(FETD_E_ARG, "invalid particle arguments");
+    std::vector<int32_t> tri;
+    std::vector<double> lam;
+    if (fetd_status st = locate_points(s, n, xy, tri, lam, "particle")) return st;
     return fetd_particles_load_bary(s, q, m, w, n, tri.data(), nullptr, lam.data(), u, species_out);
 }
 
@@ -1275,10 +1294,66 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
                             s->d_d, s->d_e);
         }
         if (e != hipSuccess) return s->hip_fail(e, "spmv");
+        if (s->probe_n > 0 && s->probe_samples < s->probe_max) {
+            const bool flush = ++s->probe_in_window == s->probe_every;
+            double *out = flush ? s->d_probe_buf + 2 * s->probe_n * s->probe_samples : nullptr;
+            e = launch_probe(s->stream, int(s->probe_n), s->d_probe_tri, s->d_probe_lam,
+                             s->d_tri_edge, s->d_grad64, s->d_e, s->d_probe_acc, out,
+                             1.0 / double(s->probe_every));
+            if (e != hipSuccess) return s->hip_fail(e, "probe");
+            if (flush) {
+                ++s->probe_samples;
+                s->probe_in_window = 0;
+            }
+        }
         ++s->step;
         ++s->steps_since_sort;
     }
     return FETD_OK;
+}
+
+fetd_status fetd_probe_set(fetd_sim *s, int64_t n, const double *xy, int32_t every,
+                           int64_t max_samples)
+{
+    if (!s) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    if (n < 0 || (n > 0 && (!xy || every < 1 || max_samples < 1)) || n > (int64_t(1) << 30))
+        return s->fail(FETD_E_ARG, "invalid probe arguments");
+    if (hipError_t e = hipStreamSynchronize(s->stream)) return s->hip_fail(e, "probe_set");
+    for (void *p : {(void *)s->d_probe_tri, (void *)s->d_probe_lam, (void *)s->d_probe_acc,
+                    (void *)s->d_probe_buf})
+        s->dev_free(p);
+    s->d_probe_tri = nullptr;
+    s->d_probe_lam = s->d_probe_acc = s->d_probe_buf = nullptr;
+    s->probe_n = s->probe_max = s->probe_samples = 0;
+    s->probe_in_window = 0;
+    if (n == 0) return FETD_OK;
+    std::vector<int32_t> tri;
+    std::vector<double> lam;
+    if (fetd_status st = locate_points(s, n, xy, tri, lam, "probe")) return st;
+    fetd_status st = upload(s, &s->d_probe_tri, tri.data(), tri.size());
+    if (!st) st = upload(s, &s->d_probe_lam, lam.data(), lam.size());
+    if (!st) st = alloc_zero(s, &s->d_probe_acc, 2 * size_t(n));
+    if (st) return st;
+    void *p = nullptr;
+    if (!s->dev_alloc(&p, sizeof(double) * 2 * size_t(n) * size_t(max_samples)))
+        return s->fail(FETD_E_OOM, "probe buffer");
+    s->d_probe_buf = static_cast<double *>(p);
+    s->probe_n = n;
+    s->probe_max = max_samples;
+    s->probe_every = every;
+    return FETD_OK;
+}
+
+fetd_status fetd_probe_get(fetd_sim *s, double *dst, int64_t capacity_bytes, int64_t *n_samples)
+{
+    if (!s) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    if (n_samples) *n_samples = s->probe_samples;
+    const size_t bytes = sizeof(double) * 2 * size_t(s->probe_n) * size_t(s->probe_samples);
+    if (!dst || bytes == 0) return FETD_OK;
+    if (capacity_bytes < int64_t(bytes)) return s->fail(FETD_E_ARG, "destination too small");
+    return download(s, dst, s->d_probe_buf, bytes);
 }
 
 fetd_status fetd_sync(fetd_sim *s)

@@ -141,6 +141,11 @@ hipError_t launch_ampere_batched(hipStream_t s, const FieldDesc *d, const uint32
 hipError_t launch_spmv_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,
                                int nrun, uint32_t total_blocks);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n);
+// Field probes: accumulate E at n points; when out is non-null write the
+// window average there (times inv_window) and restart the sum.
+hipError_t launch_probe(hipStream_t s, int n, const int32_t *tri, const double *lam,
+                        const int4 *tri_edge, const double *grad64, const double *e, double *acc,
+                        double *out, double inv_window);
 
 // Diagnostics.
 hipError_t launch_charge(hipStream_t s, int64_t n, const uint32_t *key, const void *lam,

@@ -1046,6 +1046,45 @@ __global__ __launch_bounds__(256) void k_tile_home(int64_t n, const uint32_t *__
 }
 
 // ---------------------------------------------------------------------
+// Field probes: E = sum_k s_k e_k (l_a grad l_b - l_b grad l_a) (Sec. II.B)
+// at fixed points, accumulated over a window of steps; at the end of a
+// window the average is written out and the sum restarts.
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_probe(int n, const int32_t *__restrict__ tri,
+                                               const double *__restrict__ lam,
+                                               const int4 *__restrict__ tri_edge,
+                                               const double *__restrict__ grad,
+                                               const double *__restrict__ e,
+                                               double *__restrict__ acc, double *__restrict__ out,
+                                               double inv_window)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int f = tri[i];
+    const double l1 = lam[2 * i], l2 = lam[2 * i + 1];
+    const double l0 = (1.0 - l1) - l2;
+    const int4 te = tri_edge[f];
+    const double *g = grad + size_t(f) * 6;
+    const double s0 = (te.w & 1) ? -e[te.x] : e[te.x];
+    const double s1 = (te.w & 2) ? -e[te.y] : e[te.y];
+    const double s2 = (te.w & 4) ? -e[te.z] : e[te.z];
+    // local edge k joins nodes a = k+1, b = k+2
+    const double ex = s0 * (l1 * g[4] - l2 * g[2]) + s1 * (l2 * g[0] - l0 * g[4]) +
+                      s2 * (l0 * g[2] - l1 * g[0]);
+    const double ey = s0 * (l1 * g[5] - l2 * g[3]) + s1 * (l2 * g[1] - l0 * g[5]) +
+                      s2 * (l0 * g[3] - l1 * g[1]);
+    double ax = acc[2 * i] + ex, ay = acc[2 * i + 1] + ey;
+    if (out) {
+        out[2 * i] = ax * inv_window;
+        out[2 * i + 1] = ay * inv_window;
+        ax = 0.0;
+        ay = 0.0;
+    }
+    acc[2 * i] = ax;
+    acc[2 * i + 1] = ay;
+}
+
+// ---------------------------------------------------------------------
 // Diagnostics.
 // ---------------------------------------------------------------------
 template <typename R>
@@ -1168,6 +1207,16 @@ hipError_t launch_spmv(hipStream_t s, int ne, const int32_t *slice_ptr, const in
     if (ne <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_spmv, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, slice_ptr, slice_w,
                        col, val, d, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(hipStream_t s, int n, const int32_t *tri, const double *lam,
+                        const int4 *tri_edge, const double *grad64, const double *e, double *acc,
+                        double *out, double inv_window)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe, dim3(grid_for(n, 256)), dim3(256), 0, s, n, tri, lam, tri_edge,
+                       grad64, e, acc, out, inv_window);
     return hipGetLastError();
 }
 

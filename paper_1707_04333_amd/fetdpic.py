@@ -100,7 +100,9 @@ def lib():
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32],
                     "fetd_set_absorber": [P, P],
-                    "fetd_set_ext_scale": [P, ctypes.c_double]}
+                    "fetd_set_ext_scale": [P, ctypes.c_double],
+                    "fetd_probe_set": [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int64],
+                    "fetd_probe_get": [P, P, ctypes.c_int64, P]}
         for name, args in optional.items():
             if hasattr(L, name):
                 getattr(L, name).argtypes = args
@@ -200,6 +202,19 @@ def set_absorber(h, sigma_tri):
 
 def set_ext_scale(h, scale):
     _check(lib().fetd_set_ext_scale(h, float(scale)), h)
+
+
+def probe_set(h, xy, every=1, max_samples=1):
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    _check(lib().fetd_probe_set(h, xy.shape[0], _p(xy), int(every), int(max_samples)), h)
+
+
+def probe_get(h, n_points):
+    ns = ctypes.c_int64()
+    _check(lib().fetd_probe_get(h, None, 0, ctypes.byref(ns)), h)
+    out = np.empty((ns.value, n_points, 2))
+    _check(lib().fetd_probe_get(h, _p(out), out.nbytes, ctypes.byref(ns)), h)
+    return out
 
 
 def particles_load_bary(h, q, m, w, tri, lam, u, slot=None):
@@ -328,6 +343,13 @@ class Sim:
 
     def set_ext_scale(self, scale):
         set_ext_scale(self.h, scale)
+
+    def probe_set(self, xy, every=1, max_samples=1):
+        self._probe_n = 0 if xy is None else np.asarray(xy).reshape(-1, 2).shape[0]
+        probe_set(self.h, np.zeros((0, 2)) if xy is None else xy, every, max_samples)
+
+    def probe_get(self):
+        return probe_get(self.h, getattr(self, "_probe_n", 0))
 
     def load(self, q, m, w, tri, lam, u, slot=None):
         return particles_load_bary(self.h, q, m, w, tri, lam, u, slot)

@@ -519,6 +519,38 @@ def pair_plasma(n_side: int = 316, length: float = 0.5, n_pairs: int = 8_000_000
                     extra={"omega_c": wc, "omega_p": wp, "n0": n0, "theta": theta})
 
 
+def bernstein_strip(n_x: int = 428, n_y: int = 8, length_x: float = 0.0214,
+                    theta: float = 0.005, ppc: int = 200, B0: float = 1.0, ratio: float = 2.0,
+                    seed_offset: int = 5, precision: str = "mixed") -> Workload:
+    """Pair plasma on a thin doubly periodic strip for the Bernstein
+    dispersion of Sec. III.C (the paper's run is a long strip of width
+    one gyroradius): n_x x n_y jittered cells of side length_x/n_x, ppc
+    collocated pairs per triangle with opposite in-plane Maxwell-Juttner
+    momenta of temperature theta, uniform B0, omega_c/omega_p = ratio per
+    species, dt = min(0.2/omega_c, 0.22 h/c).  The default theta = 0.005
+    (v_th = 0.07c) is the paper's non-relativistic example."""
+    h = length_x / n_x
+    length_y = n_y * h
+    mesh = grid_mesh(n_x, n_y, length_x, length_y, periodic_x=True, periodic_y=True)
+    n_pairs = ppc * mesh.n_tris
+    rng = np.random.default_rng(PARTICLE_SEED + seed_offset)
+    tri, lam = sample_in_triangles(mesh, n_pairs, rng)
+    p = sample_mj2d(n_pairs, theta, rng)
+    ang = rng.uniform(0.0, 2.0 * math.pi, n_pairs)
+    u = np.stack([C_LIGHT * p * np.cos(ang), C_LIGHT * p * np.sin(ang)], axis=1)
+    wc = E_CHARGE * B0 / M_E
+    wp = wc / ratio
+    n0 = wp * wp * EPS0 * M_E / (E_CHARGE * E_CHARGE)
+    weight = n0 * length_x * length_y / n_pairs
+    dt = min(0.2 / wc, 0.22 * h / C_LIGHT)
+    el = Species("electron", -E_CHARGE, M_E, weight, tri, lam, u)
+    po = Species("positron", E_CHARGE, M_E, weight, tri.copy(), lam.copy(), -u)
+    return Workload("bernstein_strip", mesh, [el, po], dt, 32768, "boris", precision,
+                    bz_ext=B0, spai_level=1,
+                    extra={"omega_c": wc, "omega_p": wp, "n0": n0, "theta": theta,
+                           "length_x": length_x, "length_y": length_y})
+
+
 def pair_plasma_small(**kw) -> Workload:
     """The 1/16-area copy of the pair-plasma workload (same density and
     temperature): 0.125 m square, 79 x 79 torus, 1M particles."""

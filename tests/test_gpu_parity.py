@@ -338,3 +338,33 @@ def test_synchrocyclotron_parity(oracle_lib):
     assert got["diag"]["gauss_rel"] <= 1e-12
     # six in-phase gap crossings: the electron gained tens of keV
     assert got["ekin"][-1] > 40.0 * got["ekin"][0]
+
+
+def test_field_probes_match_oracle(oracle_lib):
+    """Probe samples (window averages of the Whitney-interpolated E of Sec.
+    II.B at fixed points, the sampling of Sec. III.C) against the oracle's
+    gather at the same points; samples past max_samples are dropped."""
+    w = I.pair_plasma(n_side=16, length=0.025, n_pairs=3001, theta=0.3, steps=20,
+                      precision="fp64")
+    rng = np.random.default_rng(3)
+    xy = rng.uniform(0.0, 0.025, (40, 2))
+    g = _gpu_sim(w, 1)
+    g.probe_set(xy, every=3, max_samples=5)
+    osim = _oracle_sim(oracle_lib, w, 1)
+    tri, lam = I.locate_points(w.mesh, xy)
+    L = np.stack([(1.0 - lam[:, 0]) - lam[:, 1], lam[:, 0], lam[:, 1]], axis=1)
+    acc = np.zeros((40, 2))
+    want = []
+    for n in range(20):
+        osim.step(1, "hc")
+        g.step(1, "hc")
+        acc += np.array([oracle_lib.gather_e(osim, tri[i], L[i]) for i in range(40)])
+        if (n + 1) % 3 == 0:
+            if len(want) < 5:
+                want.append(acc / 3.0)
+            acc[:] = 0.0
+    got = g.probe_get()
+    g.close()
+    want = np.array(want)
+    assert got.shape == (5, 40, 2)
+    assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
