@@ -38,5 +38,8 @@ def test_first_band_follows_nonrelativistic_bernstein():
     dev = np.abs(ridge - theory)
     assert np.median(dev) < 0.03, np.median(dev)
     assert np.mean(dev < 0.05) > 0.8, np.mean(dev < 0.05)
-    # the branch starts near the upper-hybrid frequency and falls toward omega_c
-    assert ridge[:3].mean() > 1.15 and ridge[-5:].mean() < 1.08
+    # the branch starts near the upper-hybrid frequency and falls toward
+    # omega_c (at the top of the range the mode fades into the noise)
+    kk = k[sel]
+    assert ridge[:3].mean() > 1.15
+    assert np.median(ridge[(kk > 20.0) & (kk < 32.0)]) < 1.07
