@@ -161,17 +161,36 @@ fetd_status fetd_fields_set(fetd_sim *sim, const double *bz_ext, const double *e
  * on, the gather uses e + scale * e_ext (a radio-frequency drive such as the
  * accelerating gap of the synchrocyclotron, Sec. III.A, set by the caller
  * each step as E0 sin(phase)).  The default is 1.  The applied field is not
- * evolved by the field update.  A batch created with fetd_batch_create keeps
- * the scale each run had at creation.  FETD_E_ARG if scale is not finite. */
+ * evolved by the field update.  A batch that holds the simulation takes the
+ * new scale at its next fetd_batch_step (it rebuilds its descriptors, which
+ * also ends its captured graph).  FETD_E_ARG if scale is not finite. */
 fetd_status fetd_set_ext_scale(fetd_sim *sim, double scale);
 
-/* Absorbing layer (not part of the paper, which uses a PML): a per-
- * triangle conductivity sigma_tri [S/m] (NULL clears).  Each edge takes the
- * mean conductivity of its triangles and its d is multiplied after every
- * Ampere update by (1 - x)/(1 + x), x = sigma dt / (2 eps0), a conduction
- * loss.  Nodes touching a lossy edge are left out of the Gauss residual of
- * fetd_diagnostics. */
+/* Matched absorbing layer, the stand-in for the PML of Sec. III.C: a per-
+ * triangle conductivity sigma_tri [S/m], nf values, host memory, read
+ * during the call (NULL clears).  Electric loss: each edge takes the mean
+ * conductivity of its triangles and its d is multiplied after every Ampere
+ * update by (1 - x)/(1 + x), x = sigma dt / (2 eps0).  Magnetic loss: each
+ * triangle's b is multiplied after every Faraday update by the same factor
+ * of its own sigma (magnetic conductivity sigma mu0 / eps0), which keeps
+ * the layer's wave impedance at that of free space, so a wave entering at
+ * normal incidence is not reflected by the step in loss.  Nodes touching a
+ * lossy edge are left out of the Gauss residual of fetd_diagnostics.
+ * FETD_E_ARG (nothing changed) if any sigma is negative or not finite.
+ * A batch that holds the simulation takes the new layer at its next
+ * fetd_batch_step, as it does after fetd_fields_set or a new species. */
 fetd_status fetd_set_absorber(fetd_sim *sim, const double *sigma_tri);
+
+/* Load the self-consistent field state (Sec. II.A): b [nf] face fluxes
+ * b^{n-1/2} [Wb/m] in triangle order, d [ne] edge fluxes d^n [C/m] in the
+ * edge order of FETD_FIELD_EDGES; host memory, read during the call; either
+ * may be NULL to keep the current value.  e^n = M~ d^n is recomputed; d on
+ * wall edges is taken as 0.  With fetd_fields_get (FETD_FIELD_B, _D) and
+ * fetd_particles_get / fetd_particles_load_bary it restarts a run from a
+ * saved state.  The Gauss accounting of fetd_diagnostics restarts from the
+ * loaded state (with the particles present then).  FETD_E_ARG (nothing
+ * changed) if a value is not finite. */
+fetd_status fetd_fields_load(fetd_sim *sim, const double *b, const double *d);
 
 /* Append a species of n macro particles given in barycentric form
  * (tri[n], slot[n] or NULL for slot 0, lam[2n], u[2n]).  Load order

@@ -70,7 +70,7 @@ def _declare(L):
     L.o_move.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P,
                          ctypes.c_int, P, P, P]
     L.o_move.restype = ctypes.c_int
-    L.o_faraday.argtypes = [P, P, P, ctypes.c_double, P]
+    L.o_faraday.argtypes = [P, P, P, ctypes.c_double, P, P]
     L.o_faraday.restype = None
     L.o_ampere.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
     L.o_ampere.restype = None
@@ -310,7 +310,7 @@ class OracleSim:
     e^{n+1} = M~ d^{n+1}."""
 
     def __init__(self, mesh, dt, species, eps0, mu0, c, spai_level=1, bz_ext=None,
-                 e_ext=None, affine=None, cap=64, damp=None):
+                 e_ext=None, affine=None, cap=64, damp=None, damp_b=None):
         self.T = Topology(mesh.node_xy, mesh.tri_nodes, mesh.tri_shift, mesh.period) \
             if not isinstance(mesh, Topology) else mesh
         T = self.T
@@ -328,6 +328,7 @@ class OracleSim:
         self.e_ext = None if e_ext is None else np.ascontiguousarray(e_ext, dtype=np.float64)
         self.affine = None if affine is None else np.ascontiguousarray(affine, dtype=np.float64)
         self.damp = None if damp is None else np.ascontiguousarray(damp, dtype=np.float64)
+        self.damp_b = None if damp_b is None else np.ascontiguousarray(damp_b, dtype=np.float64)
         self.species = [OSpecies(*s) if not isinstance(s, OSpecies) else s for s in species]
         self.cap = cap
         self.step_count = 0
@@ -356,7 +357,7 @@ class OracleSim:
         ms = ctypes.byref(self.ms)
         for _ in range(n_steps):
             b_new = np.empty_like(self.b)
-            L.o_faraday(ms, _p(self.b), _p(self.e), self.dt, _p(b_new))
+            L.o_faraday(ms, _p(self.b), _p(self.e), self.dt, _p(self.damp_b), _p(b_new))
             counts = np.zeros(2, dtype=np.int64)
             bad = np.zeros(1, dtype=np.int64)
             for s in self.species:
@@ -413,10 +414,15 @@ class OracleSim:
 
 
 def absorber_damp(T: Topology, sigma_tri, dt: float, eps0: float):
-    """Conduction loss of the absorbing layer (the build's own stand-in for
-    the paper's PML): edge conductivity = mean over its triangles; d is
-    multiplied by (1 - x)/(1 + x), x = sigma dt/(2 eps0), after each Ampere
-    update.  Returns (damp per edge, nodes kept in the Gauss residual)."""
+    """Losses of the absorbing layer (the build's own stand-in for the
+    paper's PML).  Electric: edge conductivity = mean over its triangles; d
+    is multiplied by (1 - x)/(1 + x), x = sigma dt/(2 eps0), after each
+    Ampere update.  Magnetic: the matched loss sigma_m = sigma mu0/eps0 on
+    each triangle, so b is multiplied by the same factor of its own sigma
+    after each Faraday update; with both, a plane wave entering the layer
+    at normal incidence meets no impedance step (Z = sqrt(mu0/eps0) for
+    any sigma).  Returns (damp per edge, damp per triangle, nodes kept in
+    the Gauss residual)."""
     sg = np.asarray(sigma_tri, dtype=np.float64)
     f0, f1 = T.edge_tri[:, 0], T.edge_tri[:, 1]
     se = sg[f0].copy()
@@ -424,11 +430,13 @@ def absorber_damp(T: Topology, sigma_tri, dt: float, eps0: float):
     se[two] = 0.5 * (sg[f0[two]] + sg[f1[two]])
     x = se * dt / (2.0 * eps0)
     damp = np.where(se > 0, (1.0 - x) / (1.0 + x), 1.0)
+    xt = sg * dt / (2.0 * eps0)
+    damp_b = np.where(sg > 0, (1.0 - xt) / (1.0 + xt), 1.0)
     keep = T.node_free.astype(bool).copy()
     lossy = se > 0
     keep[T.edge_lo[lossy]] = False
     keep[T.edge_hi[lossy]] = False
-    return damp, keep
+    return damp, damp_b, keep
 
 
 def push(pusher, u, E, B, q, m, dt, c):

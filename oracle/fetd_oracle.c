@@ -286,15 +286,19 @@ int o_move(const o_mesh *M, int32_t *ptri, int8_t *pslot, double *pair, double d
 /* Field update (Sec. II.A, eqs. semi.dis.curl.1/2).                       */
 /* ---------------------------------------------------------------------- */
 
-/* b^{n+1/2} = b^{n-1/2} - dt C e^n. */
+/* b^{n+1/2} = b^{n-1/2} - dt C e^n.  damp_b (optional) multiplies b on
+ * absorbing-layer triangles after the update: the magnetic loss that
+ * matches the layer's electric conductivity (sigma_m / mu0 = sigma / eps0,
+ * the same factor as on d). */
 void o_faraday(const o_mesh *M, const double *b_old, const double *e, double dt,
-               double *b_new)
+               const double *damp_b, double *b_new)
 {
     for (int f = 0; f < M->nf; ++f) {
         double circ = 0.0;
         for (int k = 0; k < 3; ++k)
             circ += M->tri_sign[3 * f + k] * e[M->tri_edge[3 * f + k]];
         b_new[f] = b_old[f] - dt * circ;
+        if (damp_b) b_new[f] = b_new[f] * damp_b[f];
     }
 }
 

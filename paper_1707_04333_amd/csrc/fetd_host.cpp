@@ -87,7 +87,7 @@ struct fetd_sim {
     double *d_cur = nullptr;       // current accumulator of the step in progress
     double *d_cur_last = nullptr;  // current of the last completed step
     void *d_rec = nullptr;
-    double *d_bz_ext = nullptr, *d_e_ext = nullptr, *d_damp = nullptr;
+    double *d_bz_ext = nullptr, *d_e_ext = nullptr, *d_damp = nullptr, *d_damp_b = nullptr;
     bool has_affine = false;
     double e_scale = 1.0;  // multiplier of the applied edge field
     double affine[6] = {0, 0, 0, 0, 0, 0};
@@ -116,6 +116,7 @@ struct fetd_sim {
     // state
     int64_t step = 0;
     int64_t steps_since_sort = 0;
+    uint64_t desc_gen = 0;  // bumped when a buffer or value a batch descriptor holds changes
     bool have_baseline = false;
     std::vector<double> q0, divd0, q_last;
     int64_t q_last_step = -1;
@@ -1018,6 +1019,7 @@ fetd_status fetd_fields_set(fetd_sim *s, const double *bz_ext, const double *e_e
 {
     if (!s) return FETD_E_ARG;
     DeviceGuard g(s->device);
+    ++s->desc_gen;
     fetd_status st;
     if (bz_ext) {
         if (!s->d_bz_ext && (st = alloc_zero(s, &s->d_bz_ext, s->nf))) return st;
@@ -1045,6 +1047,7 @@ fetd_status fetd_set_ext_scale(fetd_sim *s, double scale)
     if (!s) return FETD_E_ARG;
     if (!std::isfinite(scale)) return s->fail(FETD_E_ARG, "scale must be finite");
     s->e_scale = scale;
+    ++s->desc_gen;
     return FETD_OK;
 }
 
@@ -1052,26 +1055,82 @@ fetd_status fetd_set_absorber(fetd_sim *s, const double *sigma_tri)
 {
     if (!s) return FETD_E_ARG;
     DeviceGuard g(s->device);
+    if (sigma_tri)
+        for (int f = 0; f < s->nf; ++f)
+            if (!(sigma_tri[f] >= 0.0) || !std::isfinite(sigma_tri[f]))
+                return s->fail(FETD_E_ARG, "conductivity must be finite and >= 0");
+    if (hipError_t e = hipStreamSynchronize(s->stream)) return s->hip_fail(e, "set_absorber");
     s->node_gauss = s->node_free;
+    ++s->desc_gen;
     if (!sigma_tri) {
         s->dev_free(s->d_damp);
-        s->d_damp = nullptr;
+        s->dev_free(s->d_damp_b);
+        s->d_damp = s->d_damp_b = nullptr;
         return FETD_OK;
     }
-    std::vector<double> damp(s->ne, 1.0);
+    // Electric loss on edges (conductivity averaged over the edge's
+    // triangles) and the matched magnetic loss sigma_m = sigma mu0 / eps0 on
+    // triangles: both decay with the factor (1 - x) / (1 + x),
+    // x = sigma dt / (2 eps0), so the layer's wave impedance stays that of
+    // free space.
+    auto factor = [s](double sg) {
+        const double x = sg * s->dt / (2.0 * s->eps0);
+        return sg > 0.0 ? (1.0 - x) / (1.0 + x) : 1.0;
+    };
+    std::vector<double> damp(s->ne, 1.0), damp_b(s->nf, 1.0);
     for (int e = 0; e < s->ne; ++e) {
         const int f0 = s->edge_f[2 * e], f1 = s->edge_f[2 * e + 1];
         double sg = sigma_tri[f0];
         if (f1 >= 0) sg = 0.5 * (sigma_tri[f0] + sigma_tri[f1]);
-        if (!(sg >= 0.0)) return s->fail(FETD_E_ARG, "conductivity must be >= 0");
         if (sg > 0.0) {
-            const double x = sg * s->dt / (2.0 * s->eps0);
-            damp[e] = (1.0 - x) / (1.0 + x);
+            damp[e] = factor(sg);
             s->node_gauss[s->edge_lo[e]] = 0;
             s->node_gauss[s->edge_hi[e]] = 0;
         }
     }
-    return upload_edges(s, &s->d_damp, damp.data());
+    for (int f = 0; f < s->nf; ++f) damp_b[f] = factor(sigma_tri[f]);
+    fetd_status st = upload_edges(s, &s->d_damp, damp.data());
+    if (st) return st;
+    if (!s->d_damp_b) return upload(s, &s->d_damp_b, damp_b.data(), damp_b.size());
+    hipError_t e = hipMemcpyAsync(s->d_damp_b, damp_b.data(), 8 * damp_b.size(),
+                                  hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "absorber upload");
+    return FETD_OK;
+}
+
+fetd_status fetd_fields_load(fetd_sim *s, const double *b, const double *d)
+{
+    if (!s) return FETD_E_ARG;
+    DeviceGuard g(s->device);
+    if (b)
+        for (int f = 0; f < s->nf; ++f)
+            if (!std::isfinite(b[f])) return s->fail(FETD_E_ARG, "b must be finite");
+    if (d)
+        for (int e = 0; e < s->ne; ++e)
+            if (!std::isfinite(d[e])) return s->fail(FETD_E_ARG, "d must be finite");
+    if (hipError_t e = hipStreamSynchronize(s->stream)) return s->hip_fail(e, "fields_load");
+    if (b) {
+        hipError_t e = hipMemcpyAsync(s->d_b, b, 8 * size_t(s->nf), hipMemcpyHostToDevice,
+                                      s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "b upload");
+    }
+    if (d) {
+        // wall edges carry no degree of freedom
+        std::vector<double> df(d, d + s->ne);
+        for (int e = 0; e < s->ne; ++e)
+            if (!s->edge_free[e]) df[e] = 0.0;
+        fetd_status st = upload_edges(s, &s->d_d, df.data());
+        if (st) return st;
+        hipError_t e = launch_spmv(s->stream, s->ne, s->d_sl_ptr, s->d_sl_w, s->d_sl_col,
+                                   s->d_sl_val, s->d_d, s->d_e);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "fields_load spmv");
+    }
+    // Gauss's law is accounted from this state on
+    s->have_baseline = false;
+    return FETD_OK;
 }
 
 fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, int64_t n,
@@ -1086,6 +1145,7 @@ fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, 
         if (tri[i] < 0 || tri[i] >= s->nf) return s->fail(FETD_E_ARG, "triangle id out of range");
         if (slot && (slot[i] < 0 || slot[i] > 2)) return s->fail(FETD_E_ARG, "slot out of range");
     }
+    ++s->desc_gen;
     fetd_status st = grow_particles(s, n);
     if (st) return st;
     Species sp;
@@ -1253,8 +1313,8 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
         {
         fetd_sim::Timer t(s, 0);
         e = launch_faraday(s->stream, s->nf, s->d_tri_edge, s->d_e, s->d_e_ext, s->e_scale, s->d_b,
-                                      s->d_h, s->d_inv_mu_area, s->d_inv_2area, s->d_bz_ext,
-                                      s->d_grad64, s->d_rec, s->fp32(), s->dt);
+                           s->d_damp_b, s->d_h, s->d_inv_mu_area, s->d_inv_2area, s->d_bz_ext,
+                           s->d_grad64, s->d_rec, s->fp32(), s->dt);
         }
         if (e != hipSuccess) return s->hip_fail(e, "faraday");
         double *cur = s->d_cur;
@@ -1680,6 +1740,7 @@ struct fetd_batch {
     uint32_t *d_tri_prefix = nullptr, *d_edge_prefix = nullptr, *d_seg_prefix = nullptr;
     SegDesc *d_segs[2] = {nullptr, nullptr};  // [parity of sorts since creation]
     std::vector<int> pbuf0;                   // particle buffer of each run at creation
+    std::vector<uint64_t> gen0;               // desc_gen of each run at the last build
     int parity = 0;
     int steps_since_sort = 0;
     int resort_every = 20;
@@ -1756,6 +1817,7 @@ fetd_status batch_build(fetd_batch *b)
         d.e_ext = s->d_e_ext;
         d.e_scale = s->e_scale;
         d.b = s->d_b;
+        d.damp_b = s->d_damp_b;
         d.h = s->d_h;
         d.inv_mu_area = s->d_inv_mu_area;
         d.inv_2area = s->d_inv_2area;
@@ -1789,7 +1851,11 @@ fetd_status batch_build(fetd_batch *b)
     b->edge_blocks = ep.back();
     b->tiles = sp.back();
     b->pbuf0.clear();
-    for (fetd_sim *s : b->sims) b->pbuf0.push_back(s->pbuf);
+    b->gen0.clear();
+    for (fetd_sim *s : b->sims) {
+        b->pbuf0.push_back(s->pbuf);
+        b->gen0.push_back(s->desc_gen);
+    }
     b->parity = 0;
     if (!batch_upload(b, &b->d_fields, fd) || !batch_upload(b, &b->d_tri_prefix, tp) ||
         !batch_upload(b, &b->d_edge_prefix, ep) || !batch_upload(b, &b->d_seg_prefix, sp) ||
@@ -1891,10 +1957,12 @@ fetd_status fetd_batch_step(fetd_batch *b, int32_t n_steps, int32_t pusher)
 {
     if (!b || n_steps < 0 || pusher < 0 || pusher > 3) return FETD_E_ARG;
     DeviceGuard g(b->device);
-    // the members may have been sorted or reloaded individually: rebuild
+    // the members may have been sorted, reloaded or given new applied
+    // fields or layers individually: rebuild the descriptors
     bool stale = false;
     for (size_t r = 0; r < b->sims.size(); ++r)
-        if ((b->sims[r]->pbuf ^ b->parity) != b->pbuf0[r]) stale = true;
+        if ((b->sims[r]->pbuf ^ b->parity) != b->pbuf0[r] || b->sims[r]->desc_gen != b->gen0[r])
+            stale = true;
     if (stale) {
         batch_release(b);
         if (fetd_status st = batch_build(b)) return st;

@@ -77,6 +77,7 @@ struct FieldDesc {
     const double *e_ext;
     double e_scale;   // multiplier of e_ext
     double *b;
+    const double *damp_b;  // magnetic loss per triangle (absorbing layer) or null
     double *h;
     const double *inv_mu_area;
     const double *inv_2area;
@@ -99,7 +100,8 @@ struct FieldDesc {
 
 // Host-callable launchers (fetd_kernels.hip).
 hipError_t launch_faraday(hipStream_t s, int nf, const int4 *tri_edge, const double *e,
-                          const double *e_ext, double e_scale, double *b, double *h,
+                          const double *e_ext, double e_scale, double *b, const double *damp_b,
+                          double *h,
                           const double *inv_mu_area, const double *inv_2area,
                           const double *bz_ext, const double *grad64, void *rec, bool rec_fp32,
                           double dt);

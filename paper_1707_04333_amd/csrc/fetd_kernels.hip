@@ -665,7 +665,9 @@ template <typename R>
 __device__ __forceinline__ void faraday_tri(int f, const int4 *__restrict__ tri_edge,
                                             const double *__restrict__ e,
                                             const double *__restrict__ e_ext, double e_scale,
-                                            double *__restrict__ b, double *__restrict__ h,
+                                            double *__restrict__ b,
+                                            const double *__restrict__ damp_b,
+                                            double *__restrict__ h,
                                             const double *__restrict__ inv_mu_area,
                                             const double *__restrict__ inv_2area,
                                             const double *__restrict__ bz_ext,
@@ -678,7 +680,8 @@ __device__ __forceinline__ void faraday_tri(int f, const int4 *__restrict__ tri_
     const double s1 = (te.w & 2) ? -e1 : e1;
     const double s2 = (te.w & 4) ? -e2 : e2;
     const double bo = b[f];
-    const double bn = bo - dt * ((s0 + s1) + s2);
+    double bn = bo - dt * ((s0 + s1) + s2);
+    if (damp_b) bn = bn * damp_b[f];  // matched magnetic loss of the absorbing layer
     b[f] = bn;
     h[f] = bn * inv_mu_area[f];
     double bz = (bn + bo) * inv_2area[f];
@@ -711,7 +714,9 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_faraday(int nf, const int4 *__restrict__ tri_edge,
                                                  const double *__restrict__ e,
                                                  const double *__restrict__ e_ext, double e_scale,
-                                                 double *__restrict__ b, double *__restrict__ h,
+                                                 double *__restrict__ b,
+                                                 const double *__restrict__ damp_b,
+                                                 double *__restrict__ h,
                                                  const double *__restrict__ inv_mu_area,
                                                  const double *__restrict__ inv_2area,
                                                  const double *__restrict__ bz_ext,
@@ -720,8 +725,8 @@ __global__ __launch_bounds__(256) void k_faraday(int nf, const int4 *__restrict_
 {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f < nf)
-        faraday_tri<R>(f, tri_edge, e, e_ext, e_scale, b, h, inv_mu_area, inv_2area, bz_ext, grad,
-                       rec, dt);
+        faraday_tri<R>(f, tri_edge, e, e_ext, e_scale, b, damp_b, h, inv_mu_area, inv_2area, bz_ext,
+                       grad, rec, dt);
 }
 
 // Run of a batched field-stage block: the last run whose block prefix is
@@ -747,13 +752,13 @@ __global__ __launch_bounds__(256) void k_faraday_batched(const FieldDesc *__rest
         const int f = int(g - prefix[r]) * 256 + int(threadIdx.x);
         if (f >= d.nf) continue;
         if (d.rec_fp32)
-            faraday_tri<float>(f, d.tri_edge, d.e, d.e_ext, d.e_scale, d.b, d.h, d.inv_mu_area,
-                               d.inv_2area,
-                               d.bz_ext, d.grad64, static_cast<float *>(d.rec), d.dt);
+            faraday_tri<float>(f, d.tri_edge, d.e, d.e_ext, d.e_scale, d.b, d.damp_b, d.h,
+                             d.inv_mu_area, d.inv_2area, d.bz_ext, d.grad64,
+                             static_cast<float *>(d.rec), d.dt);
         else
-            faraday_tri<double>(f, d.tri_edge, d.e, d.e_ext, d.e_scale, d.b, d.h, d.inv_mu_area,
-                                d.inv_2area,
-                                d.bz_ext, d.grad64, static_cast<double *>(d.rec), d.dt);
+            faraday_tri<double>(f, d.tri_edge, d.e, d.e_ext, d.e_scale, d.b, d.damp_b, d.h,
+                             d.inv_mu_area, d.inv_2area, d.bz_ext, d.grad64,
+                             static_cast<double *>(d.rec), d.dt);
     }
 }
 
@@ -1151,7 +1156,8 @@ inline unsigned grid_for(int64_t n, int block) { return unsigned((n + block - 1)
 }  // namespace
 
 hipError_t launch_faraday(hipStream_t s, int nf, const int4 *tri_edge, const double *e,
-                          const double *e_ext, double e_scale, double *b, double *h,
+                          const double *e_ext, double e_scale, double *b, const double *damp_b,
+                          double *h,
                           const double *inv_mu_area, const double *inv_2area,
                           const double *bz_ext, const double *grad64, void *rec, bool rec_fp32,
                           double dt)
@@ -1159,12 +1165,12 @@ hipError_t launch_faraday(hipStream_t s, int nf, const int4 *tri_edge, const dou
     if (nf <= 0) return hipSuccess;
     if (rec_fp32)
         hipLaunchKernelGGL(k_faraday<float>, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
-                           tri_edge, e, e_ext, e_scale, b, h, inv_mu_area, inv_2area, bz_ext,
-                           grad64, static_cast<float *>(rec), dt);
+                           tri_edge, e, e_ext, e_scale, b, damp_b, h, inv_mu_area, inv_2area,
+                           bz_ext, grad64, static_cast<float *>(rec), dt);
     else
         hipLaunchKernelGGL(k_faraday<double>, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
-                           tri_edge, e, e_ext, e_scale, b, h, inv_mu_area, inv_2area, bz_ext,
-                           grad64, static_cast<double *>(rec), dt);
+                           tri_edge, e, e_ext, e_scale, b, damp_b, h, inv_mu_area, inv_2area,
+                           bz_ext, grad64, static_cast<double *>(rec), dt);
     return hipGetLastError();
 }
 

@@ -102,7 +102,8 @@ def lib():
                     "fetd_set_absorber": [P, P],
                     "fetd_set_ext_scale": [P, ctypes.c_double],
                     "fetd_probe_set": [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int64],
-                    "fetd_probe_get": [P, P, ctypes.c_int64, P]}
+                    "fetd_probe_get": [P, P, ctypes.c_int64, P],
+                    "fetd_fields_load": [P, P, P]}
         for name, args in optional.items():
             if hasattr(L, name):
                 getattr(L, name).argtypes = args
@@ -198,6 +199,12 @@ def fields_set(h, bz_ext=None, e_ext=None, e_affine=None):
 def set_absorber(h, sigma_tri):
     sg = None if sigma_tri is None else np.ascontiguousarray(sigma_tri, dtype=np.float64)
     _check(lib().fetd_set_absorber(h, _p(sg)), h)
+
+
+def fields_load(h, b=None, d=None):
+    bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+    dd = None if d is None else np.ascontiguousarray(d, dtype=np.float64)
+    _check(lib().fetd_fields_load(h, _p(bb), _p(dd)), h)
 
 
 def set_ext_scale(h, scale):
@@ -343,6 +350,9 @@ class Sim:
 
     def set_ext_scale(self, scale):
         set_ext_scale(self.h, scale)
+
+    def fields_load(self, b=None, d=None):
+        fields_load(self.h, b, d)
 
     def probe_set(self, xy, every=1, max_samples=1):
         self._probe_n = 0 if xy is None else np.asarray(xy).reshape(-1, 2).shape[0]

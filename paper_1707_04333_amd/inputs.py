@@ -623,3 +623,32 @@ def large_run(n_side: int = 708, n_particles: int = 128_000_000, grade: float = 
                     bz_ext=B0, spai_level=1,
                     extra={"omega_c": wc, "omega_p": wp, "sigma_tri": sigma, "theta": theta,
                            "h_min": h_min})
+
+
+def wave_channel(nx: int = 161, ny: int = 6, length: float = 0.8, layer: float = 0.2,
+                 sigma_dt: float = 0.1, pulse_width: float = 0.03, b_peak: float = 1e-3,
+                 seed: int = MESH_SEED) -> Workload:
+    """Field-only absorbing-layer workload: the channel [0, length] x [0, W),
+    periodic in y (W = ny cells of the x spacing h = length/(nx - 1)), PEC
+    at x = 0 and x = length, with absorbing layers of width ``layer`` at
+    both ends whose conductivity rises as (depth/layer)^3 to sigma_max,
+    sigma_max dt / eps0 = ``sigma_dt``; dt = 0.2 h/c.  Initial state: a
+    Gaussian B_z pulse of peak ``b_peak`` [T] and 1/e half width
+    ``pulse_width`` at the channel's centre (face fluxes b_f = B_z(centroid)
+    A_f, d = 0), which splits into two halves running in -x and +x; after
+    ``extra['steps_return']`` steps a wave reflected at either end would be
+    back in the central region."""
+    h = length / (nx - 1)
+    width = ny * h
+    mesh = grid_mesh(nx, ny, length, width, periodic_y=True, seed=seed)
+    dt = 0.2 * h / C_LIGHT
+    cen = mesh.centroids()
+    depth = np.maximum(0.0, np.maximum(layer - cen[:, 0], cen[:, 0] - (length - layer)))
+    sigma = (sigma_dt * EPS0 / dt) * (depth / layer) ** 3
+    b0 = b_peak * np.exp(-((cen[:, 0] - 0.5 * length) / pulse_width) ** 2) * mesh.tri_area()
+    # half-way to the wall, into the layer and back, plus a quarter of the centre
+    travel = (0.5 * length - layer) + 2.0 * layer + 0.25 * (length - 2.0 * layer)
+    steps = int(round(travel / (C_LIGHT * dt)))
+    return Workload("wave_channel", mesh, [], dt, steps, "boris", "fp64", spai_level=1,
+                    extra={"sigma_tri": sigma, "b0": b0, "layer": layer, "length": length,
+                           "width": width, "steps_return": steps})

@@ -255,7 +255,9 @@ def test_locate_matches_input_generator():
 def test_batched_runs_match_separate_runs(oracle_lib, use_graph):
     """Several uneven pair-plasma runs advanced by the batched launches
     (with and without graph replay, across re-sorts) agree with the same
-    runs stepped one by one, and one of them with the oracle."""
+    runs stepped one by one, and one of them with the oracle.  Between the
+    two batch calls one member gets an absorbing layer: the batch takes it
+    up (it rebuilds its descriptors)."""
     fp = _fp()
     specs = [(12, 0.02, 3001, 0.3), (20, 0.03, 9000, 0.1), (9, 0.015, 1500, 1.0)]
     wls = [I.pair_plasma(n_side=n, length=L, n_pairs=p, theta=t, steps=40, precision="fp64")
@@ -264,9 +266,15 @@ def test_batched_runs_match_separate_runs(oracle_lib, use_graph):
     single = [_gpu_sim(w, 1, resort_every=6) for w in wls]
     b = fp.Batch(batched, use_graph=use_graph)
     b.step(15, "vay")
+    for s in single:
+        s.step(15, "vay")
+    cx = wls[0].mesh.centroids()[:, 0]
+    sigma = np.where(cx < 0.2 * specs[0][1], 0.3 * I.EPS0 / wls[0].dt, 0.0)
+    batched[0].set_absorber(sigma)
+    single[0].set_absorber(sigma)
     b.step(14, "vay")
     for s in single:
-        s.step(29, "vay")
+        s.step(14, "vay")
     for gb, gs in zip(batched, single):
         for si in range(2):
             pb, ps = gb.particles(si), gs.particles(si)
@@ -287,12 +295,14 @@ def test_batched_runs_match_separate_runs(oracle_lib, use_graph):
 
 
 def test_graded_absorbing_hc_parity(oracle_lib):
-    """Graded mesh (10:1 spacing), PEC walls with an absorbing layer, beam
-    plus thermal electrons, Higuera-Cary: FP64 parity with the oracle."""
+    """Graded mesh (10:1 spacing), PEC walls with a matched absorbing layer
+    (electric and magnetic losses), beam plus thermal electrons,
+    Higuera-Cary: FP64 parity with the oracle."""
     w = I.large_run(n_side=60, n_particles=20_000, precision="fp64")
     osim = _oracle_sim(oracle_lib, w, 1)
-    damp, keep = oracle_lib.absorber_damp(osim.T, w.extra["sigma_tri"], w.dt, I.EPS0)
+    damp, damp_b, keep = oracle_lib.absorber_damp(osim.T, w.extra["sigma_tri"], w.dt, I.EPS0)
     osim.damp = np.ascontiguousarray(damp)
+    osim.damp_b = np.ascontiguousarray(damp_b)
     g = _gpu_sim(w, 1)
     osim.step(40, "hc")
     g.step(40, "hc")
@@ -300,6 +310,65 @@ def test_graded_absorbing_hc_parity(oracle_lib):
     _compare_fields(osim, g, tol=1e-11)
     d = g.diagnostics()
     assert d["gauss_rel"] <= 1e-12 and d["n_lost"] == osim.lost
+    g.close()
+
+
+def test_matched_layer_wave_channel_parity(oracle_lib):
+    """Matched absorbing layer on a field-only run: a B_z pulse loaded with
+    fetd_fields_load leaves the channel through the layers; e, d, b after
+    700 steps match the oracle and the energy sent back into the centre is
+    below 1e-3 of the pulse's."""
+    w = I.wave_channel()
+    g = _gpu_sim(w, 1)
+    g.fields_load(b=w.extra["b0"])
+    osim = oracle_lib.OracleSim(w.mesh, w.dt, [], I.EPS0, I.MU0, I.C_LIGHT, spai_level=1)
+    damp, damp_b, _ = oracle_lib.absorber_damp(osim.T, w.extra["sigma_tri"], w.dt, I.EPS0)
+    osim.damp, osim.damp_b = np.ascontiguousarray(damp), np.ascontiguousarray(damp_b)
+    osim.b = np.ascontiguousarray(w.extra["b0"], dtype=np.float64).copy()
+    E0 = sum(osim.energies()[:2])
+    n = w.extra["steps_return"]
+    osim.step(n)
+    g.step(n, "boris")
+    # the fields have decayed by ~1e-3 in amplitude: compare against the
+    # pulse's own scale
+    for name, ref, scale in (("b", osim.b, np.abs(w.extra["b0"]).max()),
+                             ("d", osim.d, None), ("e", osim.e, None)):
+        got = g.field(name)
+        s = scale if scale is not None else np.abs(ref).max() * 1e3
+        assert np.abs(got - ref).max() <= 1e-12 * s, name
+    cx = w.mesh.centroids()[:, 0]
+    L, lay = w.extra["length"], w.extra["layer"]
+    cf = (cx > lay) & (cx < L - lay)
+    gb = g.field("b")
+    WB = 0.5 * np.sum(gb[cf] ** 2 / (I.MU0 * osim.T.area[cf]))
+    assert WB / E0 < 1e-3
+    g.close()
+
+
+def test_fields_load_round_trip(oracle_lib):
+    """fetd_fields_load: the loaded b and d read back unchanged (d zero on
+    wall edges) and e = M~ d matches the oracle's approximate inverse."""
+    w = I.cyclotron()
+    g = _gpu_sim(w, 2)
+    osim = _oracle_sim(oracle_lib, w, 2)
+    rng = np.random.default_rng(21)
+    b = rng.normal(size=w.mesh.n_tris) * 1e-6
+    d = rng.normal(size=osim.T.ne) * 1e-9
+    g.fields_load(b=b, d=d)
+    free = osim.T.edge_free.astype(bool)
+    assert np.array_equal(g.field("b"), b)
+    assert np.array_equal(g.field("d"), np.where(free, d, 0.0))
+    from oracle import csr_matvec
+    ref = np.where(free, csr_matvec(*osim.Mt, np.where(free, d, 0.0)), 0.0)
+    assert np.abs(g.field("e") - ref).max() <= 1e-12 * np.abs(ref).max()
+    # a loaded state steps like the oracle's from the same state
+    osim.b, osim.d, osim.e = b.copy(), np.where(free, d, 0.0), ref.copy()
+    osim.step(10, "boris")
+    g.step(10, "boris")
+    _compare_particles(osim, g)
+    _compare_fields(osim, g, tol=1e-11)
+    with pytest.raises(_fp().FetdError):
+        g.fields_load(b=np.full(w.mesh.n_tris, np.nan))
     g.close()
 
 

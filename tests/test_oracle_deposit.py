@@ -171,9 +171,12 @@ def test_absorbing_layer_gauss_and_loss(oracle_lib):
                                    I.EPS0, I.MU0, I.C_LIGHT, spai_level=1, bz_ext=w.bz_ext)
         keep = sim.T.node_free.astype(bool)
         if lossy:
-            damp, keep = oracle_lib.absorber_damp(sim.T, w.extra["sigma_tri"], w.dt, I.EPS0)
+            damp, damp_b, keep = oracle_lib.absorber_damp(sim.T, w.extra["sigma_tri"], w.dt,
+                                                          I.EPS0)
             sim.damp = np.ascontiguousarray(damp)
+            sim.damp_b = np.ascontiguousarray(damp_b)
             assert damp.min() < 1.0 and damp.max() == 1.0
+            assert damp_b.min() < 1.0 and damp_b.max() == 1.0
         q0, s0 = sim.charge(), sim.T.divergence(sim.d)
         sim.step(200, "hc")
         q, s = sim.charge(), sim.T.divergence(sim.d)

@@ -136,7 +136,7 @@ def test_curl_of_gradient_is_zero(oracle_lib):
     out = np.empty(T.nf)
     import ctypes
     oracle_lib.lib().o_faraday(ctypes.byref(sim.ms), oracle_lib._p(sim.b), oracle_lib._p(e),
-                               1.0, oracle_lib._p(out))
+                               1.0, None, oracle_lib._p(out))
     assert np.abs(out).max() <= 1e-14 * np.abs(phi).max()
 
 
