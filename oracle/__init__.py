@@ -30,12 +30,14 @@ PUSHERS = {"boris": BORIS, "boris_tan": BORIS_TAN, "vay": VAY, "hc": HC}
 
 
 def build(force: bool = True) -> str:
-    """Compile fetd_oracle.c into liboracle.so (plain C, FP64, no FMA)."""
-    src = os.path.join(_HERE, "fetd_oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+    """Compile fetd_oracle.c (triangles) and fetd3_oracle.c (tetrahedra)
+    into liboracle.so (plain C, FP64, no FMA)."""
+    srcs = [os.path.join(_HERE, "fetd_oracle.c"), os.path.join(_HERE, "fetd3_oracle.c")]
+    newest = max(os.path.getmtime(s) for s in srcs)
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < newest:
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+                               "-fPIC", "-shared", "-o", tmp, *srcs, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
