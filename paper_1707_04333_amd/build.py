@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfetdpic.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["fetd_kernels.hip", "fetd_host.cpp"]
+SOURCES = ["fetd_kernels.hip", "fetd_host.cpp", "fetd_sparse.cpp", "fetd3_kernels.hip",
+           "fetd3_host.cpp"]
 ARCH = os.environ.get("FETD_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,0 +1,582 @@
+// HIP kernels (gfx950) of the tetrahedral FETD-PIC path, FP64:
+//   k3_faraday    b^{n+1/2} = b^{n-1/2} - dt C e^n and the face average
+//                 (b^{n+1/2} + b^{n-1/2})/2 (Sec. II.A, eq. semi.dis.curl.1)
+//   k3_record     per-tetrahedron gather record: E = sum l_n V_n from the
+//                 Whitney 1-forms of the six edges, B = sum l_n U_n from the
+//                 Whitney 2-forms of the four faces (Sec. II.B)
+//   k3_particles  gather, push (Sec. II.C, four pushers), move with face
+//                 crossings and the charge-conserving W1 deposit of every
+//                 piece on its six edges (Sec. II.D, eq. I.assign)
+//   k3_hnu, k3_ampere, k3_spmv   h = [*mu^-1] b, d += dt (C^T h - i),
+//                 e = M~ d (Sec. II.A, eq. semi.dis.curl.2 in the d form)
+//   k3_sort_*     counting sort of the particles by tetrahedron
+#include "fetd3_internal.h"
+
+namespace fetd3 {
+namespace {
+
+__device__ __forceinline__ void atomic_add_f64(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+inline unsigned grid_for(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+// value of a[i] for a runtime i in 0..3 without dynamic indexing
+__device__ __forceinline__ double pick4(const double (&a)[4], int i)
+{
+    return i == 0 ? a[0] : i == 1 ? a[1] : i == 2 ? a[2] : a[3];
+}
+
+__device__ __forceinline__ void put4(double (&a)[4], int i, double v)
+{
+    a[0] = i == 0 ? v : a[0];
+    a[1] = i == 1 ? v : a[1];
+    a[2] = i == 2 ? v : a[2];
+    a[3] = i == 3 ? v : a[3];
+}
+
+// The four barycentrics from the stored triple of slot r.
+__device__ __forceinline__ void unpack_lambda(int r, double s0, double s1, double s2,
+                                              double (&L)[4])
+{
+    const double lr = ((1.0 - s0) - s1) - s2;
+    L[0] = L[1] = L[2] = L[3] = 0.0;
+    put4(L, r, lr);
+    put4(L, (r + 1) & 3, s0);
+    put4(L, (r + 2) & 3, s1);
+    put4(L, (r + 3) & 3, s2);
+}
+
+__global__ __launch_bounds__(256) void k3_faraday(int nf, const int4 *__restrict__ face_edge,
+                                                  const double *__restrict__ e,
+                                                  double *__restrict__ b,
+                                                  double *__restrict__ bavg, double dt)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const int4 fe = face_edge[f];
+    // C row: +1 on edges (i,j) and (j,l), -1 on (i,l) (bits of fe.w)
+    const double c0 = (fe.w & 1) ? -e[fe.x] : e[fe.x];
+    const double c1 = (fe.w & 2) ? -e[fe.y] : e[fe.y];
+    const double c2 = (fe.w & 4) ? -e[fe.z] : e[fe.z];
+    const double bo = b[f];
+    const double bn = bo - dt * ((c0 + c1) + c2);
+    b[f] = bn;
+    bavg[f] = 0.5 * (bn + bo);
+}
+
+__global__ __launch_bounds__(256) void k3_record(int nt, Mesh3 m, const double *__restrict__ e,
+                                                 const double *__restrict__ e_ext,
+                                                 const double *__restrict__ bavg,
+                                                 double *__restrict__ rec)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int32_t *te = m.tet_edge + 8 * size_t(t);
+    const int bits = te[6];
+    double g[12];
+    for (int i = 0; i < 12; ++i) g[i] = m.grad[12 * size_t(t) + i];
+    double V[12], U[12];
+    for (int i = 0; i < 12; ++i) V[i] = U[i] = 0.0;
+    // E = sum_k s_k e_k (l_a grad l_b - l_b grad l_a) = sum_n l_n V_n
+    constexpr int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double dof = e[te[k]];
+        if (e_ext) dof = dof + e_ext[te[k]];
+        const double tk = ((bits >> k) & 1) ? -dof : dof;
+        const int a = ea[k], b = eb[k];
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            V[3 * a + x] += tk * g[3 * b + x];
+            V[3 * b + x] -= tk * g[3 * a + x];
+        }
+    }
+    // B = sum_k p_k b_k 2 (l_p X_qr + l_q X_rp + l_r X_pq) = sum_n l_n U_n
+    const int4 tf = m.tet_face[t];
+    const int fid[4] = {tf.x, tf.y, tf.z, tf.w};
+    constexpr int fp[4] = {1, 0, 0, 0}, fq[4] = {2, 2, 1, 1}, fr[4] = {3, 3, 3, 2};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double bk = bavg[fid[k]];
+        const double beta = 2.0 * (((bits >> (8 + k)) & 1) ? -bk : bk);
+        const int p = fp[k], q = fq[k], r = fr[k];
+        const double *gp = g + 3 * p, *gq = g + 3 * q, *gr = g + 3 * r;
+        const double xqr[3] = {gq[1] * gr[2] - gq[2] * gr[1], gq[2] * gr[0] - gq[0] * gr[2],
+                               gq[0] * gr[1] - gq[1] * gr[0]};
+        const double xrp[3] = {gr[1] * gp[2] - gr[2] * gp[1], gr[2] * gp[0] - gr[0] * gp[2],
+                               gr[0] * gp[1] - gr[1] * gp[0]};
+        const double xpq[3] = {gp[1] * gq[2] - gp[2] * gq[1], gp[2] * gq[0] - gp[0] * gq[2],
+                               gp[0] * gq[1] - gp[1] * gq[0]};
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            U[3 * p + x] += beta * xqr[x];
+            U[3 * q + x] += beta * xrp[x];
+            U[3 * r + x] += beta * xpq[x];
+        }
+    }
+    double *o = rec + size_t(kRec) * t;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        o[i] = V[i];
+        o[12 + i] = U[i];
+    }
+}
+
+// ---------------------------------------------------------------------
+// Pushers (Sec. II.C) for general 3-vectors; eps = alpha E, beta = alpha B.
+// ---------------------------------------------------------------------
+struct V3 {
+    double x, y, z;
+};
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b)
+{
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// gamma of a momentum: sqrt(1 + |u|^2 / c^2)
+__device__ __forceinline__ double gam(V3 u, double inv_c2) { return sqrt(1.0 + dot(u, u) * inv_c2); }
+
+template <int P>
+__device__ __forceinline__ V3 push3(V3 u, V3 eps, V3 beta, double c, double inv_c2)
+{
+    if constexpr (P == 2) {
+        // Vay: u' = u + 2 eps + v x beta; gamma+ from the implicit midpoint
+        // equation; u = s [u' + (u'.t) t + u' x t], t = beta/gamma+.
+        const double g = gam(u, inv_c2);
+        const V3 v = (1.0 / g) * u;
+        const V3 upr = (u + eps + cross(v, beta)) + eps;
+        const double gp = gam(upr, inv_c2);
+        const double bb = dot(beta, beta);
+        const double sig = gp * gp - bb;
+        const double us = dot(upr, beta) / c;
+        const double gn = sqrt(0.5 * (sig + sqrt(sig * sig + 4.0 * (bb + us * us))));
+        const V3 t = (1.0 / gn) * beta;
+        const double sv = 1.0 / (1.0 + dot(t, t));
+        return sv * ((upr + dot(upr, t) * t) + cross(upr, t));
+    } else {
+        const V3 um = u + eps;
+        double gbar;
+        if constexpr (P == 3) {
+            // Higuera-Cary: gamma of the midpoint momentum
+            const double bb = dot(beta, beta);
+            const double gm = gam(um, inv_c2);
+            const double sig = gm * gm - bb;
+            const double w = dot(beta, um) / c;
+            gbar = sqrt(0.5 * (sig + sqrt(sig * sig + 4.0 * (bb + w * w))));
+        } else {
+            gbar = gam(um, inv_c2);
+        }
+        V3 t;
+        if constexpr (P == 1) {
+            // Boris with the tangent correction of the rotation angle
+            const double bm = sqrt(dot(beta, beta));
+            t = bm > 0.0 ? (tan(bm / gbar) / bm) * beta : V3{0.0, 0.0, 0.0};
+        } else {
+            t = (1.0 / gbar) * beta;
+        }
+        const V3 s = (2.0 / (1.0 + dot(t, t))) * t;
+        const V3 up = um + cross(um, t);
+        return (um + cross(up, s)) + eps;
+    }
+}
+
+// Current of one piece inside tetrahedron t from Ls to Lf: i_e += sign
+// (Q/dt) (l_a^s l_b^f - l_a^f l_b^s) on each local edge (a, b).
+__device__ __forceinline__ void deposit_piece(const int32_t *__restrict__ te, int bits,
+                                              const double (&Ls)[4], const double (&Lf)[4],
+                                              double qdt, double *__restrict__ cur)
+{
+    constexpr int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int a = ea[k], b = eb[k];
+        const double w = Ls[a] * Lf[b] - Lf[a] * Ls[b];
+        const double sq = ((bits >> k) & 1) ? -qdt : qdt;
+        atomic_add_f64(cur + te[k], sq * w);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    unsigned long long pieces = 0, lost_here = 0;
+    if (p < a.n) {
+        const uint32_t key = a.key[p];
+        if (key != kLost) {
+            int t = int(key & kTetMask);
+            int r = int(key >> 30);
+            const int64_t n = a.stride;
+            double L[4];
+            unpack_lambda(r, a.lam[p], a.lam[n + p], a.lam[2 * n + p], L);
+            const double *rc = a.rec + size_t(kRec) * t;
+            V3 E{0.0, 0.0, 0.0}, B{0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                E = E + L[k] * V3{rc[3 * k], rc[3 * k + 1], rc[3 * k + 2]};
+                B = B + L[k] * V3{rc[12 + 3 * k], rc[13 + 3 * k], rc[14 + 3 * k]};
+            }
+            if (a.b_ext) B = B + V3{a.b_ext[3 * t], a.b_ext[3 * t + 1], a.b_ext[3 * t + 2]};
+            const V3 u0{a.u[p], a.u[n + p], a.u[2 * n + p]};
+            const V3 u1 = push3<P>(u0, a.alpha * E, a.alpha * B, a.c, a.inv_c2);
+            const bool finite = isfinite(u1.x) && isfinite(u1.y) && isfinite(u1.z);
+            if (!finite) {
+                atomicOr(a.counters + 2, 2ull);
+                atomicMin(a.counters + 3, (unsigned long long)p);
+            }
+            int cap = finite ? a.cap : 0;  // a bad particle is left where it is
+            bool done = !finite;
+            a.u[p] = u1.x;
+            a.u[n + p] = u1.y;
+            a.u[2 * n + p] = u1.z;
+            const double g = gam(u1, a.inv_c2);
+            double rx = a.dt * u1.x / g, ry = a.dt * u1.y / g, rz = a.dt * u1.z / g;
+            int entry = -1;
+            for (int it = 0; it < cap; ++it) {
+                const double *G = m.grad + 12 * size_t(t);
+                const int32_t *te = m.tet_edge + 8 * size_t(t);
+                const int bits = te[6];
+                double dL[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    dL[k] = G[3 * k] * rx + G[3 * k + 1] * ry + G[3 * k + 2] * rz;
+                int ks = -1;
+                double ts = 0.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (k == entry || !(dL[k] < 0.0)) continue;
+                    const double tk = (L[k] > 0.0 ? L[k] : 0.0) / (-dL[k]);
+                    if (ks < 0 || tk < ts) {
+                        ks = k;
+                        ts = tk;
+                    }
+                }
+                double Lf[4];
+                ++pieces;
+                if (ks < 0 || ts >= 1.0) {
+                    const int i1 = (r + 1) & 3, i2 = (r + 2) & 3, i3 = (r + 3) & 3;
+                    const double f1 = pick4(L, i1) + pick4(dL, i1);
+                    const double f2 = pick4(L, i2) + pick4(dL, i2);
+                    const double f3 = pick4(L, i3) + pick4(dL, i3);
+                    unpack_lambda(r, f1, f2, f3, Lf);
+                    deposit_piece(te, bits, L, Lf, a.qdt, a.cur);
+                    a.key[p] = uint32_t(t) | (uint32_t(r) << 30);
+                    a.lam[p] = f1;
+                    a.lam[n + p] = f2;
+                    a.lam[2 * n + p] = f3;
+                    done = true;
+                    break;
+                }
+                const int kp = (ks + 1) & 3, kq = (ks + 2) & 3, kw = (ks + 3) & 3;
+                const double lp = pick4(L, kp) + ts * pick4(dL, kp);
+                const double lq = pick4(L, kq) + ts * pick4(dL, kq);
+                const double lw = (1.0 - lp) - lq;
+                Lf[0] = Lf[1] = Lf[2] = Lf[3] = 0.0;
+                put4(Lf, kp, lp);
+                put4(Lf, kq, lq);
+                put4(Lf, kw, lw);
+                deposit_piece(te, bits, L, Lf, a.qdt, a.cur);
+                const int4 nb4 = m.tet_nbr[t];
+                const int nb = ks == 0 ? nb4.x : ks == 1 ? nb4.y : ks == 2 ? nb4.z : nb4.w;
+                if (nb < 0) {
+                    // wall: removed after depositing up to it
+                    a.key[p] = kLost;
+                    ++lost_here;
+                    done = true;
+                    break;
+                }
+                const uint32_t mp = (m.tet_map[t] >> (8 * ks)) & 0xFFu;
+                const int np = int(mp & 3), nq = int((mp >> 2) & 3), nw = int((mp >> 4) & 3);
+                const int nk = int(mp >> 6);
+                L[0] = L[1] = L[2] = L[3] = 0.0;
+                put4(L, np, lp);
+                put4(L, nq, lq);
+                put4(L, nw, lw);
+                r = nw;
+                entry = nk;
+                t = nb;
+                const double sc = 1.0 - ts;
+                rx *= sc;
+                ry *= sc;
+                rz *= sc;
+            }
+            if (!done) {
+                atomicOr(a.counters + 2, 1ull);
+                atomicMin(a.counters + 3, (unsigned long long)p);
+            }
+        }
+    }
+    // block totals of pieces and removed particles
+    __shared__ unsigned long long s_pc[4], s_lc[4];
+    for (int off = 32; off > 0; off >>= 1) {
+        pieces += __shfl_down(pieces, off, 64);
+        lost_here += __shfl_down(lost_here, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_pc[wv] = pieces;
+        s_lc[wv] = lost_here;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long sp = 0, sl = 0;
+        for (int i = 0; i < int(blockDim.x >> 6); ++i) {
+            sp += s_pc[i];
+            sl += s_lc[i];
+        }
+        if (sp) atomicAdd(a.counters + 0, sp);
+        if (sl) atomicAdd(a.counters + 1, sl);
+    }
+}
+
+__global__ __launch_bounds__(256) void k3_hnu(int nf, const int32_t *__restrict__ ptr,
+                                              const int32_t *__restrict__ col,
+                                              const double *__restrict__ val,
+                                              const double *__restrict__ b, double *__restrict__ h)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    double acc = 0.0;
+    for (int j = ptr[f]; j < ptr[f + 1]; ++j) acc += val[j] * b[col[j]];
+    h[f] = acc;
+}
+
+// d += dt (C^T h - i) on free edges (C^T h summed over the edge's faces in
+// increasing face order; sign in bit 31 of ef_face), then the current is
+// kept for diagnostics and cleared.
+__global__ __launch_bounds__(256) void k3_ampere(int ne, const int32_t *__restrict__ ef_ptr,
+                                                 const int32_t *__restrict__ ef_face,
+                                                 const uint8_t *__restrict__ edge_free,
+                                                 const double *__restrict__ h,
+                                                 double *__restrict__ cur,
+                                                 double *__restrict__ cur_last,
+                                                 double *__restrict__ d, double dt)
+{
+    const int ed = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ed >= ne) return;
+    double acc = 0.0;
+    for (int j = ef_ptr[ed]; j < ef_ptr[ed + 1]; ++j) {
+        const int32_t v = ef_face[j];
+        const double hv = h[v & 0x7FFFFFFF];
+        acc = acc + (v < 0 ? -hv : hv);
+    }
+    const double i = cur[ed];
+    d[ed] = edge_free[ed] ? d[ed] + dt * (acc - i) : 0.0;
+    cur_last[ed] = i;
+    cur[ed] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k3_spmv(int ne, const int32_t *__restrict__ ptr,
+                                               const int32_t *__restrict__ col,
+                                               const double *__restrict__ val,
+                                               const uint8_t *__restrict__ edge_free,
+                                               const double *__restrict__ d,
+                                               double *__restrict__ e)
+{
+    const int ed = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ed >= ne) return;
+    double acc = 0.0;
+    if (edge_free[ed])
+        for (int j = ptr[ed]; j < ptr[ed + 1]; ++j) acc += val[j] * d[col[j]];
+    e[ed] = acc;
+}
+
+// Counting sort: histogram of live keys per tetrahedron ...
+__global__ __launch_bounds__(256) void k3_sort_count(int64_t n, const uint32_t *__restrict__ key,
+                                                     int32_t *__restrict__ counts)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t k = key[p];
+    if (k != kLost) atomicAdd(counts + (k & kTetMask), 1);
+}
+
+// ... exclusive scan of counts[0..nt] into cursor (one block of 1024) ...
+__global__ __launch_bounds__(1024) void k3_sort_scan(int n, const int32_t *__restrict__ counts,
+                                                     int32_t *__restrict__ cursor)
+{
+    __shared__ int32_t part[1024];
+    const int tid = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+    int32_t s = 0;
+    for (int i = lo; i < hi; ++i) s += counts[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int32_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int32_t run = part[tid] - s;
+    for (int i = lo; i < hi; ++i) {
+        cursor[i] = run;
+        run += counts[i];
+    }
+}
+
+// ... and scatter of every live particle to the next free place of its
+// tetrahedron (order within a tetrahedron is arbitrary).
+__global__ __launch_bounds__(256) void k3_sort_scatter(Sort3 a)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const uint32_t k = a.key_in[p];
+    if (k == kLost) return;
+    const int64_t q = atomicAdd(a.cursor + (k & kTetMask), 1);
+    a.key_out[q] = k;
+    a.pid_out[q] = a.pid_in[p];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a.lam_out[c * a.stride_out + q] = a.lam_in[c * a.stride_in + p];
+        a.u_out[c * a.stride_out + q] = a.u_in[c * a.stride_in + p];
+    }
+}
+
+__global__ __launch_bounds__(256) void k3_charge(int64_t n, const uint32_t *__restrict__ key,
+                                                 const double *__restrict__ lam, int64_t stride,
+                                                 const int4 *__restrict__ tet_node, double qw,
+                                                 double *__restrict__ q)
+{
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t k = key[p];
+    if (k == kLost) return;
+    double L[4];
+    unpack_lambda(int(k >> 30), lam[p], lam[stride + p], lam[2 * stride + p], L);
+    const int4 tn = tet_node[k & kTetMask];
+    atomic_add_f64(q + tn.x, qw * L[0]);
+    atomic_add_f64(q + tn.y, qw * L[1]);
+    atomic_add_f64(q + tn.z, qw * L[2]);
+    atomic_add_f64(q + tn.w, qw * L[3]);
+}
+
+__global__ __launch_bounds__(256) void k3_divd(int ne, const int2 *__restrict__ edge_nodes,
+                                               const double *__restrict__ d,
+                                               double *__restrict__ out)
+{
+    const int ed = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ed >= ne) return;
+    const int2 en = edge_nodes[ed];
+    atomic_add_f64(out + en.x, d[ed]);
+    atomic_add_f64(out + en.y, -d[ed]);
+}
+
+__global__ __launch_bounds__(256) void k3_divb(int nt, const int4 *__restrict__ tet_face,
+                                               const int32_t *__restrict__ fout_bits,
+                                               const double *__restrict__ b,
+                                               double *__restrict__ out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int4 f = tet_face[t];
+    const int bits = fout_bits[t];
+    const double v0 = (bits & 1) ? -b[f.x] : b[f.x];
+    const double v1 = (bits & 2) ? -b[f.y] : b[f.y];
+    const double v2 = (bits & 4) ? -b[f.z] : b[f.z];
+    const double v3 = (bits & 8) ? -b[f.w] : b[f.w];
+    out[t] = ((v0 + v1) + v2) + v3;
+}
+
+}  // namespace
+
+hipError_t launch3_faraday(hipStream_t s, int nf, const int4 *face_edge, const double *e,
+                           double *b, double *bavg, double dt)
+{
+    if (nf <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_faraday, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf, face_edge, e, b,
+                       bavg, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch3_record(hipStream_t s, int nt, const Mesh3 &m, const double *e,
+                          const double *e_ext, const double *bavg, double *rec)
+{
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_record, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, m, e, e_ext, bavg,
+                       rec);
+    return hipGetLastError();
+}
+
+hipError_t launch3_particles(hipStream_t s, const Mesh3 &m, const Step3 &a, int pusher)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid(grid_for(a.n, kBlock)), block(kBlock);
+    switch (pusher) {
+    case 0: hipLaunchKernelGGL(k3_particles<0>, grid, block, 0, s, m, a); break;
+    case 1: hipLaunchKernelGGL(k3_particles<1>, grid, block, 0, s, m, a); break;
+    case 2: hipLaunchKernelGGL(k3_particles<2>, grid, block, 0, s, m, a); break;
+    default: hipLaunchKernelGGL(k3_particles<3>, grid, block, 0, s, m, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch3_hnu(hipStream_t s, int nf, const int32_t *ptr, const int32_t *col,
+                       const double *val, const double *b, double *h)
+{
+    if (nf <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_hnu, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf, ptr, col, val, b, h);
+    return hipGetLastError();
+}
+
+hipError_t launch3_ampere(hipStream_t s, int ne, const int32_t *ef_ptr, const int32_t *ef_face,
+                          const uint8_t *edge_free, const double *h, double *cur,
+                          double *cur_last, double *d, double dt)
+{
+    if (ne <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_ampere, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, ef_ptr, ef_face,
+                       edge_free, h, cur, cur_last, d, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch3_spmv(hipStream_t s, int ne, const int32_t *ptr, const int32_t *col,
+                        const double *val, const uint8_t *edge_free, const double *d, double *e)
+{
+    if (ne <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_spmv, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, ptr, col, val,
+                       edge_free, d, e);
+    return hipGetLastError();
+}
+
+hipError_t launch3_sort(hipStream_t s, const Sort3 &a)
+{
+    if (a.n <= 0) return hipSuccess;
+    hipError_t e = hipMemsetAsync(a.counts, 0, sizeof(int32_t) * (size_t(a.nt) + 1), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k3_sort_count, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a.n, a.key_in,
+                       a.counts);
+    hipLaunchKernelGGL(k3_sort_scan, dim3(1), dim3(1024), 0, s, a.nt + 1, a.counts, a.cursor);
+    hipLaunchKernelGGL(k3_sort_scatter, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch3_charge(hipStream_t s, int64_t n, const uint32_t *key, const double *lam,
+                          int64_t stride, const int4 *tet_node, double qw, double *q)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_charge, dim3(grid_for(n, 256)), dim3(256), 0, s, n, key, lam, stride,
+                       tet_node, qw, q);
+    return hipGetLastError();
+}
+
+hipError_t launch3_divd(hipStream_t s, int ne, const int2 *edge_nodes, const double *d,
+                        double *out)
+{
+    if (ne <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_divd, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, edge_nodes, d, out);
+    return hipGetLastError();
+}
+
+hipError_t launch3_divb(hipStream_t s, int nt, const int4 *tet_face, const int32_t *fout_bits,
+                        const double *b, double *out)
+{
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_divb, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, tet_face, fout_bits,
+                       b, out);
+    return hipGetLastError();
+}
+
+}  // namespace fetd3

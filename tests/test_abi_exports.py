@@ -1,5 +1,5 @@
 """The C-ABI library loads and exports every entry point include/fetdpic.h
-declares (no compute calls: this runs without a GPU)."""
+and include/fetd3.h declare (no compute calls: this runs without a GPU)."""
 import ctypes
 import os
 import re
@@ -8,9 +8,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "fetdpic.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fetd_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(fetd3?_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -18,7 +23,9 @@ def test_header_declares_the_boundary():
     for name in ("fetd_mesh_create", "fetd_particles_load", "fetd_particles_load_bary",
                  "fetd_pic_step", "fetd_fields_get", "fetd_particles_get", "fetd_diagnostics",
                  "fetd_destroy", "fetd_last_error", "fetd_fields_set", "fetd_sync", "fetd_sort",
-                 "fetd_info_get"):
+                 "fetd_info_get", "fetd3_mesh_create", "fetd3_particles_load_bary",
+                 "fetd3_pic_step", "fetd3_fields_get", "fetd3_particles_get",
+                 "fetd3_diagnostics", "fetd3_destroy"):
         assert name in syms
 
 
@@ -39,3 +46,14 @@ def test_argument_errors_without_device():
     assert b"out is NULL" in L.fetd_last_error(None)
     assert L.fetd_pic_step(None, 1, 0) == fetdpic.FETD_E_ARG
     L.fetd_destroy(None)
+
+
+def test_tet_argument_errors_without_device():
+    from paper_1707_04333_amd import fetd3
+    L = fetd3.lib()
+    out = ctypes.c_void_p()
+    assert L.fetd3_mesh_create(None, None, ctypes.byref(out)) == -1
+    assert L.fetd3_mesh_create(None, None, None) == -1
+    assert b"out is NULL" in L.fetd3_last_error(None)
+    assert L.fetd3_pic_step(None, 1, 0) == -1
+    L.fetd3_destroy(None)
