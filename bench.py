@@ -18,7 +18,7 @@ timings of its launches inside the timed region, and the FP64 CPU oracle on
 a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload pair|large|boosted|cyclotron]
+                       [--workload pair|large|boosted|cyclotron|bernstein|synchro|tet]
 """
 import argparse
 import hashlib
@@ -226,6 +226,87 @@ def run_bernstein(args):
             "band1_frac_within_0.05": float(np.mean(dev < 0.05))}
 
 
+def tet_particle_launch_bytes(n_particles, nt, ne):
+    """Algorithmic bytes of one tetrahedral particle launch (FP64): every
+    particle reads and writes its key (4 B), stored barycentric triple and
+    momentum (3 + 3 doubles); every tetrahedron's gather record (24
+    doubles), gradients (12 doubles), edge table (32 B), neighbour table
+    (16 B) and node map (4 B) are read once; every edge's current is read
+    and written once."""
+    return n_particles * 2 * (4 + 6 * 8) + nt * (24 * 8 + 12 * 8 + 32 + 16 + 4) + ne * 16
+
+
+def run_tet(args):
+    """The tetrahedral path on a triply periodic pair plasma: 48^3 Kuhn cells
+    (663,552 tetrahedra), 8M electrons + 8M positrons (24 per tetrahedron),
+    3-D Maxwell-Juttner momenta at theta = 0.1, B0 = 1 T along z,
+    omega_c/omega_p = 2, FP64 throughout, Boris, sorted every 20 steps."""
+    from paper_1707_04333_amd import fetd3
+    from paper_1707_04333_amd import inputs3 as J
+    log("generating the tetrahedral pair plasma")
+    w = J.tet_pair_plasma(n_pairs=args.pairs)
+    n_p = w.n_particles
+    species_n = [s.n for s in w.species]
+    sim = fetd3.from_workload3(w, resort_every=20)
+    nt, ne = w.mesh.n_tets, None
+    sim.step(args.warmup, "boris")
+    sim.sync()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    sim.step(args.steps, "boris")
+    sim.sync()
+    el = time.perf_counter() - t0
+    stages, launches = sim.stage_times()
+    sim.profile(False)
+    d = sim.diagnostics()
+    ne = d["n_edges"]
+    sim.close()
+    per_launch = float(np.mean([tet_particle_launch_bytes(n, nt, ne) for n in species_n]))
+    avg_s = stages["particles"] / 1e3 / max(launches, 1)
+    achieved = per_launch / avg_s / 1e9
+    out = {"metric": METRIC, "value": n_p * args.steps / el, "unit": "particle-steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "tet_pair_plasma", "n_tets": nt, "n_edges": ne,
+                      "n_faces": d["n_faces"], "n_particles": n_p, "theta": w.extra["theta"],
+                      "pusher": "boris", "precision": "fp64", "resort_every": 20,
+                      "spai_level": 1},
+           "roofline": {"bound": "hbm", "kernel": "k3_particles", "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": None, "avg_launch_ms": avg_s * 1e3,
+                        "algorithmic_bytes_per_launch": per_launch},
+           "stage_ms_per_step": {k: v / args.steps for k, v in stages.items()},
+           "gauss_rel": d["gauss_rel"], "divb_rel": d["divb_rel"],
+           "pieces_per_particle_step": d["n_segments"] / (n_p * (args.steps + args.warmup))}
+    del w
+    if not args.no_cpu:
+        log("timing the tetrahedral CPU oracle on a sample")
+        out["cpu_baseline"] = tet_cpu_baseline(n_p)
+    return out
+
+
+def tet_cpu_baseline(n_full, sample_pairs=100_000, sample_steps=10):
+    """The FP64 tetrahedral oracle on the same mesh with a bounded sample."""
+    from oracle import tet as O3
+    from paper_1707_04333_amd import inputs as I
+    from paper_1707_04333_amd import inputs3 as J
+    w = J.tet_pair_plasma(n_pairs=sample_pairs)
+    sp = [(s.q, s.m, s.w, s.tri, s.lam, s.u) for s in w.species]
+    osim = O3.OracleSim3(w.mesh, w.dt, sp, I.EPS0, I.MU0, I.C_LIGHT, spai_level=1,
+                         b_ext=w.extra["b_ext"])
+    osim.step(1)
+    t0 = time.perf_counter()
+    osim.step(sample_steps)
+    el = time.perf_counter() - t0
+    n = sum(s.n for s in osim.species)
+    return {"value": n * sample_steps / el, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"same mesh ({w.mesh.n_tets} tetrahedra, FP64 field update), {n} of the "
+                       f"{n_full} particles, {sample_steps} steps after 1 warm-up step, "
+                       f"single-threaded FP64 C oracle; {el:.1f} s")}
+
+
 def make_workload(name, args, precision):
     from paper_1707_04333_amd import inputs as I
     if name == "pair":
@@ -277,6 +358,9 @@ def main():
         return
     if args.workload == "bernstein":
         print(json.dumps(run_bernstein(args)))
+        return
+    if args.workload == "tet":
+        print(json.dumps(run_tet(args)))
         return
     log(f"generating workload {args.workload}")
     w = make_workload(args.workload, args, "mixed")

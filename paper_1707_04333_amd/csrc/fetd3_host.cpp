@@ -65,6 +65,9 @@ struct fetd3_sim {
         face_node;
     std::vector<int8_t> tet_esign, tet_fpar, tet_fout, face_esign;
     std::vector<uint8_t> tet_map, edge_free, node_free;
+    // device edge numbering: first appearance along the tetrahedron order
+    std::vector<int32_t> edev, ecan;  // canonical -> device, device -> canonical
+    std::vector<uint32_t> tet_ebase;  // edges first met before tetrahedron t
     std::vector<double> grad, vol;
     Csr meps, mnu, mt;
     double spai_fro = 0;
@@ -73,13 +76,16 @@ struct fetd3_sim {
     std::vector<void *> allocs;
     int32_t *d_tet_edge = nullptr, *d_fout = nullptr;
     int4 *d_tet_face = nullptr, *d_tet_nbr = nullptr, *d_tet_node = nullptr, *d_face_edge = nullptr;
-    uint32_t *d_tet_map = nullptr;
+    uint32_t *d_tet_map = nullptr, *d_tet_ebase = nullptr;
     double *d_grad = nullptr;
     int2 *d_edge_nodes = nullptr;
     uint8_t *d_edge_free = nullptr;
-    int32_t *d_nu_ptr = nullptr, *d_nu_col = nullptr, *d_ef_ptr = nullptr, *d_ef_face = nullptr;
-    int32_t *d_mt_ptr = nullptr, *d_mt_col = nullptr;
+    int32_t *d_ef_ptr = nullptr, *d_ef_face = nullptr;
+    // [*mu^-1] (faces) and M~ (device edge order) in sliced-ELL form
+    int32_t *d_nu_sptr = nullptr, *d_nu_sw = nullptr, *d_nu_col = nullptr;
+    int32_t *d_mt_sptr = nullptr, *d_mt_sw = nullptr, *d_mt_col = nullptr;
     double *d_nu_val = nullptr, *d_mt_val = nullptr;
+    int32_t *d_chunk_sums = nullptr;
     double *d_b = nullptr, *d_bavg = nullptr, *d_h = nullptr, *d_d = nullptr, *d_e = nullptr;
     double *d_cur = nullptr, *d_cur_last = nullptr, *d_rec = nullptr;
     double *d_b_ext = nullptr, *d_e_ext = nullptr;
@@ -162,6 +168,24 @@ fetd_status download3(fetd3_sim *s, void *dst, const void *src, size_t bytes)
     hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "download");
+    return FETD_OK;
+}
+
+// Edge arrays cross the boundary in canonical order and live on the device
+// in device order.
+fetd_status upload_edges3(fetd3_sim *s, double **dst, const double *canon)
+{
+    std::vector<double> tmp(s->ne);
+    for (int r = 0; r < s->ne; ++r) tmp[r] = canon[s->ecan[r]];
+    return upload3(s, dst, tmp.data(), tmp.size());
+}
+
+fetd_status download_edges3(fetd3_sim *s, double *canon, const double *src)
+{
+    std::vector<double> tmp(s->ne);
+    fetd_status st = download3(s, tmp.data(), src, 8 * tmp.size());
+    if (st) return st;
+    for (int r = 0; r < s->ne; ++r) canon[s->ecan[r]] = tmp[r];
     return FETD_OK;
 }
 
@@ -425,17 +449,82 @@ void assemble_hodges3(fetd3_sim *s)
     csr_from_rows(rf, s->mnu);
 }
 
+// Sliced-ELL copy of a CSR matrix (rows in the given order, entries in
+// their stored order; padding value 0 with the row itself as column).
+struct SellHost {
+    std::vector<int32_t> sptr, sw, col;
+    std::vector<double> val;
+};
+
+SellHost to_sell(const std::vector<int32_t> &ptr, const std::vector<int32_t> &col,
+                 const std::vector<double> &val)
+{
+    SellHost h;
+    const int n = int(ptr.size()) - 1;
+    const int ns = (n + 63) / 64;
+    h.sptr.resize(ns);
+    h.sw.resize(ns);
+    int64_t off = 0;
+    for (int sl = 0; sl < ns; ++sl) {
+        int w = 0;
+        for (int r = 64 * sl; r < std::min(n, 64 * sl + 64); ++r) w = std::max(w, ptr[r + 1] - ptr[r]);
+        h.sptr[sl] = int32_t(off);
+        h.sw[sl] = w;
+        off += int64_t(w) * 64;
+    }
+    h.col.assign(off, 0);
+    h.val.assign(off, 0.0);
+    for (int sl = 0; sl < ns; ++sl)
+        for (int lane = 0; lane < 64; ++lane) {
+            const int r = 64 * sl + lane;
+            for (int j = 0; j < h.sw[sl]; ++j) {
+                const int64_t q = h.sptr[sl] + 64 * j + lane;
+                if (r < n && j < ptr[r + 1] - ptr[r]) {
+                    h.col[q] = col[ptr[r] + j];
+                    h.val[q] = val[ptr[r] + j];
+                } else {
+                    h.col[q] = r < n ? r : 0;
+                }
+            }
+        }
+    return h;
+}
+
+// Device edge numbering by first appearance along the tetrahedron order:
+// the edges of a run of consecutive tetrahedra get nearby ids, so one
+// particle block's currents fall into a short window of ids.
+void number_edges3(fetd3_sim *s)
+{
+    s->edev.assign(s->ne, -1);
+    s->ecan.assign(s->ne, -1);
+    s->tet_ebase.assign(s->nt, 0);
+    int32_t next = 0;
+    for (int t = 0; t < s->nt; ++t) {
+        s->tet_ebase[t] = uint32_t(next);
+        for (int k = 0; k < 6; ++k) {
+            const int e = s->tet_edge[6 * t + k];
+            if (s->edev[e] < 0) {
+                s->edev[e] = next;
+                s->ecan[next] = e;
+                ++next;
+            }
+        }
+    }
+}
+
 fetd_status upload_mesh3(fetd3_sim *s)
 {
     fetd_status st;
     const int nt = s->nt, nf = s->nf, ne = s->ne;
+    number_edges3(s);
+    const std::vector<int32_t> &edev = s->edev, &ecan = s->ecan;
     std::vector<int32_t> te(8 * size_t(nt), 0), fout(nt, 0);
     std::vector<int4> tf(nt), tn(nt), tnode(nt), fe(nf);
     std::vector<uint32_t> tm(nt, 0);
     for (int t = 0; t < nt; ++t) {
         int bits = 0;
         for (int k = 0; k < 6; ++k) {
-            te[8 * size_t(t) + k] = s->tet_edge[6 * t + k];
+            te[8 * size_t(t) + k] = edev[s->tet_edge[6 * t + k]];
             if (s->tet_esign[6 * t + k] < 0) bits |= 1 << k;
         }
         for (int k = 0; k < 4; ++k) {
@@ -463,24 +552,43 @@ fetd_status upload_mesh3(fetd3_sim *s)
         int bits = 0;
         for (int j = 0; j < 3; ++j)
             if (s->face_esign[3 * f + j] < 0) bits |= 1 << j;
-        fe[f] = make_int4(s->face_edge[3 * f], s->face_edge[3 * f + 1], s->face_edge[3 * f + 2], bits);
+        fe[f] = make_int4(edev[s->face_edge[3 * f]], edev[s->face_edge[3 * f + 1]],
+                          edev[s->face_edge[3 * f + 2]], bits);
     }
-    // edge -> faces (C^T), faces in increasing order, sign in bit 31
+    // edge -> faces (C^T) in device edge order, faces in increasing order,
+    // sign in bit 31
     std::vector<int32_t> efp(ne + 1, 0), eff;
     for (int f = 0; f < nf; ++f)
-        for (int j = 0; j < 3; ++j) ++efp[s->face_edge[3 * f + j] + 1];
+        for (int j = 0; j < 3; ++j) ++efp[edev[s->face_edge[3 * f + j]] + 1];
     for (int e = 0; e < ne; ++e) efp[e + 1] += efp[e];
     eff.resize(efp[ne]);
     {
         std::vector<int32_t> pos(efp.begin(), efp.end() - 1);
         for (int f = 0; f < nf; ++f)
             for (int j = 0; j < 3; ++j) {
-                const int e = s->face_edge[3 * f + j];
-                eff[pos[e]++] = s->face_esign[3 * f + j] < 0 ? int32_t(uint32_t(f) | 0x80000000u) : f;
+                const int r = edev[s->face_edge[3 * f + j]];
+                eff[pos[r]++] = s->face_esign[3 * f + j] < 0 ? int32_t(uint32_t(f) | 0x80000000u) : f;
             }
     }
     std::vector<int2> en(ne);
-    for (int e = 0; e < ne; ++e) en[e] = make_int2(s->edge_lo[e], s->edge_hi[e]);
+    std::vector<uint8_t> efree(ne);
+    for (int r = 0; r < ne; ++r) {
+        en[r] = make_int2(s->edge_lo[ecan[r]], s->edge_hi[ecan[r]]);
+        efree[r] = s->edge_free[ecan[r]];
+    }
+    // M~ in device order; each row keeps the canonical order of its entries
+    std::vector<int32_t> mtp(ne + 1, 0), mtc;
+    std::vector<double> mtv;
+    mtc.reserve(s->mt.col.size());
+    mtv.reserve(s->mt.val.size());
+    for (int r = 0; r < ne; ++r) {
+        const int e = ecan[r];
+        for (int q = s->mt.ptr[e]; q < s->mt.ptr[e + 1]; ++q) {
+            mtc.push_back(edev[s->mt.col[q]]);
+            mtv.push_back(s->mt.val[q]);
+        }
+        mtp[r + 1] = int32_t(mtc.size());
+    }
     if ((st = upload3(s, &s->d_tet_edge, te.data(), te.size()))) return st;
     if ((st = upload3(s, &s->d_fout, fout.data(), fout.size()))) return st;
     if ((st = upload3(s, &s->d_tet_face, tf.data(), tf.size()))) return st;
@@ -492,13 +600,21 @@ fetd_status upload_mesh3(fetd3_sim *s)
     if ((st = upload3(s, &s->d_ef_ptr, efp.data(), efp.size()))) return st;
     if ((st = upload3(s, &s->d_ef_face, eff.data(), eff.size()))) return st;
     if ((st = upload3(s, &s->d_edge_nodes, en.data(), en.size()))) return st;
-    if ((st = upload3(s, &s->d_edge_free, s->edge_free.data(), s->edge_free.size()))) return st;
-    if ((st = upload3(s, &s->d_nu_ptr, s->mnu.ptr.data(), s->mnu.ptr.size()))) return st;
-    if ((st = upload3(s, &s->d_nu_col, s->mnu.col.data(), s->mnu.col.size()))) return st;
-    if ((st = upload3(s, &s->d_nu_val, s->mnu.val.data(), s->mnu.val.size()))) return st;
-    if ((st = upload3(s, &s->d_mt_ptr, s->mt.ptr.data(), s->mt.ptr.size()))) return st;
-    if ((st = upload3(s, &s->d_mt_col, s->mt.col.data(), s->mt.col.size()))) return st;
-    if ((st = upload3(s, &s->d_mt_val, s->mt.val.data(), s->mt.val.size()))) return st;
+    if ((st = upload3(s, &s->d_edge_free, efree.data(), efree.size()))) return st;
+    if ((st = upload3(s, &s->d_tet_ebase, s->tet_ebase.data(), s->tet_ebase.size()))) return st;
+    {
+        const SellHost nu = to_sell(s->mnu.ptr, s->mnu.col, s->mnu.val);
+        const SellHost mt = to_sell(mtp, mtc, mtv);
+        if ((st = upload3(s, &s->d_nu_sptr, nu.sptr.data(), nu.sptr.size()))) return st;
+        if ((st = upload3(s, &s->d_nu_sw, nu.sw.data(), nu.sw.size()))) return st;
+        if ((st = upload3(s, &s->d_nu_col, nu.col.data(), nu.col.size()))) return st;
+        if ((st = upload3(s, &s->d_nu_val, nu.val.data(), nu.val.size()))) return st;
+        if ((st = upload3(s, &s->d_mt_sptr, mt.sptr.data(), mt.sptr.size()))) return st;
+        if ((st = upload3(s, &s->d_mt_sw, mt.sw.data(), mt.sw.size()))) return st;
+        if ((st = upload3(s, &s->d_mt_col, mt.col.data(), mt.col.size()))) return st;
+        if ((st = upload3(s, &s->d_mt_val, mt.val.data(), mt.val.size()))) return st;
+    }
+    if ((st = zeros3(s, &s->d_chunk_sums, size_t(nt + 1 + 1023) / 1024 + 1))) return st;
     if ((st = zeros3(s, &s->d_b, nf)) || (st = zeros3(s, &s->d_bavg, nf)) ||
         (st = zeros3(s, &s->d_h, nf)) || (st = zeros3(s, &s->d_d, ne)) ||
         (st = zeros3(s, &s->d_e, ne)) || (st = zeros3(s, &s->d_cur, ne)) ||
@@ -512,6 +628,9 @@ fetd_status upload_mesh3(fetd3_sim *s)
     return upload3(s, &s->d_counters, init, 4);
 }
 
+Sell mt_sell(const fetd3_sim *s) { return Sell{s->d_mt_sptr, s->d_mt_sw, s->d_mt_col, s->d_mt_val}; }
+Sell nu_sell(const fetd3_sim *s) { return Sell{s->d_nu_sptr, s->d_nu_sw, s->d_nu_col, s->d_nu_val}; }
+
 Mesh3 mesh_view(const fetd3_sim *s)
 {
     Mesh3 m;
@@ -520,6 +639,7 @@ Mesh3 mesh_view(const fetd3_sim *s)
     m.tet_nbr = s->d_tet_nbr;
     m.tet_map = s->d_tet_map;
     m.grad = s->d_grad;
+    m.tet_ebase = s->d_tet_ebase;
     return m;
 }
 
@@ -633,6 +753,7 @@ fetd_status sort_all3(fetd3_sim *s)
         a.stride_in = a.stride_out = s->p_cap;
         a.counts = s->d_counts;
         a.cursor = s->d_cursor;
+        a.chunk_sums = s->d_chunk_sums;
         // the tail beyond the live particles keeps lost keys
         hipError_t e = hipMemsetAsync(a.key_out, 0xFF, 4 * size_t(sp.n), s->stream);
         if (e == hipSuccess) e = launch3_sort(s->stream, a);
@@ -736,7 +857,7 @@ fetd_status fetd3_fields_set(fetd3_sim *s, const double *b_ext, const double *e_
         s->d_b_ext = nullptr;
     }
     if (e_ext) {
-        if ((st = upload3(s, &s->d_e_ext, e_ext, size_t(s->ne)))) return st;
+        if ((st = upload_edges3(s, &s->d_e_ext, e_ext))) return st;
     } else {
         s->release(s->d_e_ext);
         s->d_e_ext = nullptr;
@@ -761,9 +882,8 @@ fetd_status fetd3_fields_load(fetd3_sim *s, const double *b, const double *d)
         std::vector<double> df(d, d + s->ne);
         for (int e = 0; e < s->ne; ++e)
             if (!s->edge_free[e]) df[e] = 0.0;
-        if ((st = upload3(s, &s->d_d, df.data(), df.size()))) return st;
-        hipError_t e = launch3_spmv(s->stream, s->ne, s->d_mt_ptr, s->d_mt_col, s->d_mt_val,
-                                    s->d_edge_free, s->d_d, s->d_e);
+        if ((st = upload_edges3(s, &s->d_d, df.data()))) return st;
+        hipError_t e = launch3_spmv(s->stream, s->ne, mt_sell(s), s->d_edge_free, s->d_d, s->d_e);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) return s->hip_fail(e, "fields_load spmv");
     }
@@ -871,7 +991,7 @@ fetd_status fetd3_pic_step(fetd3_sim *s, int32_t n_steps, int32_t pusher)
         }
         {
             StageTimer3 tm(s, 2);
-            e = launch3_hnu(s->stream, s->nf, s->d_nu_ptr, s->d_nu_col, s->d_nu_val, s->d_b, s->d_h);
+            e = launch3_hnu(s->stream, s->nf, nu_sell(s), s->d_b, s->d_h);
             if (e == hipSuccess)
                 e = launch3_ampere(s->stream, s->ne, s->d_ef_ptr, s->d_ef_face, s->d_edge_free,
                                    s->d_h, s->d_cur, s->d_cur_last, s->d_d, s->dt);
@@ -879,8 +999,7 @@ fetd_status fetd3_pic_step(fetd3_sim *s, int32_t n_steps, int32_t pusher)
         if (e != hipSuccess) return s->hip_fail(e, "ampere");
         {
             StageTimer3 tm(s, 3);
-            e = launch3_spmv(s->stream, s->ne, s->d_mt_ptr, s->d_mt_col, s->d_mt_val,
-                             s->d_edge_free, s->d_d, s->d_e);
+            e = launch3_spmv(s->stream, s->ne, mt_sell(s), s->d_edge_free, s->d_d, s->d_e);
         }
         if (e != hipSuccess) return s->hip_fail(e, "spmv");
         ++s->step;
@@ -912,14 +1031,14 @@ fetd_status fetd3_fields_get(fetd3_sim *s, int32_t which, void *dst, int64_t cap
     if (st) return st;
     const void *src = nullptr;
     size_t bytes = 0;
-    bool host = false;
+    bool host = false, edge = false;
     std::vector<int32_t> tmp;
     hipError_t e = hipSuccess;
     switch (which) {
-    case FETD3_FIELD_E: src = s->d_e; bytes = 8 * size_t(s->ne); break;
-    case FETD3_FIELD_D: src = s->d_d; bytes = 8 * size_t(s->ne); break;
+    case FETD3_FIELD_E: src = s->d_e; bytes = 8 * size_t(s->ne); edge = true; break;
+    case FETD3_FIELD_D: src = s->d_d; bytes = 8 * size_t(s->ne); edge = true; break;
     case FETD3_FIELD_B: src = s->d_b; bytes = 8 * size_t(s->nf); break;
-    case FETD3_FIELD_J: src = s->d_cur_last; bytes = 8 * size_t(s->ne); break;
+    case FETD3_FIELD_J: src = s->d_cur_last; bytes = 8 * size_t(s->ne); edge = true; break;
     case FETD3_FIELD_Q:
         if ((st = compute_charge3(s))) return st;
         src = s->d_q;
@@ -959,6 +1078,7 @@ fetd_status fetd3_fields_get(fetd3_sim *s, int32_t which, void *dst, int64_t cap
         std::memcpy(dst, src, bytes);
         return FETD_OK;
     }
+    if (edge) return download_edges3(s, static_cast<double *>(dst), static_cast<const double *>(src));
     return download3(s, dst, src, bytes);
 }
 

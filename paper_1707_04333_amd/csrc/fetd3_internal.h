@@ -29,7 +29,16 @@ struct Mesh3 {
     const int4 *tet_nbr;
     const uint32_t *tet_map;
     const double *grad;
+    // edges are numbered on the device in order of first appearance along
+    // the tetrahedron order; tet_ebase[t] = edges first met before t
+    const uint32_t *tet_ebase;
 };
+
+// LDS current window of a particle block: kWin3 consecutive device edge
+// ids starting kBack3 below the first edge id met at the block's home
+// tetrahedron (the tetrahedron of its first particle).
+constexpr int kWin3 = 4096;
+constexpr int kBack3 = 2048;
 
 // Per-tetrahedron gather record, 24 doubles: V_0..V_3 with E = sum l_n V_n,
 // then U_0..U_3 with B = sum l_n U_n (B at time n from the face average).
@@ -59,8 +68,17 @@ struct Sort3 {
     double *lam_out, *u_out;
     int32_t *pid_out;
     int64_t stride_in, stride_out;  // component stride of the SoA arrays
-    int32_t *counts;   // [nt + 1]
-    int32_t *cursor;   // [nt + 1]
+    int32_t *counts;      // [nt + 1]
+    int32_t *cursor;      // [nt + 1]
+    int32_t *chunk_sums;  // [ceil((nt + 1) / 1024)]
+};
+
+// Sliced-ELL sparse matrix: 64-row slices, column-major inside a slice.
+struct Sell {
+    const int32_t *sptr;  // [slices] first entry of each slice
+    const int32_t *sw;    // [slices] width of each slice
+    const int32_t *col;
+    const double *val;
 };
 
 hipError_t launch3_faraday(hipStream_t s, int nf, const int4 *face_edge, const double *e,
@@ -68,13 +86,12 @@ hipError_t launch3_faraday(hipStream_t s, int nf, const int4 *face_edge, const d
 hipError_t launch3_record(hipStream_t s, int nt, const Mesh3 &m, const double *e,
                           const double *e_ext, const double *bavg, double *rec);
 hipError_t launch3_particles(hipStream_t s, const Mesh3 &m, const Step3 &a, int pusher);
-hipError_t launch3_hnu(hipStream_t s, int nf, const int32_t *ptr, const int32_t *col,
-                       const double *val, const double *b, double *h);
+hipError_t launch3_hnu(hipStream_t s, int nf, const Sell &m, const double *b, double *h);
 hipError_t launch3_ampere(hipStream_t s, int ne, const int32_t *ef_ptr, const int32_t *ef_face,
                           const uint8_t *edge_free, const double *h, double *cur,
                           double *cur_last, double *d, double dt);
-hipError_t launch3_spmv(hipStream_t s, int ne, const int32_t *ptr, const int32_t *col,
-                        const double *val, const uint8_t *edge_free, const double *d, double *e);
+hipError_t launch3_spmv(hipStream_t s, int ne, const Sell &m, const uint8_t *edge_free,
+                        const double *d, double *e);
 hipError_t launch3_sort(hipStream_t s, const Sort3 &a);
 hipError_t launch3_charge(hipStream_t s, int64_t n, const uint32_t *key, const double *lam,
                           int64_t stride, const int4 *tet_node, double qw, double *q);

@@ -182,11 +182,29 @@ __device__ __forceinline__ V3 push3(V3 u, V3 eps, V3 beta, double c, double inv_
     }
 }
 
+// Block-local FP64 current accumulation: kWin3 consecutive device edge ids
+// in LDS around the block's home tetrahedron; an edge outside the window
+// goes straight to the global accumulator.
+struct Window3 {
+    double *acc;
+    double *global;
+    int base;
+
+    __device__ __forceinline__ void add(int edge, double v) const
+    {
+        const unsigned j = unsigned(edge - base);
+        if (j < unsigned(kWin3))
+            __hip_atomic_fetch_add(acc + j, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            atomic_add_f64(global + edge, v);
+    }
+};
+
 // Current of one piece inside tetrahedron t from Ls to Lf: i_e += sign
 // (Q/dt) (l_a^s l_b^f - l_a^f l_b^s) on each local edge (a, b).
 __device__ __forceinline__ void deposit_piece(const int32_t *__restrict__ te, int bits,
                                               const double (&Ls)[4], const double (&Lf)[4],
-                                              double qdt, double *__restrict__ cur)
+                                              double qdt, const Window3 &win)
 {
     constexpr int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
 #pragma unroll
@@ -194,7 +212,7 @@ __device__ __forceinline__ void deposit_piece(const int32_t *__restrict__ te, in
         const int a = ea[k], b = eb[k];
         const double w = Ls[a] * Lf[b] - Lf[a] * Ls[b];
         const double sq = ((bits >> k) & 1) ? -qdt : qdt;
-        atomic_add_f64(cur + te[k], sq * w);
+        win.add(te[k], sq * w);
     }
 }
 
@@ -203,6 +221,18 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
 {
     const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     unsigned long long pieces = 0, lost_here = 0;
+    __shared__ double s_win[kWin3];
+    __shared__ int s_base;
+    for (int j = threadIdx.x; j < kWin3; j += blockDim.x) s_win[j] = 0.0;
+    if (threadIdx.x == 0) {
+        // home: the tetrahedron of the block's first particle (read before
+        // any thread of the block writes its key)
+        const uint32_t k0 = a.key[int64_t(blockIdx.x) * blockDim.x];
+        const int home = k0 == kLost ? 0 : int(k0 & kTetMask);
+        s_base = int(m.tet_ebase[home]) - kBack3;
+    }
+    __syncthreads();
+    const Window3 win{s_win, a.cur, s_base};
     if (p < a.n) {
         const uint32_t key = a.key[p];
         if (key != kLost) {
@@ -261,7 +291,7 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
                     const double f2 = pick4(L, i2) + pick4(dL, i2);
                     const double f3 = pick4(L, i3) + pick4(dL, i3);
                     unpack_lambda(r, f1, f2, f3, Lf);
-                    deposit_piece(te, bits, L, Lf, a.qdt, a.cur);
+                    deposit_piece(te, bits, L, Lf, a.qdt, win);
                     a.key[p] = uint32_t(t) | (uint32_t(r) << 30);
                     a.lam[p] = f1;
                     a.lam[n + p] = f2;
@@ -277,7 +307,7 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
                 put4(Lf, kp, lp);
                 put4(Lf, kq, lq);
                 put4(Lf, kw, lw);
-                deposit_piece(te, bits, L, Lf, a.qdt, a.cur);
+                deposit_piece(te, bits, L, Lf, a.qdt, win);
                 const int4 nb4 = m.tet_nbr[t];
                 const int nb = ks == 0 ? nb4.x : ks == 1 ? nb4.y : ks == 2 ? nb4.z : nb4.w;
                 if (nb < 0) {
@@ -308,6 +338,12 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
             }
         }
     }
+    // flush the window (nonzero entries were deposited at valid edge ids)
+    __syncthreads();
+    for (int j = threadIdx.x; j < kWin3; j += blockDim.x) {
+        const double v = s_win[j];
+        if (v != 0.0) atomic_add_f64(a.cur + (win.base + j), v);
+    }
     // block totals of pieces and removed particles
     __shared__ unsigned long long s_pc[4], s_lc[4];
     for (int off = 32; off > 0; off >>= 1) {
@@ -331,15 +367,23 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
     }
 }
 
-__global__ __launch_bounds__(256) void k3_hnu(int nf, const int32_t *__restrict__ ptr,
+// Sparse products in sliced-ELL form: slices of 64 consecutive rows, each
+// stored column-major with the slice's widest row as width (padding: value
+// 0, column = the row itself), so a wavefront reads every entry once,
+// coalesced.  Each row sums its entries in its stored order.
+__global__ __launch_bounds__(256) void k3_hnu(int nf, const int32_t *__restrict__ sptr,
+                                              const int32_t *__restrict__ sw,
                                               const int32_t *__restrict__ col,
                                               const double *__restrict__ val,
                                               const double *__restrict__ b, double *__restrict__ h)
 {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
+    const int sl = f >> 6, lane = f & 63;
+    const int w = sw[sl];
+    const int64_t base = int64_t(sptr[sl]) + lane;
     double acc = 0.0;
-    for (int j = ptr[f]; j < ptr[f + 1]; ++j) acc += val[j] * b[col[j]];
+    for (int j = 0; j < w; ++j) acc += val[base + 64 * j] * b[col[base + 64 * j]];
     h[f] = acc;
 }
 
@@ -368,7 +412,8 @@ __global__ __launch_bounds__(256) void k3_ampere(int ne, const int32_t *__restri
     cur[ed] = 0.0;
 }
 
-__global__ __launch_bounds__(256) void k3_spmv(int ne, const int32_t *__restrict__ ptr,
+__global__ __launch_bounds__(256) void k3_spmv(int ne, const int32_t *__restrict__ sptr,
+                                               const int32_t *__restrict__ sw,
                                                const int32_t *__restrict__ col,
                                                const double *__restrict__ val,
                                                const uint8_t *__restrict__ edge_free,
@@ -377,9 +422,12 @@ __global__ __launch_bounds__(256) void k3_spmv(int ne, const int32_t *__restrict
 {
     const int ed = blockIdx.x * blockDim.x + threadIdx.x;
     if (ed >= ne) return;
+    const int sl = ed >> 6, lane = ed & 63;
+    const int w = sw[sl];
+    const int64_t base = int64_t(sptr[sl]) + lane;
     double acc = 0.0;
     if (edge_free[ed])
-        for (int j = ptr[ed]; j < ptr[ed + 1]; ++j) acc += val[j] * d[col[j]];
+        for (int j = 0; j < w; ++j) acc += val[base + 64 * j] * d[col[base + 64 * j]];
     e[ed] = acc;
 }
 
@@ -393,29 +441,59 @@ __global__ __launch_bounds__(256) void k3_sort_count(int64_t n, const uint32_t *
     if (k != kLost) atomicAdd(counts + (k & kTetMask), 1);
 }
 
-// ... exclusive scan of counts[0..nt] into cursor (one block of 1024) ...
-__global__ __launch_bounds__(1024) void k3_sort_scan(int n, const int32_t *__restrict__ counts,
-                                                     int32_t *__restrict__ cursor)
+// ... exclusive scan of counts[0..nt] into cursor: each block of 1024
+// scans its chunk and reports the chunk total ...
+__global__ __launch_bounds__(1024) void k3_scan_chunks(int n, const int32_t *__restrict__ counts,
+                                                       int32_t *__restrict__ cursor,
+                                                       int32_t *__restrict__ chunk_sums)
+{
+    __shared__ int32_t part[1024];
+    const int i = blockIdx.x * 1024 + threadIdx.x;
+    const int32_t v = i < n ? counts[i] : 0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int32_t x = threadIdx.x >= unsigned(off) ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += x;
+        __syncthreads();
+    }
+    if (i < n) cursor[i] = part[threadIdx.x] - v;
+    if (threadIdx.x == 1023) chunk_sums[blockIdx.x] = part[1023];
+}
+
+// ... the chunk totals are scanned by one block (sequential runs per
+// thread, so any number of chunks fits) ...
+__global__ __launch_bounds__(1024) void k3_scan_totals(int nchunk, int32_t *__restrict__ sums)
 {
     __shared__ int32_t part[1024];
     const int tid = threadIdx.x;
-    const int chunk = (n + 1023) / 1024;
-    const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+    const int per = (nchunk + 1023) / 1024;
+    const int lo = min(nchunk, tid * per), hi = min(nchunk, lo + per);
     int32_t s = 0;
-    for (int i = lo; i < hi; ++i) s += counts[i];
+    for (int i = lo; i < hi; ++i) s += sums[i];
     part[tid] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        const int32_t v = tid >= off ? part[tid - off] : 0;
+        const int32_t x = tid >= off ? part[tid - off] : 0;
         __syncthreads();
-        part[tid] += v;
+        part[tid] += x;
         __syncthreads();
     }
     int32_t run = part[tid] - s;
     for (int i = lo; i < hi; ++i) {
-        cursor[i] = run;
-        run += counts[i];
+        const int32_t c = sums[i];
+        sums[i] = run;
+        run += c;
     }
+}
+
+// ... and added back to every chunk.
+__global__ __launch_bounds__(1024) void k3_scan_add(int n, int32_t *__restrict__ cursor,
+                                                    const int32_t *__restrict__ sums)
+{
+    const int i = blockIdx.x * 1024 + threadIdx.x;
+    if (i < n) cursor[i] += sums[blockIdx.x];
 }
 
 // ... and scatter of every live particle to the next free place of its
@@ -514,11 +592,11 @@ hipError_t launch3_particles(hipStream_t s, const Mesh3 &m, const Step3 &a, int 
     return hipGetLastError();
 }
 
-hipError_t launch3_hnu(hipStream_t s, int nf, const int32_t *ptr, const int32_t *col,
-                       const double *val, const double *b, double *h)
+hipError_t launch3_hnu(hipStream_t s, int nf, const Sell &m, const double *b, double *h)
 {
     if (nf <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k3_hnu, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf, ptr, col, val, b, h);
+    hipLaunchKernelGGL(k3_hnu, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf, m.sptr, m.sw, m.col,
+                       m.val, b, h);
     return hipGetLastError();
 }
 
@@ -532,12 +610,12 @@ hipError_t launch3_ampere(hipStream_t s, int ne, const int32_t *ef_ptr, const in
     return hipGetLastError();
 }
 
-hipError_t launch3_spmv(hipStream_t s, int ne, const int32_t *ptr, const int32_t *col,
-                        const double *val, const uint8_t *edge_free, const double *d, double *e)
+hipError_t launch3_spmv(hipStream_t s, int ne, const Sell &m, const uint8_t *edge_free,
+                        const double *d, double *e)
 {
     if (ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k3_spmv, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, ptr, col, val,
-                       edge_free, d, e);
+    hipLaunchKernelGGL(k3_spmv, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, m.sptr, m.sw, m.col,
+                       m.val, edge_free, d, e);
     return hipGetLastError();
 }
 
@@ -548,7 +626,11 @@ hipError_t launch3_sort(hipStream_t s, const Sort3 &a)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k3_sort_count, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a.n, a.key_in,
                        a.counts);
-    hipLaunchKernelGGL(k3_sort_scan, dim3(1), dim3(1024), 0, s, a.nt + 1, a.counts, a.cursor);
+    const int n1 = a.nt + 1, nchunk = (n1 + 1023) / 1024;
+    hipLaunchKernelGGL(k3_scan_chunks, dim3(nchunk), dim3(1024), 0, s, n1, a.counts, a.cursor,
+                       a.chunk_sums);
+    hipLaunchKernelGGL(k3_scan_totals, dim3(1), dim3(1024), 0, s, nchunk, a.chunk_sums);
+    hipLaunchKernelGGL(k3_scan_add, dim3(nchunk), dim3(1024), 0, s, n1, a.cursor, a.chunk_sums);
     hipLaunchKernelGGL(k3_sort_scatter, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
