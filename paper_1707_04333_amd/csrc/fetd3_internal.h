@@ -37,8 +37,8 @@ struct Mesh3 {
 // LDS current window of a particle block: kWin3 consecutive device edge
 // ids starting kBack3 below the first edge id met at the block's home
 // tetrahedron (the tetrahedron of its first particle).
-constexpr int kWin3 = 4096;
-constexpr int kBack3 = 2048;
+constexpr int kWin3 = 2048;
+constexpr int kBack3 = 1024;
 
 // Per-tetrahedron gather record, 24 doubles: V_0..V_3 with E = sum l_n V_n,
 // then U_0..U_3 with B = sum l_n U_n (B at time n from the face average).

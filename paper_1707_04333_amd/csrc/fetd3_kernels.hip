@@ -216,10 +216,82 @@ __device__ __forceinline__ void deposit_piece(const int32_t *__restrict__ te, in
     }
 }
 
+// Cross-lane move of a double by a DPP control; lanes whose source lies
+// outside the row (or in a row disabled by RM) read 0.
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, 0xF, true);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL, int RM>
+__device__ __forceinline__ void seg_step6(double (&c)[6], bool take)
+{
+    double o[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) o[k] = dpp_f64<CTRL, RM>(c[k]);
+    if (take)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) c[k] += o[k];
+}
+
+// Inclusive segmented sum over the wavefront: every lane ends with the sum
+// over its run [seg_start, lane] (row shifts 1, 2, 4, 8 inside rows of 16
+// lanes, then the row-15 and row-31 broadcasts across rows).
+__device__ __forceinline__ void wave_segmented_sum6(double (&c)[6], int lane, int seg_start)
+{
+    const int in_row = lane & 15;
+    seg_step6<0x111, 0xF>(c, in_row >= 1 && lane - 1 >= seg_start);
+    seg_step6<0x112, 0xF>(c, in_row >= 2 && lane - 2 >= seg_start);
+    seg_step6<0x114, 0xF>(c, in_row >= 4 && lane - 4 >= seg_start);
+    seg_step6<0x118, 0xF>(c, in_row >= 8 && lane - 8 >= seg_start);
+    seg_step6<0x142, 0xA>(c, (lane & 16) && (lane & ~15) - 1 >= seg_start);
+    seg_step6<0x143, 0xC>(c, lane >= 32 && 31 >= seg_start);
+}
+
+// Exit test of one piece: dL_k = grad l_k . r for the four faces, the face
+// with the smallest tau_k = max(l_k, 0)/(-dL_k) among dL_k < 0 (not the
+// face just entered; ties to the smaller k), or ks = -1.
+__device__ __forceinline__ void exit_face(const double *__restrict__ G, double rx, double ry,
+                                          double rz, const double (&L)[4], int entry,
+                                          double (&dL)[4], int &ks, double &ts)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dL[k] = G[3 * k] * rx + G[3 * k + 1] * ry + G[3 * k + 2] * rz;
+    ks = -1;
+    ts = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k == entry || !(dL[k] < 0.0)) continue;
+        const double tk = (L[k] > 0.0 ? L[k] : 0.0) / (-dL[k]);
+        if (ks < 0 || tk < ts) {
+            ks = k;
+            ts = tk;
+        }
+    }
+}
+
+// W1 weights l_a^s l_b^f - l_a^f l_b^s of the six local edges of a piece.
+__device__ __forceinline__ void piece_weights(const double (&Ls)[4], const double (&Lf)[4],
+                                              double (&w)[6])
+{
+    constexpr int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) w[k] = Ls[ea[k]] * Lf[eb[k]] - Lf[ea[k]] * Ls[eb[k]];
+}
+
+// One particle block: phase A (every lane: gather, push, first piece), a
+// wavefront sum of the first-piece currents over runs of equal start
+// tetrahedron (particles are sorted by tetrahedron), then phase B for the
+// particles that crossed a face, depositing piece by piece.
 template <int P>
 __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
 {
     const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     unsigned long long pieces = 0, lost_here = 0;
     __shared__ double s_win[kWin3];
     __shared__ int s_base;
@@ -233,13 +305,18 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
     }
     __syncthreads();
     const Window3 win{s_win, a.cur, s_base};
+    const int64_t n = a.stride;
+
+    // ---- phase A
+    bool moving = false;
+    int t = 0, r = 0;
+    double L[4] = {0.0, 0.0, 0.0, 0.0};
+    double rx = 0.0, ry = 0.0, rz = 0.0;
     if (p < a.n) {
         const uint32_t key = a.key[p];
         if (key != kLost) {
-            int t = int(key & kTetMask);
-            int r = int(key >> 30);
-            const int64_t n = a.stride;
-            double L[4];
+            t = int(key & kTetMask);
+            r = int(key >> 30);
             unpack_lambda(r, a.lam[p], a.lam[n + p], a.lam[2 * n + p], L);
             const double *rc = a.rec + size_t(kRec) * t;
             V3 E{0.0, 0.0, 0.0}, B{0.0, 0.0, 0.0};
@@ -251,93 +328,161 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
             if (a.b_ext) B = B + V3{a.b_ext[3 * t], a.b_ext[3 * t + 1], a.b_ext[3 * t + 2]};
             const V3 u0{a.u[p], a.u[n + p], a.u[2 * n + p]};
             const V3 u1 = push3<P>(u0, a.alpha * E, a.alpha * B, a.c, a.inv_c2);
-            const bool finite = isfinite(u1.x) && isfinite(u1.y) && isfinite(u1.z);
-            if (!finite) {
-                atomicOr(a.counters + 2, 2ull);
-                atomicMin(a.counters + 3, (unsigned long long)p);
-            }
-            int cap = finite ? a.cap : 0;  // a bad particle is left where it is
-            bool done = !finite;
             a.u[p] = u1.x;
             a.u[n + p] = u1.y;
             a.u[2 * n + p] = u1.z;
-            const double g = gam(u1, a.inv_c2);
-            double rx = a.dt * u1.x / g, ry = a.dt * u1.y / g, rz = a.dt * u1.z / g;
-            int entry = -1;
-            for (int it = 0; it < cap; ++it) {
-                const double *G = m.grad + 12 * size_t(t);
-                const int32_t *te = m.tet_edge + 8 * size_t(t);
-                const int bits = te[6];
-                double dL[4];
+            if (isfinite(u1.x) && isfinite(u1.y) && isfinite(u1.z)) {
+                moving = a.cap > 0;
+                const double g = gam(u1, a.inv_c2);
+                rx = a.dt * u1.x / g;
+                ry = a.dt * u1.y / g;
+                rz = a.dt * u1.z / g;
+            } else {
+                // a bad particle is left where it is
+                atomicOr(a.counters + 2, 2ull);
+                atomicMin(a.counters + 3, (unsigned long long)p);
+            }
+        }
+    }
+    int t0 = -1, bits0 = 0, entry = -1;
+    int te0[6] = {0, 0, 0, 0, 0, 0};
+    double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    bool more = false;  // crossed a face into a neighbour: continue in phase B
+    if (moving) {
+        t0 = t;
+        const int32_t *te = m.tet_edge + 8 * size_t(t);
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    dL[k] = G[3 * k] * rx + G[3 * k + 1] * ry + G[3 * k + 2] * rz;
-                int ks = -1;
-                double ts = 0.0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (k == entry || !(dL[k] < 0.0)) continue;
-                    const double tk = (L[k] > 0.0 ? L[k] : 0.0) / (-dL[k]);
-                    if (ks < 0 || tk < ts) {
-                        ks = k;
-                        ts = tk;
-                    }
-                }
-                double Lf[4];
-                ++pieces;
-                if (ks < 0 || ts >= 1.0) {
-                    const int i1 = (r + 1) & 3, i2 = (r + 2) & 3, i3 = (r + 3) & 3;
-                    const double f1 = pick4(L, i1) + pick4(dL, i1);
-                    const double f2 = pick4(L, i2) + pick4(dL, i2);
-                    const double f3 = pick4(L, i3) + pick4(dL, i3);
-                    unpack_lambda(r, f1, f2, f3, Lf);
-                    deposit_piece(te, bits, L, Lf, a.qdt, win);
-                    a.key[p] = uint32_t(t) | (uint32_t(r) << 30);
-                    a.lam[p] = f1;
-                    a.lam[n + p] = f2;
-                    a.lam[2 * n + p] = f3;
-                    done = true;
-                    break;
-                }
-                const int kp = (ks + 1) & 3, kq = (ks + 2) & 3, kw = (ks + 3) & 3;
-                const double lp = pick4(L, kp) + ts * pick4(dL, kp);
-                const double lq = pick4(L, kq) + ts * pick4(dL, kq);
-                const double lw = (1.0 - lp) - lq;
-                Lf[0] = Lf[1] = Lf[2] = Lf[3] = 0.0;
-                put4(Lf, kp, lp);
-                put4(Lf, kq, lq);
-                put4(Lf, kw, lw);
-                deposit_piece(te, bits, L, Lf, a.qdt, win);
-                const int4 nb4 = m.tet_nbr[t];
-                const int nb = ks == 0 ? nb4.x : ks == 1 ? nb4.y : ks == 2 ? nb4.z : nb4.w;
-                if (nb < 0) {
-                    // wall: removed after depositing up to it
-                    a.key[p] = kLost;
-                    ++lost_here;
-                    done = true;
-                    break;
-                }
+        for (int k = 0; k < 6; ++k) te0[k] = te[k];
+        bits0 = te[6];
+        double dL[4];
+        int ks;
+        double ts;
+        exit_face(m.grad + 12 * size_t(t), rx, ry, rz, L, -1, dL, ks, ts);
+        ++pieces;
+        double Lf[4];
+        if (ks < 0 || ts >= 1.0) {
+            const int i1 = (r + 1) & 3, i2 = (r + 2) & 3, i3 = (r + 3) & 3;
+            const double f1 = pick4(L, i1) + pick4(dL, i1);
+            const double f2 = pick4(L, i2) + pick4(dL, i2);
+            const double f3 = pick4(L, i3) + pick4(dL, i3);
+            unpack_lambda(r, f1, f2, f3, Lf);
+            piece_weights(L, Lf, c);
+            a.key[p] = uint32_t(t) | (uint32_t(r) << 30);
+            a.lam[p] = f1;
+            a.lam[n + p] = f2;
+            a.lam[2 * n + p] = f3;
+        } else {
+            const int kp = (ks + 1) & 3, kq = (ks + 2) & 3, kw = (ks + 3) & 3;
+            const double lp = pick4(L, kp) + ts * pick4(dL, kp);
+            const double lq = pick4(L, kq) + ts * pick4(dL, kq);
+            const double lw = (1.0 - lp) - lq;
+            Lf[0] = Lf[1] = Lf[2] = Lf[3] = 0.0;
+            put4(Lf, kp, lp);
+            put4(Lf, kq, lq);
+            put4(Lf, kw, lw);
+            piece_weights(L, Lf, c);
+            const int4 nb4 = m.tet_nbr[t];
+            const int nb = ks == 0 ? nb4.x : ks == 1 ? nb4.y : ks == 2 ? nb4.z : nb4.w;
+            if (nb < 0) {
+                // wall: removed after depositing up to it
+                a.key[p] = kLost;
+                ++lost_here;
+            } else {
                 const uint32_t mp = (m.tet_map[t] >> (8 * ks)) & 0xFFu;
-                const int np = int(mp & 3), nq = int((mp >> 2) & 3), nw = int((mp >> 4) & 3);
-                const int nk = int(mp >> 6);
                 L[0] = L[1] = L[2] = L[3] = 0.0;
-                put4(L, np, lp);
-                put4(L, nq, lq);
-                put4(L, nw, lw);
-                r = nw;
-                entry = nk;
+                put4(L, int(mp & 3), lp);
+                put4(L, int((mp >> 2) & 3), lq);
+                put4(L, int((mp >> 4) & 3), lw);
+                r = int((mp >> 4) & 3);
+                entry = int(mp >> 6);
                 t = nb;
                 const double sc = 1.0 - ts;
                 rx *= sc;
                 ry *= sc;
                 rz *= sc;
-            }
-            if (!done) {
-                atomicOr(a.counters + 2, 1ull);
-                atomicMin(a.counters + 3, (unsigned long long)p);
+                more = true;
             }
         }
     }
+
+    // ---- first-piece currents: wavefront sum over runs of equal start
+    // tetrahedron, then the run's last lane adds them to the window
+    {
+        const int kprev = __shfl_up(t0, 1, 64);
+        const bool head = lane == 0 || kprev != t0;
+        const unsigned long long hm = __ballot(head);
+        const unsigned long long below = hm & ((2ull << lane) - 1ull);
+        const int seg_start = 63 - __clzll(below);
+        wave_segmented_sum6(c, lane, seg_start);
+        const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
+        if (tail && t0 >= 0)
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                win.add(te0[k], (((bits0 >> k) & 1) ? -a.qdt : a.qdt) * c[k]);
+    }
+
+    // ---- phase B: the particles that crossed a face
+    if (more) {
+        bool fin = false;
+        for (int it = 1; it < a.cap; ++it) {
+            const int32_t *te = m.tet_edge + 8 * size_t(t);
+            const int bits = te[6];
+            double dL[4];
+            int ks;
+            double ts;
+            exit_face(m.grad + 12 * size_t(t), rx, ry, rz, L, entry, dL, ks, ts);
+            double Lf[4];
+            ++pieces;
+            if (ks < 0 || ts >= 1.0) {
+                const int i1 = (r + 1) & 3, i2 = (r + 2) & 3, i3 = (r + 3) & 3;
+                const double f1 = pick4(L, i1) + pick4(dL, i1);
+                const double f2 = pick4(L, i2) + pick4(dL, i2);
+                const double f3 = pick4(L, i3) + pick4(dL, i3);
+                unpack_lambda(r, f1, f2, f3, Lf);
+                deposit_piece(te, bits, L, Lf, a.qdt, win);
+                a.key[p] = uint32_t(t) | (uint32_t(r) << 30);
+                a.lam[p] = f1;
+                a.lam[n + p] = f2;
+                a.lam[2 * n + p] = f3;
+                fin = true;
+                break;
+            }
+            const int kp = (ks + 1) & 3, kq = (ks + 2) & 3, kw = (ks + 3) & 3;
+            const double lp = pick4(L, kp) + ts * pick4(dL, kp);
+            const double lq = pick4(L, kq) + ts * pick4(dL, kq);
+            const double lw = (1.0 - lp) - lq;
+            Lf[0] = Lf[1] = Lf[2] = Lf[3] = 0.0;
+            put4(Lf, kp, lp);
+            put4(Lf, kq, lq);
+            put4(Lf, kw, lw);
+            deposit_piece(te, bits, L, Lf, a.qdt, win);
+            const int4 nb4 = m.tet_nbr[t];
+            const int nb = ks == 0 ? nb4.x : ks == 1 ? nb4.y : ks == 2 ? nb4.z : nb4.w;
+            if (nb < 0) {
+                a.key[p] = kLost;
+                ++lost_here;
+                fin = true;
+                break;
+            }
+            const uint32_t mp = (m.tet_map[t] >> (8 * ks)) & 0xFFu;
+            L[0] = L[1] = L[2] = L[3] = 0.0;
+            put4(L, int(mp & 3), lp);
+            put4(L, int((mp >> 2) & 3), lq);
+            put4(L, int((mp >> 4) & 3), lw);
+            r = int((mp >> 4) & 3);
+            entry = int(mp >> 6);
+            t = nb;
+            const double sc = 1.0 - ts;
+            rx *= sc;
+            ry *= sc;
+            rz *= sc;
+        }
+        if (!fin) {
+            atomicOr(a.counters + 2, 1ull);
+            atomicMin(a.counters + 3, (unsigned long long)p);
+        }
+    }
+
     // flush the window (nonzero entries were deposited at valid edge ids)
     __syncthreads();
     for (int j = threadIdx.x; j < kWin3; j += blockDim.x) {
@@ -350,7 +495,7 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
         pieces += __shfl_down(pieces, off, 64);
         lost_here += __shfl_down(lost_here, off, 64);
     }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wv = threadIdx.x >> 6;
     if (lane == 0) {
         s_pc[wv] = pieces;
         s_lc[wv] = lost_here;
