@@ -39,6 +39,9 @@ struct Mesh3 {
 // tetrahedron (the tetrahedron of its first particle).
 constexpr int kWin3 = 2048;
 constexpr int kBack3 = 1024;
+// Open-addressing table of the block for edges outside the window.
+constexpr int kHashBits3 = 8;
+constexpr int kHash3 = 1 << kHashBits3;
 
 // Per-tetrahedron gather record, 24 doubles: V_0..V_3 with E = sum l_n V_n,
 // then U_0..U_3 with B = sum l_n U_n (B at time n from the face average).

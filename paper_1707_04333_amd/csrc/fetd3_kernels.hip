@@ -183,20 +183,40 @@ __device__ __forceinline__ V3 push3(V3 u, V3 eps, V3 beta, double c, double inv_
 }
 
 // Block-local FP64 current accumulation: kWin3 consecutive device edge ids
-// in LDS around the block's home tetrahedron; an edge outside the window
-// goes straight to the global accumulator.
+// in LDS around the block's home tetrahedron, and a small open-addressing
+// table for the edges outside it (an edge shared with a tetrahedron far
+// away in the tetrahedron order); only when the table's probes are taken
+// does an add go straight to the global accumulator.
 struct Window3 {
     double *acc;
+    int *hkey;     // [kHash3], -1 = free
+    double *hval;  // [kHash3]
     double *global;
     int base;
 
     __device__ __forceinline__ void add(int edge, double v) const
     {
         const unsigned j = unsigned(edge - base);
-        if (j < unsigned(kWin3))
+        if (j < unsigned(kWin3)) {
             __hip_atomic_fetch_add(acc + j, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        else
-            atomic_add_f64(global + edge, v);
+            return;
+        }
+        const unsigned h = (unsigned(edge) * 2654435761u) >> (32 - kHashBits3);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const unsigned slot = (h + unsigned(q)) & unsigned(kHash3 - 1);
+            int k = hkey[slot];
+            if (k == -1) {
+                k = atomicCAS(hkey + slot, -1, edge);
+                if (k == -1) k = edge;
+            }
+            if (k == edge) {
+                __hip_atomic_fetch_add(hval + slot, v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                return;
+            }
+        }
+        atomic_add_f64(global + edge, v);
     }
 };
 
@@ -294,8 +314,14 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
     const int lane = threadIdx.x & 63;
     unsigned long long pieces = 0, lost_here = 0;
     __shared__ double s_win[kWin3];
+    __shared__ double s_hval[kHash3];
+    __shared__ int s_hkey[kHash3];
     __shared__ int s_base;
     for (int j = threadIdx.x; j < kWin3; j += blockDim.x) s_win[j] = 0.0;
+    for (int j = threadIdx.x; j < kHash3; j += blockDim.x) {
+        s_hkey[j] = -1;
+        s_hval[j] = 0.0;
+    }
     if (threadIdx.x == 0) {
         // home: the tetrahedron of the block's first particle (read before
         // any thread of the block writes its key)
@@ -304,7 +330,7 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
         s_base = int(m.tet_ebase[home]) - kBack3;
     }
     __syncthreads();
-    const Window3 win{s_win, a.cur, s_base};
+    const Window3 win{s_win, s_hkey, s_hval, a.cur, s_base};
     const int64_t n = a.stride;
 
     // ---- phase A
@@ -488,6 +514,11 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
     for (int j = threadIdx.x; j < kWin3; j += blockDim.x) {
         const double v = s_win[j];
         if (v != 0.0) atomic_add_f64(a.cur + (win.base + j), v);
+    }
+    for (int j = threadIdx.x; j < kHash3; j += blockDim.x) {
+        const int k = s_hkey[j];
+        const double v = s_hval[j];
+        if (k >= 0 && v != 0.0) atomic_add_f64(a.cur + k, v);
     }
     // block totals of pieces and removed particles
     __shared__ unsigned long long s_pc[4], s_lc[4];
