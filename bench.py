@@ -226,59 +226,85 @@ def run_bernstein(args):
             "band1_frac_within_0.05": float(np.mean(dev < 0.05))}
 
 
-def tet_particle_launch_bytes(n_particles, nt, ne):
-    """Algorithmic bytes of one tetrahedral particle launch (FP64): every
-    particle reads and writes its key (4 B), stored barycentric triple and
-    momentum (3 + 3 doubles); every tetrahedron's gather record (24
-    doubles), gradients (12 doubles), edge table (32 B), neighbour table
-    (16 B) and node map (4 B) are read once; every edge's current is read
-    and written once."""
-    return n_particles * 2 * (4 + 6 * 8) + nt * (24 * 8 + 12 * 8 + 32 + 16 + 4) + ne * 16
+def tet_particle_launch_bytes(n_particles, nt, ne, fp32):
+    """Algorithmic bytes of one tetrahedral particle launch: every particle
+    reads and writes its key (4 B), stored barycentric triple and momentum
+    (3 + 3 reals); every tetrahedron's gather record (24 reals), gradients
+    (12 reals), edge table (32 B), neighbour table (16 B) and node map (4 B)
+    are read once; every edge's FP64 current is read and written once."""
+    r = 4 if fp32 else 8
+    return n_particles * 2 * (4 + 6 * r) + nt * (36 * r + 32 + 16 + 4) + ne * 16
+
+
+def _run_tet_one(w, precision, steps, warmup):
+    from paper_1707_04333_amd import fetd3
+    sim = fetd3.from_workload3(w, resort_every=20, precision=precision)
+    sim.step(warmup, "boris")
+    sim.sync()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    sim.step(steps, "boris")
+    sim.sync()
+    el = time.perf_counter() - t0
+    stages, launches = sim.stage_times()
+    sim.profile(False)
+    d = sim.diagnostics()
+    sim.close()
+    return el, stages, launches, d
 
 
 def run_tet(args):
     """The tetrahedral path on a triply periodic pair plasma: 48^3 Kuhn cells
     (663,552 tetrahedra), 8M electrons + 8M positrons (24 per tetrahedron),
     3-D Maxwell-Juttner momenta at theta = 0.1, B0 = 1 T along z,
-    omega_c/omega_p = 2, FP64 throughout, Boris, sorted every 20 steps."""
-    from paper_1707_04333_amd import fetd3
+    omega_c/omega_p = 2, Boris, sorted every 20 steps; mixed precision (the
+    value) and FP64."""
     from paper_1707_04333_amd import inputs3 as J
     log("generating the tetrahedral pair plasma")
     w = J.tet_pair_plasma(n_pairs=args.pairs)
     n_p = w.n_particles
     species_n = [s.n for s in w.species]
-    sim = fetd3.from_workload3(w, resort_every=20)
-    nt, ne = w.mesh.n_tets, None
-    sim.step(args.warmup, "boris")
-    sim.sync()
-    sim.profile(True)
-    t0 = time.perf_counter()
-    sim.step(args.steps, "boris")
-    sim.sync()
-    el = time.perf_counter() - t0
-    stages, launches = sim.stage_times()
-    sim.profile(False)
-    d = sim.diagnostics()
-    ne = d["n_edges"]
-    sim.close()
-    per_launch = float(np.mean([tet_particle_launch_bytes(n, nt, ne) for n in species_n]))
-    avg_s = stages["particles"] / 1e3 / max(launches, 1)
-    achieved = per_launch / avg_s / 1e9
-    out = {"metric": METRIC, "value": n_p * args.steps / el, "unit": "particle-steps/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "tet_pair_plasma", "n_tets": nt, "n_edges": ne,
-                      "n_faces": d["n_faces"], "n_particles": n_p, "theta": w.extra["theta"],
-                      "pusher": "boris", "precision": "fp64", "resort_every": 20,
+    nt = w.mesh.n_tets
+    res = {}
+    for prec in ("mixed", "fp64"):
+        if prec == "fp64" and args.no_fp64:
+            continue
+        log(f"tetrahedral run, {prec}")
+        el, stages, launches, d = _run_tet_one(w, prec, args.steps, args.warmup)
+        ne = d["n_edges"]
+        per_launch = float(np.mean([tet_particle_launch_bytes(n, nt, ne, prec == "mixed")
+                                    for n in species_n]))
+        avg_s = stages["particles"] / 1e3 / max(launches, 1)
+        achieved = per_launch / avg_s / 1e9
+        res[prec] = {"value": n_p * args.steps / el, "ms_per_step": el / args.steps * 1e3,
+                     "roofline": {"bound": "hbm", "kernel": "k3_particles", "achieved": achieved,
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                                  "avg_launch_ms": avg_s * 1e3,
+                                  "algorithmic_bytes_per_launch": per_launch},
+                     "stage_ms_per_step": {k: v / args.steps for k, v in stages.items()},
+                     "gauss_rel": d["gauss_rel"], "divb_rel": d["divb_rel"],
+                     "pieces_per_particle_step": d["n_segments"]
+                     / (n_p * (args.steps + args.warmup)), "n_edges": ne,
+                     "n_faces": d["n_faces"]}
+    m = res["mixed"]
+    out = {"metric": METRIC, "value": m["value"], "unit": "particle-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 particle state/push/march, f64 barycentrics in flight, deposit+fields",
+           "data": "synthetic",
+           "config": {"workload": "tet_pair_plasma", "n_tets": nt, "n_edges": m["n_edges"],
+                      "n_faces": m["n_faces"], "n_particles": n_p, "theta": w.extra["theta"],
+                      "pusher": "boris", "precision": "mixed", "resort_every": 20,
                       "spai_level": 1},
-           "roofline": {"bound": "hbm", "kernel": "k3_particles", "achieved": achieved,
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": None, "avg_launch_ms": avg_s * 1e3,
-                        "algorithmic_bytes_per_launch": per_launch},
-           "stage_ms_per_step": {k: v / args.steps for k, v in stages.items()},
-           "gauss_rel": d["gauss_rel"], "divb_rel": d["divb_rel"],
-           "pieces_per_particle_step": d["n_segments"] / (n_p * (args.steps + args.warmup))}
+           "roofline": m["roofline"], "stage_ms_per_step": m["stage_ms_per_step"],
+           "gauss_rel": m["gauss_rel"], "divb_rel": m["divb_rel"],
+           "pieces_per_particle_step": m["pieces_per_particle_step"]}
+    if "fp64" in res:
+        f = res["fp64"]
+        out["fp64"] = {k: f[k] for k in ("value", "ms_per_step", "roofline", "stage_ms_per_step",
+                                         "gauss_rel", "divb_rel")}
+        out["mixed_vs_fp64"] = m["value"] / f["value"]
     del w
     if not args.no_cpu:
         log("timing the tetrahedral CPU oracle on a sample")

@@ -6,7 +6,8 @@
  * edges) and S (cells x faces), Hodge matrices [*eps] on edges and
  * [*mu^-1] on faces, a sparse approximate inverse of [*eps], the four
  * relativistic pushers of Sec. II.C and the charge-conserving scatter of
- * Sec. II.D on the six edges of a tetrahedron.  FP64 throughout.
+ * Sec. II.D on the six edges of a tetrahedron.  FP64, or the mixed mode
+ * of fetd3_opts.precision.
  *
  * Conventions (pinned by the tests):
  *   - tetrahedra are positively oriented (det[x1-x0, x2-x0, x3-x0] > 0);
@@ -65,6 +66,10 @@ typedef struct {
     void *hip_stream;         /* stream to run on, or NULL for a private one */
     int32_t crossing_cap;     /* faces a particle may cross per step (0 = 64) */
     int32_t resort_every;     /* steps between sorts by tetrahedron (0 = 20) */
+    int32_t precision;        /* FETD_FP64, or FETD_MIXED: FP32 particle state, gather, push
+                                 and march; FP64 barycentrics in flight, deposit, currents
+                                 and field update (charge conservation stays at FP64
+                                 rounding: FP32 products are exact in FP64) */
 } fetd3_opts;
 
 enum {

@@ -57,7 +57,10 @@ struct fetd3_sim {
     bool own_stream = false;
     double dt = 0, eps0 = 0, mu0 = 0, c = 0;
     int spai_level = 1, cap = 64, resort_every = 20;
+    bool fp32 = false;  // mixed mode: FP32 particle state, gather, push and march
     std::string err;
+
+    size_t rb() const { return fp32 ? 4 : 8; }
 
     // mesh (canonical numbering)
     int nn = 0, nt = 0, ne = 0, nf = 0, n_free_e = 0;
@@ -78,6 +81,7 @@ struct fetd3_sim {
     int4 *d_tet_face = nullptr, *d_tet_nbr = nullptr, *d_tet_node = nullptr, *d_face_edge = nullptr;
     uint32_t *d_tet_map = nullptr, *d_tet_ebase = nullptr;
     double *d_grad = nullptr;
+    float *d_grad32 = nullptr;
     int2 *d_edge_nodes = nullptr;
     uint8_t *d_edge_free = nullptr;
     int32_t *d_ef_ptr = nullptr, *d_ef_face = nullptr;
@@ -87,17 +91,19 @@ struct fetd3_sim {
     double *d_nu_val = nullptr, *d_mt_val = nullptr;
     int32_t *d_chunk_sums = nullptr;
     double *d_b = nullptr, *d_bavg = nullptr, *d_h = nullptr, *d_d = nullptr, *d_e = nullptr;
-    double *d_cur = nullptr, *d_cur_last = nullptr, *d_rec = nullptr;
+    double *d_cur = nullptr, *d_cur_last = nullptr;
+    char *d_rec = nullptr;  // [24 nt] reals of the particle precision
     double *d_b_ext = nullptr, *d_e_ext = nullptr;
     double *d_q = nullptr, *d_divd = nullptr, *d_divb = nullptr;
     unsigned long long *d_counters = nullptr;
     int32_t *d_counts = nullptr, *d_cursor = nullptr;
 
-    // particles (two buffers for the sort; SoA with stride p_cap)
+    // particles (two buffers for the sort; SoA with stride p_cap; reals are
+    // double, or float in the mixed mode)
     std::vector<Species3> species;
     int64_t p_cap = 0;
     uint32_t *d_key[2] = {nullptr, nullptr};
-    double *d_lam[2] = {nullptr, nullptr}, *d_u[2] = {nullptr, nullptr};
+    char *d_lam[2] = {nullptr, nullptr}, *d_u[2] = {nullptr, nullptr};  // [3][p_cap] reals
     int32_t *d_pid[2] = {nullptr, nullptr};
     int pbuf = 0;
 
@@ -168,6 +174,17 @@ fetd_status download3(fetd3_sim *s, void *dst, const void *src, size_t bytes)
     hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "download");
+    return FETD_OK;
+}
+
+// count reals of the particle precision from the device, as doubles
+fetd_status download_reals3(fetd3_sim *s, double *dst, const char *src, int64_t count)
+{
+    if (!s->fp32) return download3(s, dst, src, 8 * size_t(count));
+    std::vector<float> tmp(count);
+    fetd_status st = download3(s, tmp.data(), src, 4 * size_t(count));
+    if (st) return st;
+    for (int64_t i = 0; i < count; ++i) dst[i] = double(tmp[i]);
     return FETD_OK;
 }
 
@@ -596,6 +613,10 @@ fetd_status upload_mesh3(fetd3_sim *s)
     if ((st = upload3(s, &s->d_tet_node, tnode.data(), tnode.size()))) return st;
     if ((st = upload3(s, &s->d_tet_map, tm.data(), tm.size()))) return st;
     if ((st = upload3(s, &s->d_grad, s->grad.data(), s->grad.size()))) return st;
+    {
+        std::vector<float> g32(s->grad.begin(), s->grad.end());
+        if ((st = upload3(s, &s->d_grad32, g32.data(), g32.size()))) return st;
+    }
     if ((st = upload3(s, &s->d_face_edge, fe.data(), fe.size()))) return st;
     if ((st = upload3(s, &s->d_ef_ptr, efp.data(), efp.size()))) return st;
     if ((st = upload3(s, &s->d_ef_face, eff.data(), eff.size()))) return st;
@@ -618,7 +639,7 @@ fetd_status upload_mesh3(fetd3_sim *s)
     if ((st = zeros3(s, &s->d_b, nf)) || (st = zeros3(s, &s->d_bavg, nf)) ||
         (st = zeros3(s, &s->d_h, nf)) || (st = zeros3(s, &s->d_d, ne)) ||
         (st = zeros3(s, &s->d_e, ne)) || (st = zeros3(s, &s->d_cur, ne)) ||
-        (st = zeros3(s, &s->d_cur_last, ne)) || (st = zeros3(s, &s->d_rec, size_t(kRec) * nt)) ||
+        (st = zeros3(s, &s->d_cur_last, ne)) || (st = zeros3(s, &s->d_rec, size_t(kRec) * nt * s->rb())) ||
         (st = zeros3(s, &s->d_q, s->nn)) || (st = zeros3(s, &s->d_divd, s->nn)) ||
         (st = zeros3(s, &s->d_divb, nt)) || (st = zeros3(s, &s->d_counters, 4)) ||
         (st = zeros3(s, &s->d_counts, size_t(nt) + 1)) ||
@@ -639,6 +660,7 @@ Mesh3 mesh_view(const fetd3_sim *s)
     m.tet_nbr = s->d_tet_nbr;
     m.tet_map = s->d_tet_map;
     m.grad = s->d_grad;
+    m.grad32 = s->d_grad32;
     m.tet_ebase = s->d_tet_ebase;
     return m;
 }
@@ -662,8 +684,8 @@ fetd_status compute_charge3(fetd3_sim *s)
     for (const Species3 &sp : s->species) {
         if (e != hipSuccess) break;
         e = launch3_charge(s->stream, sp.n, s->d_key[s->pbuf] + sp.offset,
-                           s->d_lam[s->pbuf] + sp.offset, s->p_cap, s->d_tet_node, sp.q * sp.w,
-                           s->d_q);
+                           s->d_lam[s->pbuf] + sp.offset * s->rb(), s->fp32, s->p_cap,
+                           s->d_tet_node, sp.q * sp.w, s->d_q);
     }
     if (e != hipSuccess) return s->hip_fail(e, "charge");
     return FETD_OK;
@@ -700,20 +722,21 @@ fetd_status grow_particles3(fetd3_sim *s, int64_t extra)
     hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "grow");
     for (int b = 0; b < 2; ++b) {
+        const size_t rb = s->rb();
         uint32_t *key = nullptr;
-        double *lam = nullptr, *u = nullptr;
+        char *lam = nullptr, *u = nullptr;
         int32_t *pid = nullptr;
-        if (!s->alloc(&key, cap) || !s->alloc(&lam, 3 * cap) || !s->alloc(&u, 3 * cap) ||
+        if (!s->alloc(&key, cap) || !s->alloc(&lam, 3 * cap * rb) || !s->alloc(&u, 3 * cap * rb) ||
             !s->alloc(&pid, cap))
             return s->fail(FETD_E_OOM, "particle allocation failed");
         e = hipMemsetAsync(key, 0xFF, sizeof(uint32_t) * cap, s->stream);
         if (used > 0 && e == hipSuccess) {
             e = hipMemcpyAsync(key, s->d_key[b], 4 * used, hipMemcpyDeviceToDevice, s->stream);
             for (int c = 0; c < 3 && e == hipSuccess; ++c) {
-                e = hipMemcpyAsync(lam + c * cap, s->d_lam[b] + c * s->p_cap, 8 * used,
+                e = hipMemcpyAsync(lam + c * cap * rb, s->d_lam[b] + c * s->p_cap * rb, rb * used,
                                    hipMemcpyDeviceToDevice, s->stream);
                 if (e == hipSuccess)
-                    e = hipMemcpyAsync(u + c * cap, s->d_u[b] + c * s->p_cap, 8 * used,
+                    e = hipMemcpyAsync(u + c * cap * rb, s->d_u[b] + c * s->p_cap * rb, rb * used,
                                        hipMemcpyDeviceToDevice, s->stream);
             }
             if (e == hipSuccess)
@@ -743,12 +766,13 @@ fetd_status sort_all3(fetd3_sim *s)
         a.n = sp.n;
         a.nt = s->nt;
         a.key_in = s->d_key[cb] + sp.offset;
-        a.lam_in = s->d_lam[cb] + sp.offset;
-        a.u_in = s->d_u[cb] + sp.offset;
+        a.lam_in = s->d_lam[cb] + sp.offset * s->rb();
+        a.u_in = s->d_u[cb] + sp.offset * s->rb();
         a.pid_in = s->d_pid[cb] + sp.offset;
         a.key_out = s->d_key[ob] + sp.offset;
-        a.lam_out = s->d_lam[ob] + sp.offset;
-        a.u_out = s->d_u[ob] + sp.offset;
+        a.lam_out = s->d_lam[ob] + sp.offset * s->rb();
+        a.u_out = s->d_u[ob] + sp.offset * s->rb();
+        a.elem_bytes = int(s->rb());
         a.pid_out = s->d_pid[ob] + sp.offset;
         a.stride_in = a.stride_out = s->p_cap;
         a.counts = s->d_counts;
@@ -802,7 +826,8 @@ fetd_status fetd3_mesh_create(const fetd3_mesh_desc *mesh, const fetd3_opts *opt
     if (!mesh || !opts || !mesh->node_xyz || !mesh->tet_nodes || mesh->n_nodes <= 0 ||
         mesh->n_tets <= 0 || mesh->n_tets > int32_t(kTetMask) || !(opts->dt > 0) ||
         !(opts->eps0 > 0) || !(opts->mu0 > 0) || !(opts->c > 0) || opts->spai_level < 0 ||
-        opts->spai_level > 2 || (mesh->tet_shift && !mesh->period)) {
+        opts->spai_level > 2 || (mesh->tet_shift && !mesh->period) ||
+        (opts->precision != FETD_FP64 && opts->precision != FETD_MIXED)) {
         g_err3 = "invalid mesh description or options";
         return FETD_E_ARG;
     }
@@ -816,6 +841,7 @@ fetd_status fetd3_mesh_create(const fetd3_mesh_desc *mesh, const fetd3_opts *opt
     s->spai_level = opts->spai_level;
     s->cap = opts->crossing_cap > 0 ? opts->crossing_cap : 64;
     s->resort_every = opts->resort_every > 0 ? opts->resort_every : 20;
+    s->fp32 = opts->precision == FETD_MIXED;
     DeviceGuard3 g(s->device);
     fetd_status st = build_topology3(s, mesh);
     if (!st) {
@@ -916,23 +942,29 @@ fetd_status fetd3_particles_load_bary(fetd3_sim *s, double q, double m, double w
     if (n > 0) {
         std::vector<uint32_t> key(n);
         std::vector<int32_t> pid(n);
-        std::vector<double> L(3 * n), U(3 * n);
+        const size_t rb = s->rb();
+        std::vector<char> L(3 * n * rb), U(3 * n * rb);
         for (int64_t i = 0; i < n; ++i) {
             key[i] = uint32_t(tet[i]) | (uint32_t(slot ? slot[i] : 0) << 30);
             pid[i] = int32_t(i);
             for (int c = 0; c < 3; ++c) {
-                L[c * n + i] = lam[3 * i + c];
-                U[c * n + i] = u[3 * i + c];
+                if (s->fp32) {
+                    reinterpret_cast<float *>(L.data())[c * n + i] = float(lam[3 * i + c]);
+                    reinterpret_cast<float *>(U.data())[c * n + i] = float(u[3 * i + c]);
+                } else {
+                    reinterpret_cast<double *>(L.data())[c * n + i] = lam[3 * i + c];
+                    reinterpret_cast<double *>(U.data())[c * n + i] = u[3 * i + c];
+                }
             }
         }
         const int b = s->pbuf;
         hipError_t e = hipMemcpyAsync(s->d_key[b] + used, key.data(), 4 * n,
                                       hipMemcpyHostToDevice, s->stream);
         for (int c = 0; c < 3 && e == hipSuccess; ++c) {
-            e = hipMemcpyAsync(s->d_lam[b] + c * s->p_cap + used, &L[c * n], 8 * n,
+            e = hipMemcpyAsync(s->d_lam[b] + (c * s->p_cap + used) * rb, &L[c * n * rb], rb * n,
                                hipMemcpyHostToDevice, s->stream);
             if (e == hipSuccess)
-                e = hipMemcpyAsync(s->d_u[b] + c * s->p_cap + used, &U[c * n], 8 * n,
+                e = hipMemcpyAsync(s->d_u[b] + (c * s->p_cap + used) * rb, &U[c * n * rb], rb * n,
                                    hipMemcpyHostToDevice, s->stream);
         }
         if (e == hipSuccess)
@@ -964,15 +996,16 @@ fetd_status fetd3_pic_step(fetd3_sim *s, int32_t n_steps, int32_t pusher)
             StageTimer3 tm(s, 0);
             e = launch3_faraday(s->stream, s->nf, s->d_face_edge, s->d_e, s->d_b, s->d_bavg, s->dt);
             if (e == hipSuccess)
-                e = launch3_record(s->stream, s->nt, mv, s->d_e, s->d_e_ext, s->d_bavg, s->d_rec);
+                e = launch3_record(s->stream, s->nt, mv, s->d_e, s->d_e_ext, s->d_bavg, s->d_rec,
+                                   s->fp32);
         }
         if (e != hipSuccess) return s->hip_fail(e, "faraday");
         for (const Species3 &sp : s->species) {
             Step3 a;
             a.n = sp.n;
             a.key = s->d_key[s->pbuf] + sp.offset;
-            a.lam = s->d_lam[s->pbuf] + sp.offset;
-            a.u = s->d_u[s->pbuf] + sp.offset;
+            a.lam = s->d_lam[s->pbuf] + sp.offset * s->rb();
+            a.u = s->d_u[s->pbuf] + sp.offset * s->rb();
             a.rec = s->d_rec;
             a.b_ext = s->d_b_ext;
             a.cur = s->d_cur;
@@ -985,7 +1018,7 @@ fetd_status fetd3_pic_step(fetd3_sim *s, int32_t n_steps, int32_t pusher)
             a.counters = s->d_counters;
             a.stride = s->p_cap;
             StageTimer3 tm(s, 1);
-            e = launch3_particles(s->stream, mv, a, pusher);
+            e = launch3_particles(s->stream, mv, a, pusher, s->fp32);
             ++s->particle_launches;
             if (e != hipSuccess) return s->hip_fail(e, "particles");
         }
@@ -1099,8 +1132,9 @@ fetd_status fetd3_particles_get(fetd3_sim *s, int32_t species, int64_t capacity,
     if ((st = download3(s, key.data(), s->d_key[b] + sp.offset, 4 * n))) return st;
     if ((st = download3(s, pid.data(), s->d_pid[b] + sp.offset, 4 * n))) return st;
     for (int c = 0; c < 3; ++c) {
-        if ((st = download3(s, &L[c * n], s->d_lam[b] + c * s->p_cap + sp.offset, 8 * n))) return st;
-        if ((st = download3(s, &U[c * n], s->d_u[b] + c * s->p_cap + sp.offset, 8 * n))) return st;
+        const size_t off = (c * s->p_cap + sp.offset) * s->rb();
+        if ((st = download_reals3(s, &L[c * n], s->d_lam[b] + off, n))) return st;
+        if ((st = download_reals3(s, &U[c * n], s->d_u[b] + off, n))) return st;
     }
     std::vector<std::pair<int32_t, int64_t>> live;
     live.reserve(n);
@@ -1180,8 +1214,9 @@ fetd_status fetd3_diagnostics(fetd3_sim *s, fetd3_diag *out)
         std::vector<double> U(3 * sp.n);
         if ((st = download3(s, key.data(), s->d_key[s->pbuf] + sp.offset, 4 * sp.n))) return st;
         for (int cc = 0; cc < 3; ++cc)
-            if ((st = download3(s, &U[cc * sp.n], s->d_u[s->pbuf] + cc * s->p_cap + sp.offset,
-                                8 * sp.n)))
+            if ((st = download_reals3(s, &U[cc * sp.n],
+                                      s->d_u[s->pbuf] + (cc * s->p_cap + sp.offset) * s->rb(),
+                                      sp.n)))
                 return st;
         for (int64_t i = 0; i < sp.n; ++i) {
             if (key[i] == kLost) continue;

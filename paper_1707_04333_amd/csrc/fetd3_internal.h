@@ -29,6 +29,7 @@ struct Mesh3 {
     const int4 *tet_nbr;
     const uint32_t *tet_map;
     const double *grad;
+    const float *grad32;  // same in FP32 (mixed mode)
     // edges are numbered on the device in order of first appearance along
     // the tetrahedron order; tet_ebase[t] = edges first met before t
     const uint32_t *tet_ebase;
@@ -51,9 +52,9 @@ struct Step3 {
     int64_t n;
     int64_t stride;     // component stride of lam and u
     uint32_t *key;
-    double *lam;        // [3][stride] stored barycentrics (SoA)
-    double *u;          // [3][stride] momenta (SoA)
-    const double *rec;  // [24 nt]
+    void *lam;          // [3][stride] stored barycentrics (SoA; double, or float when mixed)
+    void *u;            // [3][stride] momenta (SoA; same type)
+    const void *rec;    // [24 nt] gather records (same type)
     const double *b_ext;  // [3 nt] or null
     double *cur;        // [ne]
     double qdt, alpha, dt, c, inv_c2;
@@ -65,10 +66,11 @@ struct Sort3 {
     int64_t n;
     int nt;
     const uint32_t *key_in;
-    const double *lam_in, *u_in;
+    const void *lam_in, *u_in;
     const int32_t *pid_in;
     uint32_t *key_out;
-    double *lam_out, *u_out;
+    void *lam_out, *u_out;
+    int elem_bytes;  // 8 (double) or 4 (float) per component
     int32_t *pid_out;
     int64_t stride_in, stride_out;  // component stride of the SoA arrays
     int32_t *counts;      // [nt + 1]
@@ -87,8 +89,9 @@ struct Sell {
 hipError_t launch3_faraday(hipStream_t s, int nf, const int4 *face_edge, const double *e,
                            double *b, double *bavg, double dt);
 hipError_t launch3_record(hipStream_t s, int nt, const Mesh3 &m, const double *e,
-                          const double *e_ext, const double *bavg, double *rec);
-hipError_t launch3_particles(hipStream_t s, const Mesh3 &m, const Step3 &a, int pusher);
+                          const double *e_ext, const double *bavg, void *rec, bool fp32);
+hipError_t launch3_particles(hipStream_t s, const Mesh3 &m, const Step3 &a, int pusher,
+                             bool fp32);
 hipError_t launch3_hnu(hipStream_t s, int nf, const Sell &m, const double *b, double *h);
 hipError_t launch3_ampere(hipStream_t s, int ne, const int32_t *ef_ptr, const int32_t *ef_face,
                           const uint8_t *edge_free, const double *h, double *cur,
@@ -96,8 +99,8 @@ hipError_t launch3_ampere(hipStream_t s, int ne, const int32_t *ef_ptr, const in
 hipError_t launch3_spmv(hipStream_t s, int ne, const Sell &m, const uint8_t *edge_free,
                         const double *d, double *e);
 hipError_t launch3_sort(hipStream_t s, const Sort3 &a);
-hipError_t launch3_charge(hipStream_t s, int64_t n, const uint32_t *key, const double *lam,
-                          int64_t stride, const int4 *tet_node, double qw, double *q);
+hipError_t launch3_charge(hipStream_t s, int64_t n, const uint32_t *key, const void *lam,
+                          bool fp32, int64_t stride, const int4 *tet_node, double qw, double *q);
 hipError_t launch3_divd(hipStream_t s, int ne, const int2 *edge_nodes, const double *d,
                         double *out);
 hipError_t launch3_divb(hipStream_t s, int nt, const int4 *tet_face, const int32_t *fout_bits,

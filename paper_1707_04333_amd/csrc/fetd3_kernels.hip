@@ -63,10 +63,11 @@ __global__ __launch_bounds__(256) void k3_faraday(int nf, const int4 *__restrict
     bavg[f] = 0.5 * (bn + bo);
 }
 
+template <typename R>
 __global__ __launch_bounds__(256) void k3_record(int nt, Mesh3 m, const double *__restrict__ e,
                                                  const double *__restrict__ e_ext,
                                                  const double *__restrict__ bavg,
-                                                 double *__restrict__ rec)
+                                                 R *__restrict__ rec)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
@@ -113,71 +114,91 @@ __global__ __launch_bounds__(256) void k3_record(int nt, Mesh3 m, const double *
             U[3 * r + x] += beta * xpq[x];
         }
     }
-    double *o = rec + size_t(kRec) * t;
+    R *o = rec + size_t(kRec) * t;
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
-        o[i] = V[i];
-        o[12 + i] = U[i];
+        o[i] = R(V[i]);
+        o[12 + i] = R(U[i]);
     }
 }
 
 // ---------------------------------------------------------------------
 // Pushers (Sec. II.C) for general 3-vectors; eps = alpha E, beta = alpha B.
 // ---------------------------------------------------------------------
+template <typename R>
 struct V3 {
-    double x, y, z;
+    R x, y, z;
 };
-__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ __forceinline__ V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
-__device__ __forceinline__ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ V3 cross(V3 a, V3 b)
+template <typename R>
+__device__ __forceinline__ V3<R> operator+(V3<R> a, V3<R> b)
+{
+    return {a.x + b.x, a.y + b.y, a.z + b.z};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> operator*(R s, V3<R> a)
+{
+    return {s * a.x, s * a.y, s * a.z};
+}
+template <typename R>
+__device__ __forceinline__ R dot(V3<R> a, V3<R> b)
+{
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <typename R>
+__device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b)
 {
     return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 
 // gamma of a momentum: sqrt(1 + |u|^2 / c^2)
-__device__ __forceinline__ double gam(V3 u, double inv_c2) { return sqrt(1.0 + dot(u, u) * inv_c2); }
-
-template <int P>
-__device__ __forceinline__ V3 push3(V3 u, V3 eps, V3 beta, double c, double inv_c2)
+template <typename R>
+__device__ __forceinline__ R gam(V3<R> u, R inv_c2)
 {
+    return sqrt(R(1) + dot(u, u) * inv_c2);
+}
+
+// One momentum update in the precision R (FP64, or FP32 in the mixed mode).
+template <int P, typename R>
+__device__ __forceinline__ V3<R> push3(V3<R> u, V3<R> eps, V3<R> beta, R c, R inv_c2)
+{
+    const R one = R(1);
     if constexpr (P == 2) {
         // Vay: u' = u + 2 eps + v x beta; gamma+ from the implicit midpoint
         // equation; u = s [u' + (u'.t) t + u' x t], t = beta/gamma+.
-        const double g = gam(u, inv_c2);
-        const V3 v = (1.0 / g) * u;
-        const V3 upr = (u + eps + cross(v, beta)) + eps;
-        const double gp = gam(upr, inv_c2);
-        const double bb = dot(beta, beta);
-        const double sig = gp * gp - bb;
-        const double us = dot(upr, beta) / c;
-        const double gn = sqrt(0.5 * (sig + sqrt(sig * sig + 4.0 * (bb + us * us))));
-        const V3 t = (1.0 / gn) * beta;
-        const double sv = 1.0 / (1.0 + dot(t, t));
+        const R g = gam(u, inv_c2);
+        const V3<R> v = (one / g) * u;
+        const V3<R> upr = (u + eps + cross(v, beta)) + eps;
+        const R gp = gam(upr, inv_c2);
+        const R bb = dot(beta, beta);
+        const R sig = gp * gp - bb;
+        const R us = dot(upr, beta) / c;
+        const R gn = sqrt(R(0.5) * (sig + sqrt(sig * sig + R(4) * (bb + us * us))));
+        const V3<R> t = (one / gn) * beta;
+        const R sv = one / (one + dot(t, t));
         return sv * ((upr + dot(upr, t) * t) + cross(upr, t));
     } else {
-        const V3 um = u + eps;
-        double gbar;
+        const V3<R> um = u + eps;
+        R gbar;
         if constexpr (P == 3) {
             // Higuera-Cary: gamma of the midpoint momentum
-            const double bb = dot(beta, beta);
-            const double gm = gam(um, inv_c2);
-            const double sig = gm * gm - bb;
-            const double w = dot(beta, um) / c;
-            gbar = sqrt(0.5 * (sig + sqrt(sig * sig + 4.0 * (bb + w * w))));
+            const R bb = dot(beta, beta);
+            const R gm = gam(um, inv_c2);
+            const R sig = gm * gm - bb;
+            const R w = dot(beta, um) / c;
+            gbar = sqrt(R(0.5) * (sig + sqrt(sig * sig + R(4) * (bb + w * w))));
         } else {
             gbar = gam(um, inv_c2);
         }
-        V3 t;
+        V3<R> t;
         if constexpr (P == 1) {
             // Boris with the tangent correction of the rotation angle
-            const double bm = sqrt(dot(beta, beta));
-            t = bm > 0.0 ? (tan(bm / gbar) / bm) * beta : V3{0.0, 0.0, 0.0};
+            const R bm = sqrt(dot(beta, beta));
+            t = bm > R(0) ? (tan(bm / gbar) / bm) * beta : V3<R>{R(0), R(0), R(0)};
         } else {
-            t = (1.0 / gbar) * beta;
+            t = (one / gbar) * beta;
         }
-        const V3 s = (2.0 / (1.0 + dot(t, t))) * t;
-        const V3 up = um + cross(um, t);
+        const V3<R> s = (R(2) / (one + dot(t, t))) * t;
+        const V3<R> up = um + cross(um, t);
         return (um + cross(up, s)) + eps;
     }
 }
@@ -275,23 +296,32 @@ __device__ __forceinline__ void wave_segmented_sum6(double (&c)[6], int lane, in
 // Exit test of one piece: dL_k = grad l_k . r for the four faces, the face
 // with the smallest tau_k = max(l_k, 0)/(-dL_k) among dL_k < 0 (not the
 // face just entered; ties to the smaller k), or ks = -1.
-__device__ __forceinline__ void exit_face(const double *__restrict__ G, double rx, double ry,
-                                          double rz, const double (&L)[4], int entry,
-                                          double (&dL)[4], int &ks, double &ts)
+template <typename R>
+__device__ __forceinline__ void exit_face(const R *__restrict__ G, R rx, R ry, R rz,
+                                          const double (&L)[4], int entry, R (&dL)[4], int &ks,
+                                          R &ts)
 {
 #pragma unroll
     for (int k = 0; k < 4; ++k) dL[k] = G[3 * k] * rx + G[3 * k + 1] * ry + G[3 * k + 2] * rz;
     ks = -1;
-    ts = 0.0;
+    ts = R(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (k == entry || !(dL[k] < 0.0)) continue;
-        const double tk = (L[k] > 0.0 ? L[k] : 0.0) / (-dL[k]);
+        if (k == entry || !(dL[k] < R(0))) continue;
+        const R lk = R(L[k]);
+        const R tk = (lk > R(0) ? lk : R(0)) / (-dL[k]);
         if (ks < 0 || tk < ts) {
             ks = k;
             ts = tk;
         }
     }
+}
+
+// value of a[i] for a runtime i in 0..3 (precision R)
+template <typename R>
+__device__ __forceinline__ R pickR(const R (&a)[4], int i)
+{
+    return i == 0 ? a[0] : i == 1 ? a[1] : i == 2 ? a[2] : a[3];
 }
 
 // W1 weights l_a^s l_b^f - l_a^f l_b^s of the six local edges of a piece.
@@ -303,11 +333,87 @@ __device__ __forceinline__ void piece_weights(const double (&Ls)[4], const doubl
     for (int k = 0; k < 6; ++k) w[k] = Ls[ea[k]] * Lf[eb[k]] - Lf[ea[k]] * Ls[eb[k]];
 }
 
+// Continue a particle that crossed a face: march and deposit piece by piece
+// (pieces 2, 3, ... of the step).  Barycentrics are carried in FP64 so that
+// every piece ends where the next one starts and they sum to 1 exactly;
+// the march itself runs in the precision R.
+template <typename R>
+__device__ __forceinline__ void continue_move(const Mesh3 &m, const Step3 &a, const Window3 &win,
+                                              const R *__restrict__ grad, int64_t p, int t, int r,
+                                              int entry, double (&L)[4], R rx, R ry, R rz,
+                                              unsigned long long &pieces,
+                                              unsigned long long &lost_here)
+{
+    const int64_t n = a.stride;
+    R *lam = static_cast<R *>(a.lam);
+    bool fin = false;
+    for (int it = 1; it < a.cap; ++it) {
+        const int32_t *te = m.tet_edge + 8 * size_t(t);
+        const int bits = te[6];
+        R dL[4];
+        int ks;
+        R ts;
+        exit_face(grad + 12 * size_t(t), rx, ry, rz, L, entry, dL, ks, ts);
+        double Lf[4];
+        ++pieces;
+        if (ks < 0 || ts >= R(1)) {
+            const int i1 = (r + 1) & 3, i2 = (r + 2) & 3, i3 = (r + 3) & 3;
+            const R f1 = R(pick4(L, i1)) + pickR(dL, i1);
+            const R f2 = R(pick4(L, i2)) + pickR(dL, i2);
+            const R f3 = R(pick4(L, i3)) + pickR(dL, i3);
+            unpack_lambda(r, double(f1), double(f2), double(f3), Lf);
+            deposit_piece(te, bits, L, Lf, a.qdt, win);
+            a.key[p] = uint32_t(t) | (uint32_t(r) << 30);
+            lam[p] = f1;
+            lam[n + p] = f2;
+            lam[2 * n + p] = f3;
+            fin = true;
+            break;
+        }
+        const int kp = (ks + 1) & 3, kq = (ks + 2) & 3, kw = (ks + 3) & 3;
+        const R lp = R(pick4(L, kp)) + ts * pickR(dL, kp);
+        const R lq = R(pick4(L, kq)) + ts * pickR(dL, kq);
+        const double lw = (1.0 - double(lp)) - double(lq);
+        Lf[0] = Lf[1] = Lf[2] = Lf[3] = 0.0;
+        put4(Lf, kp, double(lp));
+        put4(Lf, kq, double(lq));
+        put4(Lf, kw, lw);
+        deposit_piece(te, bits, L, Lf, a.qdt, win);
+        const int4 nb4 = m.tet_nbr[t];
+        const int nb = ks == 0 ? nb4.x : ks == 1 ? nb4.y : ks == 2 ? nb4.z : nb4.w;
+        if (nb < 0) {
+            // wall: removed after depositing up to it
+            a.key[p] = kLost;
+            ++lost_here;
+            fin = true;
+            break;
+        }
+        const uint32_t mp = (m.tet_map[t] >> (8 * ks)) & 0xFFu;
+        L[0] = L[1] = L[2] = L[3] = 0.0;
+        put4(L, int(mp & 3), double(lp));
+        put4(L, int((mp >> 2) & 3), double(lq));
+        put4(L, int((mp >> 4) & 3), lw);
+        r = int((mp >> 4) & 3);
+        entry = int(mp >> 6);
+        t = nb;
+        const R sc = R(1) - ts;
+        rx *= sc;
+        ry *= sc;
+        rz *= sc;
+    }
+    if (!fin) {
+        atomicOr(a.counters + 2, 1ull);
+        atomicMin(a.counters + 3, (unsigned long long)p);
+    }
+}
+
 // One particle block: phase A (every lane: gather, push, first piece), a
 // wavefront sum of the first-piece currents over runs of equal start
 // tetrahedron (particles are sorted by tetrahedron), then phase B for the
-// particles that crossed a face, depositing piece by piece.
-template <int P>
+// particles that crossed a face, depositing piece by piece.  R is the
+// precision of the particle state, gather, push and march (FP64, or FP32 in
+// the mixed mode); barycentrics in flight and all currents are FP64.
+template <int P, typename R>
 __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
 {
     const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -332,37 +438,46 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
     __syncthreads();
     const Window3 win{s_win, s_hkey, s_hval, a.cur, s_base};
     const int64_t n = a.stride;
+    R *lam = static_cast<R *>(a.lam);
+    R *u = static_cast<R *>(a.u);
+    const R *rec = static_cast<const R *>(a.rec);
+    const R *grad = static_cast<const R *>(sizeof(R) == 4 ? static_cast<const void *>(m.grad32)
+                                                          : static_cast<const void *>(m.grad));
 
     // ---- phase A
     bool moving = false;
     int t = 0, r = 0;
     double L[4] = {0.0, 0.0, 0.0, 0.0};
-    double rx = 0.0, ry = 0.0, rz = 0.0;
+    R rx = R(0), ry = R(0), rz = R(0);
     if (p < a.n) {
         const uint32_t key = a.key[p];
         if (key != kLost) {
             t = int(key & kTetMask);
             r = int(key >> 30);
-            unpack_lambda(r, a.lam[p], a.lam[n + p], a.lam[2 * n + p], L);
-            const double *rc = a.rec + size_t(kRec) * t;
-            V3 E{0.0, 0.0, 0.0}, B{0.0, 0.0, 0.0};
+            unpack_lambda(r, double(lam[p]), double(lam[n + p]), double(lam[2 * n + p]), L);
+            const R *rc = rec + size_t(kRec) * t;
+            V3<R> E{R(0), R(0), R(0)}, B{R(0), R(0), R(0)};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                E = E + L[k] * V3{rc[3 * k], rc[3 * k + 1], rc[3 * k + 2]};
-                B = B + L[k] * V3{rc[12 + 3 * k], rc[13 + 3 * k], rc[14 + 3 * k]};
+                const R lk = R(L[k]);
+                E = E + lk * V3<R>{rc[3 * k], rc[3 * k + 1], rc[3 * k + 2]};
+                B = B + lk * V3<R>{rc[12 + 3 * k], rc[13 + 3 * k], rc[14 + 3 * k]};
             }
-            if (a.b_ext) B = B + V3{a.b_ext[3 * t], a.b_ext[3 * t + 1], a.b_ext[3 * t + 2]};
-            const V3 u0{a.u[p], a.u[n + p], a.u[2 * n + p]};
-            const V3 u1 = push3<P>(u0, a.alpha * E, a.alpha * B, a.c, a.inv_c2);
-            a.u[p] = u1.x;
-            a.u[n + p] = u1.y;
-            a.u[2 * n + p] = u1.z;
+            if (a.b_ext)
+                B = B + V3<R>{R(a.b_ext[3 * t]), R(a.b_ext[3 * t + 1]), R(a.b_ext[3 * t + 2])};
+            const V3<R> u0{u[p], u[n + p], u[2 * n + p]};
+            const R al = R(a.alpha);
+            const V3<R> u1 = push3<P, R>(u0, al * E, al * B, R(a.c), R(a.inv_c2));
+            u[p] = u1.x;
+            u[n + p] = u1.y;
+            u[2 * n + p] = u1.z;
             if (isfinite(u1.x) && isfinite(u1.y) && isfinite(u1.z)) {
                 moving = a.cap > 0;
-                const double g = gam(u1, a.inv_c2);
-                rx = a.dt * u1.x / g;
-                ry = a.dt * u1.y / g;
-                rz = a.dt * u1.z / g;
+                const R g = gam(u1, R(a.inv_c2));
+                const R dt = R(a.dt);
+                rx = dt * u1.x / g;
+                ry = dt * u1.y / g;
+                rz = dt * u1.z / g;
             } else {
                 // a bad particle is left where it is
                 atomicOr(a.counters + 2, 2ull);
@@ -380,31 +495,31 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
 #pragma unroll
         for (int k = 0; k < 6; ++k) te0[k] = te[k];
         bits0 = te[6];
-        double dL[4];
+        R dL[4];
         int ks;
-        double ts;
-        exit_face(m.grad + 12 * size_t(t), rx, ry, rz, L, -1, dL, ks, ts);
+        R ts;
+        exit_face(grad + 12 * size_t(t), rx, ry, rz, L, -1, dL, ks, ts);
         ++pieces;
         double Lf[4];
-        if (ks < 0 || ts >= 1.0) {
+        if (ks < 0 || ts >= R(1)) {
             const int i1 = (r + 1) & 3, i2 = (r + 2) & 3, i3 = (r + 3) & 3;
-            const double f1 = pick4(L, i1) + pick4(dL, i1);
-            const double f2 = pick4(L, i2) + pick4(dL, i2);
-            const double f3 = pick4(L, i3) + pick4(dL, i3);
-            unpack_lambda(r, f1, f2, f3, Lf);
+            const R f1 = R(pick4(L, i1)) + pickR(dL, i1);
+            const R f2 = R(pick4(L, i2)) + pickR(dL, i2);
+            const R f3 = R(pick4(L, i3)) + pickR(dL, i3);
+            unpack_lambda(r, double(f1), double(f2), double(f3), Lf);
             piece_weights(L, Lf, c);
             a.key[p] = uint32_t(t) | (uint32_t(r) << 30);
-            a.lam[p] = f1;
-            a.lam[n + p] = f2;
-            a.lam[2 * n + p] = f3;
+            lam[p] = f1;
+            lam[n + p] = f2;
+            lam[2 * n + p] = f3;
         } else {
             const int kp = (ks + 1) & 3, kq = (ks + 2) & 3, kw = (ks + 3) & 3;
-            const double lp = pick4(L, kp) + ts * pick4(dL, kp);
-            const double lq = pick4(L, kq) + ts * pick4(dL, kq);
-            const double lw = (1.0 - lp) - lq;
+            const R lp = R(pick4(L, kp)) + ts * pickR(dL, kp);
+            const R lq = R(pick4(L, kq)) + ts * pickR(dL, kq);
+            const double lw = (1.0 - double(lp)) - double(lq);
             Lf[0] = Lf[1] = Lf[2] = Lf[3] = 0.0;
-            put4(Lf, kp, lp);
-            put4(Lf, kq, lq);
+            put4(Lf, kp, double(lp));
+            put4(Lf, kq, double(lq));
             put4(Lf, kw, lw);
             piece_weights(L, Lf, c);
             const int4 nb4 = m.tet_nbr[t];
@@ -416,13 +531,13 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
             } else {
                 const uint32_t mp = (m.tet_map[t] >> (8 * ks)) & 0xFFu;
                 L[0] = L[1] = L[2] = L[3] = 0.0;
-                put4(L, int(mp & 3), lp);
-                put4(L, int((mp >> 2) & 3), lq);
+                put4(L, int(mp & 3), double(lp));
+                put4(L, int((mp >> 2) & 3), double(lq));
                 put4(L, int((mp >> 4) & 3), lw);
                 r = int((mp >> 4) & 3);
                 entry = int(mp >> 6);
                 t = nb;
-                const double sc = 1.0 - ts;
+                const R sc = R(1) - ts;
                 rx *= sc;
                 ry *= sc;
                 rz *= sc;
@@ -448,68 +563,9 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
     }
 
     // ---- phase B: the particles that crossed a face
-    if (more) {
-        bool fin = false;
-        for (int it = 1; it < a.cap; ++it) {
-            const int32_t *te = m.tet_edge + 8 * size_t(t);
-            const int bits = te[6];
-            double dL[4];
-            int ks;
-            double ts;
-            exit_face(m.grad + 12 * size_t(t), rx, ry, rz, L, entry, dL, ks, ts);
-            double Lf[4];
-            ++pieces;
-            if (ks < 0 || ts >= 1.0) {
-                const int i1 = (r + 1) & 3, i2 = (r + 2) & 3, i3 = (r + 3) & 3;
-                const double f1 = pick4(L, i1) + pick4(dL, i1);
-                const double f2 = pick4(L, i2) + pick4(dL, i2);
-                const double f3 = pick4(L, i3) + pick4(dL, i3);
-                unpack_lambda(r, f1, f2, f3, Lf);
-                deposit_piece(te, bits, L, Lf, a.qdt, win);
-                a.key[p] = uint32_t(t) | (uint32_t(r) << 30);
-                a.lam[p] = f1;
-                a.lam[n + p] = f2;
-                a.lam[2 * n + p] = f3;
-                fin = true;
-                break;
-            }
-            const int kp = (ks + 1) & 3, kq = (ks + 2) & 3, kw = (ks + 3) & 3;
-            const double lp = pick4(L, kp) + ts * pick4(dL, kp);
-            const double lq = pick4(L, kq) + ts * pick4(dL, kq);
-            const double lw = (1.0 - lp) - lq;
-            Lf[0] = Lf[1] = Lf[2] = Lf[3] = 0.0;
-            put4(Lf, kp, lp);
-            put4(Lf, kq, lq);
-            put4(Lf, kw, lw);
-            deposit_piece(te, bits, L, Lf, a.qdt, win);
-            const int4 nb4 = m.tet_nbr[t];
-            const int nb = ks == 0 ? nb4.x : ks == 1 ? nb4.y : ks == 2 ? nb4.z : nb4.w;
-            if (nb < 0) {
-                a.key[p] = kLost;
-                ++lost_here;
-                fin = true;
-                break;
-            }
-            const uint32_t mp = (m.tet_map[t] >> (8 * ks)) & 0xFFu;
-            L[0] = L[1] = L[2] = L[3] = 0.0;
-            put4(L, int(mp & 3), lp);
-            put4(L, int((mp >> 2) & 3), lq);
-            put4(L, int((mp >> 4) & 3), lw);
-            r = int((mp >> 4) & 3);
-            entry = int(mp >> 6);
-            t = nb;
-            const double sc = 1.0 - ts;
-            rx *= sc;
-            ry *= sc;
-            rz *= sc;
-        }
-        if (!fin) {
-            atomicOr(a.counters + 2, 1ull);
-            atomicMin(a.counters + 3, (unsigned long long)p);
-        }
-    }
+    if (more) continue_move<R>(m, a, win, grad, p, t, r, entry, L, rx, ry, rz, pieces, lost_here);
 
-    // flush the window (nonzero entries were deposited at valid edge ids)
+    // flush the window and the table (non-zero entries hold valid edge ids)
     __syncthreads();
     for (int j = threadIdx.x; j < kWin3; j += blockDim.x) {
         const double v = s_win[j];
@@ -674,6 +730,7 @@ __global__ __launch_bounds__(1024) void k3_scan_add(int n, int32_t *__restrict__
 
 // ... and scatter of every live particle to the next free place of its
 // tetrahedron (order within a tetrahedron is arbitrary).
+template <typename R>
 __global__ __launch_bounds__(256) void k3_sort_scatter(Sort3 a)
 {
     const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -683,15 +740,18 @@ __global__ __launch_bounds__(256) void k3_sort_scatter(Sort3 a)
     const int64_t q = atomicAdd(a.cursor + (k & kTetMask), 1);
     a.key_out[q] = k;
     a.pid_out[q] = a.pid_in[p];
+    const R *li = static_cast<const R *>(a.lam_in), *ui = static_cast<const R *>(a.u_in);
+    R *lo = static_cast<R *>(a.lam_out), *uo = static_cast<R *>(a.u_out);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        a.lam_out[c * a.stride_out + q] = a.lam_in[c * a.stride_in + p];
-        a.u_out[c * a.stride_out + q] = a.u_in[c * a.stride_in + p];
+        lo[c * a.stride_out + q] = li[c * a.stride_in + p];
+        uo[c * a.stride_out + q] = ui[c * a.stride_in + p];
     }
 }
 
+template <typename R>
 __global__ __launch_bounds__(256) void k3_charge(int64_t n, const uint32_t *__restrict__ key,
-                                                 const double *__restrict__ lam, int64_t stride,
+                                                 const R *__restrict__ lam, int64_t stride,
                                                  const int4 *__restrict__ tet_node, double qw,
                                                  double *__restrict__ q)
 {
@@ -700,7 +760,8 @@ __global__ __launch_bounds__(256) void k3_charge(int64_t n, const uint32_t *__re
     const uint32_t k = key[p];
     if (k == kLost) return;
     double L[4];
-    unpack_lambda(int(k >> 30), lam[p], lam[stride + p], lam[2 * stride + p], L);
+    unpack_lambda(int(k >> 30), double(lam[p]), double(lam[stride + p]), double(lam[2 * stride + p]),
+                  L);
     const int4 tn = tet_node[k & kTetMask];
     atomic_add_f64(q + tn.x, qw * L[0]);
     atomic_add_f64(q + tn.y, qw * L[1]);
@@ -747,24 +808,37 @@ hipError_t launch3_faraday(hipStream_t s, int nf, const int4 *face_edge, const d
 }
 
 hipError_t launch3_record(hipStream_t s, int nt, const Mesh3 &m, const double *e,
-                          const double *e_ext, const double *bavg, double *rec)
+                          const double *e_ext, const double *bavg, void *rec, bool fp32)
 {
     if (nt <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k3_record, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, m, e, e_ext, bavg,
-                       rec);
+    if (fp32)
+        hipLaunchKernelGGL(k3_record<float>, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, m, e,
+                           e_ext, bavg, static_cast<float *>(rec));
+    else
+        hipLaunchKernelGGL(k3_record<double>, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, m, e,
+                           e_ext, bavg, static_cast<double *>(rec));
     return hipGetLastError();
 }
 
-hipError_t launch3_particles(hipStream_t s, const Mesh3 &m, const Step3 &a, int pusher)
+template <typename R>
+void launch3_particles_t(hipStream_t s, const Mesh3 &m, const Step3 &a, int pusher)
 {
-    if (a.n <= 0) return hipSuccess;
     const dim3 grid(grid_for(a.n, kBlock)), block(kBlock);
     switch (pusher) {
-    case 0: hipLaunchKernelGGL(k3_particles<0>, grid, block, 0, s, m, a); break;
-    case 1: hipLaunchKernelGGL(k3_particles<1>, grid, block, 0, s, m, a); break;
-    case 2: hipLaunchKernelGGL(k3_particles<2>, grid, block, 0, s, m, a); break;
-    default: hipLaunchKernelGGL(k3_particles<3>, grid, block, 0, s, m, a); break;
+    case 0: hipLaunchKernelGGL((k3_particles<0, R>), grid, block, 0, s, m, a); break;
+    case 1: hipLaunchKernelGGL((k3_particles<1, R>), grid, block, 0, s, m, a); break;
+    case 2: hipLaunchKernelGGL((k3_particles<2, R>), grid, block, 0, s, m, a); break;
+    default: hipLaunchKernelGGL((k3_particles<3, R>), grid, block, 0, s, m, a); break;
     }
+}
+
+hipError_t launch3_particles(hipStream_t s, const Mesh3 &m, const Step3 &a, int pusher, bool fp32)
+{
+    if (a.n <= 0) return hipSuccess;
+    if (fp32)
+        launch3_particles_t<float>(s, m, a, pusher);
+    else
+        launch3_particles_t<double>(s, m, a, pusher);
     return hipGetLastError();
 }
 
@@ -807,16 +881,23 @@ hipError_t launch3_sort(hipStream_t s, const Sort3 &a)
                        a.chunk_sums);
     hipLaunchKernelGGL(k3_scan_totals, dim3(1), dim3(1024), 0, s, nchunk, a.chunk_sums);
     hipLaunchKernelGGL(k3_scan_add, dim3(nchunk), dim3(1024), 0, s, n1, a.cursor, a.chunk_sums);
-    hipLaunchKernelGGL(k3_sort_scatter, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+    if (a.elem_bytes == 4)
+        hipLaunchKernelGGL(k3_sort_scatter<float>, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k3_sort_scatter<double>, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch3_charge(hipStream_t s, int64_t n, const uint32_t *key, const double *lam,
-                          int64_t stride, const int4 *tet_node, double qw, double *q)
+hipError_t launch3_charge(hipStream_t s, int64_t n, const uint32_t *key, const void *lam,
+                          bool fp32, int64_t stride, const int4 *tet_node, double qw, double *q)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k3_charge, dim3(grid_for(n, 256)), dim3(256), 0, s, n, key, lam, stride,
-                       tet_node, qw, q);
+    if (fp32)
+        hipLaunchKernelGGL(k3_charge<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, key,
+                           static_cast<const float *>(lam), stride, tet_node, qw, q);
+    else
+        hipLaunchKernelGGL(k3_charge<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, key,
+                           static_cast<const double *>(lam), stride, tet_node, qw, q);
     return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ import ctypes
 
 import numpy as np
 
-from .fetdpic import PUSHERS, FetdError, lib as _base_lib
+from .fetdpic import PRECISIONS, PUSHERS, FetdError, lib as _base_lib
 
 FIELDS = {"e": 0, "d": 1, "b": 2, "j": 3, "q": 4, "divd": 5, "divb": 6, "edges": 7, "faces": 8,
           "spai_ptr": 9, "spai_col": 10, "spai_val": 11}
@@ -28,7 +28,8 @@ class Opts3(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("eps0", ctypes.c_double), ("mu0", ctypes.c_double),
                 ("c", ctypes.c_double), ("spai_level", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("crossing_cap", ctypes.c_int32), ("resort_every", ctypes.c_int32)]
+                ("crossing_cap", ctypes.c_int32), ("resort_every", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
 
 
 class Diag3(ctypes.Structure):
@@ -86,7 +87,7 @@ class Sim3:
     """Owning wrapper of one tetrahedral simulation handle."""
 
     def __init__(self, mesh, dt, eps0, mu0, c, spai_level=1, device=0, crossing_cap=64,
-                 resort_every=20):
+                 resort_every=20, precision="fp64"):
         xyz = np.ascontiguousarray(mesh.node_xyz, dtype=np.float64)
         tet = np.ascontiguousarray(mesh.tet_nodes, dtype=np.int32)
         sh = None if mesh.tet_shift is None else np.ascontiguousarray(mesh.tet_shift, dtype=np.int8)
@@ -101,7 +102,8 @@ class Sim3:
         except ImportError:
             pass
         opts = Opts3(float(dt), float(eps0), float(mu0), float(c), int(spai_level), int(device),
-                     stream, int(crossing_cap), int(resort_every))
+                     stream, int(crossing_cap), int(resort_every),
+                     PRECISIONS[precision] if isinstance(precision, str) else int(precision))
         h = ctypes.c_void_p()
         _check(lib().fetd3_mesh_create(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h)))
         self.h = h

@@ -165,3 +165,46 @@ def test_tet_error_paths():
         g.sync()
     assert ei.value.status == FETD_E_TRACK
     g.close()
+
+
+def _percentile_errors3(osim, g):
+    el, eu, mis, total = [], [], 0, 0
+    us = max(float(np.abs(s.u).max()) for s in osim.species)
+    for si, s in enumerate(osim.species):
+        gp = g.particles(si)
+        alive = np.nonzero(s.tet >= 0)[0]
+        assert np.array_equal(gp["id"], alive), "lost sets differ"
+        same = (gp["tet"] == s.tet[alive]) & (gp["slot"] == s.slot[alive])
+        mis += int((~same).sum())
+        total += alive.size
+        el.append(np.abs(gp["lam"][same] - s.lam[alive][same]).max(axis=1))
+        eu.append(np.abs(gp["u"][same] - s.u[alive][same]).max(axis=1) / us)
+    el, eu = np.concatenate(el), np.concatenate(eu)
+    return mis, total, np.percentile(el, [50, 99, 100]), np.percentile(eu, [50, 99, 100])
+
+
+def test_tet_mixed_precision_gauss_and_error(O3):
+    """Mixed mode (FP32 particle state, gather, push and march; FP64
+    barycentrics in flight, deposit and fields) against the FP64 oracle:
+    Gauss's law and S b stay at FP64 rounding; without self-fields every
+    particle agrees to FP32 accuracy; with them the bulk (99th percentile)
+    and the kinetic energy are bounded."""
+    w = J.tet_pair_plasma(n_side=8, length=0.008, n_pairs=20_000, theta=0.3)
+    weak = J.tet_pair_plasma(n_side=8, length=0.008, n_pairs=20_000, theta=0.3)
+    for s in weak.species:
+        s.w = 1e-6
+    for wl, tol in ((weak, None), (w, 1e-4)):
+        osim = _o(O3, wl)
+        g = _g(wl, precision="mixed", resort_every=9)
+        osim.step(30, "boris")
+        g.step(30, "boris")
+        d = g.diagnostics()
+        assert d["gauss_rel"] <= 1e-12 and d["divb_rel"] <= 1e-13, d
+        mis, total, el, eu = _percentile_errors3(osim, g)
+        assert mis <= 1e-3 * total, mis
+        if tol is None:
+            assert el[2] <= 2e-5 and eu[2] <= 2e-6, (el, eu)
+        else:
+            assert el[1] <= tol and eu[1] <= tol, (el, eu)
+            assert abs(d["W_kin"] / osim.energies()[2] - 1) < 1e-4
+        g.close()
