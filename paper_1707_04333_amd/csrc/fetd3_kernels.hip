@@ -663,14 +663,29 @@ __global__ __launch_bounds__(256) void k3_spmv(int ne, const int32_t *__restrict
     e[ed] = acc;
 }
 
-// Counting sort: histogram of live keys per tetrahedron ...
+// Counting sort: histogram of live keys per tetrahedron.  The particles
+// are nearly sorted already, so a wavefront first finds its runs of equal
+// tetrahedron and the last lane of each run adds the run's length.
+__device__ __forceinline__ void wave_runs(uint32_t k, int lane, int &head_lane, bool &tail)
+{
+    const uint32_t kprev = __shfl_up(k, 1, 64);
+    const bool head = lane == 0 || kprev != k;
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long below = hm & ((2ull << lane) - 1ull);
+    head_lane = 63 - __clzll(below);
+    tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
+}
+
 __global__ __launch_bounds__(256) void k3_sort_count(int64_t n, const uint32_t *__restrict__ key,
                                                      int32_t *__restrict__ counts)
 {
     const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t k = key[p];
-    if (k != kLost) atomicAdd(counts + (k & kTetMask), 1);
+    const int lane = threadIdx.x & 63;
+    const uint32_t k = p < n ? key[p] : kLost;
+    int head_lane;
+    bool tail;
+    wave_runs(k, lane, head_lane, tail);
+    if (tail && k != kLost) atomicAdd(counts + (k & kTetMask), lane - head_lane + 1);
 }
 
 // ... exclusive scan of counts[0..nt] into cursor: each block of 1024
@@ -728,16 +743,28 @@ __global__ __launch_bounds__(1024) void k3_scan_add(int n, int32_t *__restrict__
     if (i < n) cursor[i] += sums[blockIdx.x];
 }
 
-// ... and scatter of every live particle to the next free place of its
-// tetrahedron (order within a tetrahedron is arbitrary).
+// ... and scatter of every live particle to the next free places of its
+// tetrahedron: the first lane of a wavefront run reserves the run's places
+// with one atomic, the others follow it in lane order.
 template <typename R>
 __global__ __launch_bounds__(256) void k3_sort_scatter(Sort3 a)
 {
     const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    const uint32_t k = a.key_in[p];
+    const int lane = threadIdx.x & 63;
+    const uint32_t k = p < a.n ? a.key_in[p] : kLost;
+    int head_lane;
+    bool tail;
+    wave_runs(k, lane, head_lane, tail);
+    // run length seen from the head: the tail lane's distance to it
+    const unsigned long long tm = __ballot(tail);
+    const unsigned long long at_or_above = tm & ~((1ull << lane) - 1ull);
+    const int tail_lane = __ffsll(static_cast<long long>(at_or_above)) - 1;
+    int base = 0;
+    if (lane == head_lane && k != kLost)
+        base = atomicAdd(a.cursor + (k & kTetMask), tail_lane - lane + 1);
+    base = __shfl(base, head_lane, 64);
     if (k == kLost) return;
-    const int64_t q = atomicAdd(a.cursor + (k & kTetMask), 1);
+    const int64_t q = int64_t(base) + (lane - head_lane);
     a.key_out[q] = k;
     a.pid_out[q] = a.pid_in[p];
     const R *li = static_cast<const R *>(a.lam_in), *ui = static_cast<const R *>(a.u_in);
