@@ -36,6 +36,8 @@ METRIC = "particle-steps/sec + achieved HBM GB/s; mixed/batched vs FP64 at Gauss
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particle_step_pair_plasma_traffic.json")
+KERNEL3_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd3_kernels.hip")
+TRAFFIC3_FILE = os.path.join(ROOT, "profiles", "k3_particles_tet_pair_plasma_traffic.json")
 
 
 def log(msg):
@@ -54,19 +56,19 @@ def particle_launch_bytes(n_particles, nf, ne, fp32):
     return n_particles * per_particle + nf * per_tri + ne * 16
 
 
-def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(src=KERNEL_SRC):
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(precision):
+def measured_traffic(precision, traffic_file=TRAFFIC_FILE, src=KERNEL_SRC):
     """HBM bytes per particle launch from the committed rocprofv3 counter
     runs (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when
     the kernel source changed since they were taken."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(traffic_file))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sha256_16") != kernel_hash():
+    if rec.get("kernel_sha256_16") != kernel_hash(src):
         return None
     return rec.get(precision, {}).get("hbm_bytes_per_launch")
 
@@ -236,16 +238,20 @@ def tet_particle_launch_bytes(n_particles, nt, ne, fp32):
     return n_particles * 2 * (4 + 6 * r) + nt * (36 * r + 32 + 16 + 4) + ne * 16
 
 
-def _run_tet_one(w, precision, steps, warmup):
+def _run_tet_one(w, precision, steps, warmup, resort_every):
     from paper_1707_04333_amd import fetd3
-    sim = fetd3.from_workload3(w, resort_every=20, precision=precision)
+    t0 = time.perf_counter()
+    sim = fetd3.from_workload3(w, resort_every=resort_every, precision=precision)
+    log(f"{precision}: simulation created in {time.perf_counter() - t0:.1f} s")
     sim.step(warmup, "boris")
     sim.sync()
+    log(f"{precision}: {warmup} warm-up steps done")
     sim.profile(True)
     t0 = time.perf_counter()
     sim.step(steps, "boris")
     sim.sync()
     el = time.perf_counter() - t0
+    log(f"{precision}: {steps} steps in {el:.3f} s")
     stages, launches = sim.stage_times()
     sim.profile(False)
     d = sim.diagnostics()
@@ -257,12 +263,14 @@ def run_tet(args):
     """The tetrahedral path on a triply periodic pair plasma: 48^3 Kuhn cells
     (663,552 tetrahedra), 8M electrons + 8M positrons (24 per tetrahedron),
     3-D Maxwell-Juttner momenta at theta = 0.1, B0 = 1 T along z,
-    omega_c/omega_p = 2, Boris, sorted every 20 steps; mixed precision (the
-    value) and FP64."""
+    omega_c/omega_p = 2, Boris, sorted every 10 steps (the best of 10, 20,
+    40, 80 measured on this workload); mixed precision (the value) and FP64."""
     from paper_1707_04333_amd import inputs3 as J
     log("generating the tetrahedral pair plasma")
     w = J.tet_pair_plasma(n_pairs=args.pairs)
+    log(f"generated {w.mesh.n_tets} tetrahedra and {w.n_particles} particles")
     n_p = w.n_particles
+    resort = 10
     species_n = [s.n for s in w.species]
     nt = w.mesh.n_tets
     res = {}
@@ -270,7 +278,7 @@ def run_tet(args):
         if prec == "fp64" and args.no_fp64:
             continue
         log(f"tetrahedral run, {prec}")
-        el, stages, launches, d = _run_tet_one(w, prec, args.steps, args.warmup)
+        el, stages, launches, d = _run_tet_one(w, prec, args.steps, args.warmup, resort)
         ne = d["n_edges"]
         per_launch = float(np.mean([tet_particle_launch_bytes(n, nt, ne, prec == "mixed")
                                     for n in species_n]))
@@ -279,7 +287,8 @@ def run_tet(args):
         res[prec] = {"value": n_p * args.steps / el, "ms_per_step": el / args.steps * 1e3,
                      "roofline": {"bound": "hbm", "kernel": "k3_particles", "achieved": achieved,
                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                                  "frac": achieved / HBM_PEAK_GBS,
+                                  "traffic": measured_traffic(prec, TRAFFIC3_FILE, KERNEL3_SRC),
                                   "avg_launch_ms": avg_s * 1e3,
                                   "algorithmic_bytes_per_launch": per_launch},
                      "stage_ms_per_step": {k: v / args.steps for k, v in stages.items()},
@@ -295,7 +304,7 @@ def run_tet(args):
            "data": "synthetic",
            "config": {"workload": "tet_pair_plasma", "n_tets": nt, "n_edges": m["n_edges"],
                       "n_faces": m["n_faces"], "n_particles": n_p, "theta": w.extra["theta"],
-                      "pusher": "boris", "precision": "mixed", "resort_every": 20,
+                      "pusher": "boris", "precision": "mixed", "resort_every": resort,
                       "spai_level": 1},
            "roofline": m["roofline"], "stage_ms_per_step": m["stage_ms_per_step"],
            "gauss_rel": m["gauss_rel"], "divb_rel": m["divb_rel"],

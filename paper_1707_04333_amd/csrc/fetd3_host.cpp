@@ -114,9 +114,38 @@ struct fetd3_sim {
 
     // stage timing
     bool profiling = false;
-    hipEvent_t ev[12] = {};
+    std::vector<hipEvent_t> event_pool, all_events;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[5];  // recorded, not yet read
     double stage_ms[5] = {0, 0, 0, 0, 0};
     int64_t particle_launches = 0;
+
+    hipEvent_t take_event()
+    {
+        if (event_pool.empty()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            all_events.push_back(e);
+            return e;
+        }
+        hipEvent_t e = event_pool.back();
+        event_pool.pop_back();
+        return e;
+    }
+    // Fold the recorded stage intervals into stage_ms (waits for the last).
+    void resolve_timers()
+    {
+        for (int k = 0; k < 5; ++k) {
+            for (auto &ab : timed[k]) {
+                float ms = 0;
+                if (hipEventSynchronize(ab.second) == hipSuccess &&
+                    hipEventElapsedTime(&ms, ab.first, ab.second) == hipSuccess)
+                    stage_ms[k] += ms;
+                event_pool.push_back(ab.first);
+                event_pool.push_back(ab.second);
+            }
+            timed[k].clear();
+        }
+    }
 
     fetd_status fail(fetd_status st, const std::string &msg)
     {
@@ -793,21 +822,24 @@ fetd_status sort_all3(fetd3_sim *s)
     return FETD_OK;
 }
 
+// Stage interval of the profiled stream: two events recorded around the
+// stage's launches and read later (no wait inside the step loop).
 struct StageTimer3 {
     fetd3_sim *s;
     int k;
+    hipEvent_t a = nullptr;
     StageTimer3(fetd3_sim *sim, int stage) : s(sim), k(stage)
     {
-        if (s->profiling) (void)hipEventRecord(s->ev[2 * k], s->stream);
+        if (s->profiling && (a = s->take_event())) (void)hipEventRecord(a, s->stream);
     }
     ~StageTimer3()
     {
-        if (!s->profiling) return;
-        (void)hipEventRecord(s->ev[2 * k + 1], s->stream);
-        (void)hipEventSynchronize(s->ev[2 * k + 1]);
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, s->ev[2 * k], s->ev[2 * k + 1]) == hipSuccess)
-            s->stage_ms[k] += ms;
+        if (!a) return;
+        hipEvent_t b = s->take_event();
+        if (b && hipEventRecord(b, s->stream) == hipSuccess)
+            s->timed[k].push_back({a, b});
+        else
+            s->event_pool.push_back(a);
     }
 };
 
@@ -1234,10 +1266,7 @@ fetd_status fetd3_profile(fetd3_sim *s, int32_t enable)
 {
     if (!s) return FETD_E_ARG;
     DeviceGuard3 g(s->device);
-    if (enable && !s->profiling) {
-        for (hipEvent_t &e : s->ev)
-            if (!e && hipEventCreate(&e) != hipSuccess) return s->fail(FETD_E_HIP, "event");
-    }
+    s->resolve_timers();
     s->profiling = enable != 0;
     for (double &v : s->stage_ms) v = 0;
     s->particle_launches = 0;
@@ -1247,6 +1276,8 @@ fetd_status fetd3_profile(fetd3_sim *s, int32_t enable)
 fetd_status fetd3_stage_times(fetd3_sim *s, double *ms, int64_t *launches)
 {
     if (!s || !ms) return FETD_E_ARG;
+    DeviceGuard3 g(s->device);
+    s->resolve_timers();
     for (int k = 0; k < 5; ++k) ms[k] = s->stage_ms[k];
     if (launches) *launches = s->particle_launches;
     return FETD_OK;
@@ -1262,8 +1293,7 @@ void fetd3_destroy(fetd3_sim *s)
         if (s->stream) (void)hipStreamSynchronize(s->stream);
         for (void *p : s->allocs) (void)hipFree(p);
         s->allocs.clear();
-        for (hipEvent_t &e : s->ev)
-            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : s->all_events) (void)hipEventDestroy(e);
         if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     }
     delete s;
