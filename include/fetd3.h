@@ -117,7 +117,8 @@ fetd_status fetd3_fields_load(fetd3_sim *sim, const double *b, const double *d);
 
 /* Append a species of n particles (tet[n], slot[n] or NULL for slot 0,
  * lam[3n], u[3n]); *species_out gets its index.  Load order defines the
- * particle ids 0..n-1 of the species. */
+ * particle ids 0..n-1 of the species; every species is then sorted by
+ * tetrahedron (storage order only). */
 fetd_status fetd3_particles_load_bary(fetd3_sim *sim, double q, double m, double w, int64_t n,
                                       const int32_t *tet, const int8_t *slot, const double *lam,
                                       const double *u, int32_t *species_out);

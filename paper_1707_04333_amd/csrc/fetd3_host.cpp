@@ -1008,6 +1008,8 @@ fetd_status fetd3_particles_load_bary(fetd3_sim *s, double q, double m, double w
     s->species.push_back(sp);
     if (species_out) *species_out = int32_t(s->species.size() - 1);
     s->have_baseline = false;
+    // start sorted by tetrahedron (the particle kernel's locality relies on it)
+    if (n > 0) return sort_all3(s);
     return FETD_OK;
 }
 
