@@ -44,6 +44,12 @@ constexpr int kBack3 = 1024;
 constexpr int kHashBits3 = 8;
 constexpr int kHash3 = 1 << kHashBits3;
 
+// Counting sort: particles per block, and the block's LDS window of
+// tetrahedron ids (kSortBins3 ids from kSortBack3 below its first particle's).
+constexpr int kSortB3 = 1024;
+constexpr int kSortBins3 = 1024;
+constexpr int kSortBack3 = 256;
+
 // Per-tetrahedron gather record, 24 doubles: V_0..V_3 with E = sum l_n V_n,
 // then U_0..U_3 with B = sum l_n U_n (B at time n from the face average).
 constexpr int kRec = 24;

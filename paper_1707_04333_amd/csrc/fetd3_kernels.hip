@@ -17,6 +17,16 @@ namespace {
 
 __device__ __forceinline__ void atomic_add_f64(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2:
+// give each XCD a contiguous run of particle blocks, so that the
+// tetrahedron tables a run of sorted particles shares stay in one L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
+{
+    const int64_t x = b & 7, j = b >> 3;
+    const int64_t per = nb >> 3, rem = nb & 7;
+    return x < rem ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
+}
+
 inline unsigned grid_for(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 // value of a[i] for a runtime i in 0..3 without dynamic indexing
@@ -416,7 +426,8 @@ __device__ __forceinline__ void continue_move(const Mesh3 &m, const Step3 &a, co
 template <int P, typename R>
 __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
 {
-    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t p = blk * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     unsigned long long pieces = 0, lost_here = 0;
     __shared__ double s_win[kWin3];
@@ -431,7 +442,7 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
     if (threadIdx.x == 0) {
         // home: the tetrahedron of the block's first particle (read before
         // any thread of the block writes its key)
-        const uint32_t k0 = a.key[int64_t(blockIdx.x) * blockDim.x];
+        const uint32_t k0 = a.key[blk * blockDim.x];
         const int home = k0 == kLost ? 0 : int(k0 & kTetMask);
         s_base = int(m.tet_ebase[home]) - kBack3;
     }
@@ -663,29 +674,40 @@ __global__ __launch_bounds__(256) void k3_spmv(int ne, const int32_t *__restrict
     e[ed] = acc;
 }
 
-// Counting sort: histogram of live keys per tetrahedron.  The particles
-// are nearly sorted already, so a wavefront first finds its runs of equal
-// tetrahedron and the last lane of each run adds the run's length.
-__device__ __forceinline__ void wave_runs(uint32_t k, int lane, int &head_lane, bool &tail)
+// Counting sort by tetrahedron, aggregated per block of kSortB3 particles.
+// The particles were sorted at the last sort and have moved a few
+// tetrahedra since, so a block's tetrahedra mostly lie in a window of
+// kSortBins3 ids placed kSortBack3 below the tetrahedron of its first
+// particle: those are counted and placed through LDS (one global atomic per
+// touched tetrahedron), the others one by one.
+__device__ __forceinline__ uint32_t sort_window3(const Sort3 &a, int64_t b0)
 {
-    const uint32_t kprev = __shfl_up(k, 1, 64);
-    const bool head = lane == 0 || kprev != k;
-    const unsigned long long hm = __ballot(head);
-    const unsigned long long below = hm & ((2ull << lane) - 1ull);
-    head_lane = 63 - __clzll(below);
-    tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
+    const uint32_t k = a.key_in[b0];
+    const uint32_t h = k == kLost ? 0u : (k & kTetMask);
+    return h > uint32_t(kSortBack3) ? h - uint32_t(kSortBack3) : 0u;
 }
 
-__global__ __launch_bounds__(256) void k3_sort_count(int64_t n, const uint32_t *__restrict__ key,
-                                                     int32_t *__restrict__ counts)
+__global__ __launch_bounds__(256) void k3_sort_count(Sort3 a)
 {
-    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const uint32_t k = p < n ? key[p] : kLost;
-    int head_lane;
-    bool tail;
-    wave_runs(k, lane, head_lane, tail);
-    if (tail && k != kLost) atomicAdd(counts + (k & kTetMask), lane - head_lane + 1);
+    __shared__ int32_t h[kSortBins3];
+    for (int t = threadIdx.x; t < kSortBins3; t += 256) h[t] = 0;
+    const int64_t b0 = int64_t(blockIdx.x) * kSortB3;
+    const uint32_t wb = sort_window3(a, b0);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortB3 / 256; ++j) {
+        const int64_t i = b0 + j * 256 + int(threadIdx.x);
+        const uint32_t k = i < a.n ? a.key_in[i] : kLost;
+        if (k == kLost) continue;
+        const uint32_t f = k & kTetMask, bin = f - wb;
+        if (bin < uint32_t(kSortBins3))
+            atomicAdd(&h[bin], 1);
+        else
+            atomicAdd(a.counts + f, 1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kSortBins3; t += 256)
+        if (h[t]) atomicAdd(a.counts + wb + uint32_t(t), h[t]);
 }
 
 // ... exclusive scan of counts[0..nt] into cursor: each block of 1024
@@ -743,36 +765,97 @@ __global__ __launch_bounds__(1024) void k3_scan_add(int n, int32_t *__restrict__
     if (i < n) cursor[i] += sums[blockIdx.x];
 }
 
-// ... and scatter of every live particle to the next free places of its
-// tetrahedron: the first lane of a wavefront run reserves the run's places
-// with one atomic, the others follow it in lane order.
+// ... and scatter: every block ranks its particles inside their window
+// bins, reserves each touched tetrahedron's places with one atomic, and
+// writes its particles out in destination order through an LDS
+// permutation (particles outside the window reserve their place alone).
 template <typename R>
 __global__ __launch_bounds__(256) void k3_sort_scatter(Sort3 a)
 {
-    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const uint32_t k = p < a.n ? a.key_in[p] : kLost;
-    int head_lane;
-    bool tail;
-    wave_runs(k, lane, head_lane, tail);
-    // run length seen from the head: the tail lane's distance to it
-    const unsigned long long tm = __ballot(tail);
-    const unsigned long long at_or_above = tm & ~((1ull << lane) - 1ull);
-    const int tail_lane = __ffsll(static_cast<long long>(at_or_above)) - 1;
-    int base = 0;
-    if (lane == head_lane && k != kLost)
-        base = atomicAdd(a.cursor + (k & kTetMask), tail_lane - lane + 1);
-    base = __shfl(base, head_lane, 64);
-    if (k == kLost) return;
-    const int64_t q = int64_t(base) + (lane - head_lane);
-    a.key_out[q] = k;
-    a.pid_out[q] = a.pid_in[p];
+    __shared__ int32_t cnt[kSortBins3];  // count per bin, then its global base
+    __shared__ int32_t loc[kSortBins3];  // exclusive offset of the bin inside the block
+    __shared__ int32_t wsum[4];
+    __shared__ int32_t n_in, n_out;
+    __shared__ uint16_t s_src[kSortB3];  // block slot -> block-local input index
+    __shared__ int32_t s_dst[kSortB3];   // block slot -> destination
+    constexpr int kPer = kSortB3 / 256;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int t = tid; t < kSortBins3; t += 256) cnt[t] = 0;
+    if (tid == 0) n_out = 0;
+    const int64_t b0 = int64_t(blockIdx.x) * kSortB3;
+    const uint32_t wb = sort_window3(a, b0);
+    __syncthreads();
+    int32_t bin[kPer], rank[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = b0 + j * 256 + tid;
+        const uint32_t k = i < a.n ? a.key_in[i] : kLost;
+        bin[j] = -1;
+        rank[j] = -1;
+        if (k == kLost) continue;
+        const uint32_t f = k & kTetMask, b = f - wb;
+        if (b < uint32_t(kSortBins3)) {
+            bin[j] = int32_t(b);
+            rank[j] = atomicAdd(&cnt[b], 1);
+        } else {
+            // outside the window: its own place, kept at the end of the block slots
+            const int r = atomicAdd(&n_out, 1);
+            s_dst[kSortB3 - 1 - r] = atomicAdd(a.cursor + f, 1);
+            s_src[kSortB3 - 1 - r] = uint16_t(j * 256 + tid);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the bin counts (kSortBins3 / 256 per thread)
+    constexpr int kBpt = kSortBins3 / 256;
+    int32_t cq[kBpt], run = 0;
+#pragma unroll
+    for (int q = 0; q < kBpt; ++q) {
+        cq[q] = cnt[kBpt * tid + q];
+        run += cq[q];
+    }
+    int32_t incl = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int32_t before = incl - run;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    if (tid == 255) n_in = before + run;
+#pragma unroll
+    for (int q = 0; q < kBpt; ++q) {
+        loc[kBpt * tid + q] = before;
+        // one global reservation per touched tetrahedron
+        const int32_t g = cq[q] ? atomicAdd(a.cursor + wb + uint32_t(kBpt * tid + q), cq[q]) : 0;
+        cnt[kBpt * tid + q] = g;
+        before += cq[q];
+    }
+    __syncthreads();
+    // block slots of the in-window particles: bin offset + rank
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        if (bin[j] < 0) continue;
+        const int slot = loc[bin[j]] + rank[j];
+        s_src[slot] = uint16_t(j * 256 + tid);
+        s_dst[slot] = cnt[bin[j]] + rank[j];
+    }
+    __syncthreads();
+    const int nin = n_in, nout = n_out;
     const R *li = static_cast<const R *>(a.lam_in), *ui = static_cast<const R *>(a.u_in);
     R *lo = static_cast<R *>(a.lam_out), *uo = static_cast<R *>(a.u_out);
+    for (int s = tid; s < kSortB3; s += 256) {
+        if (s >= nin && s < kSortB3 - nout) continue;
+        const int64_t i = b0 + s_src[s];
+        const int64_t q = s_dst[s];
+        a.key_out[q] = a.key_in[i];
+        a.pid_out[q] = a.pid_in[i];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        lo[c * a.stride_out + q] = li[c * a.stride_in + p];
-        uo[c * a.stride_out + q] = ui[c * a.stride_in + p];
+        for (int c = 0; c < 3; ++c) {
+            lo[c * a.stride_out + q] = li[c * a.stride_in + i];
+            uo[c * a.stride_out + q] = ui[c * a.stride_in + i];
+        }
     }
 }
 
@@ -901,17 +984,18 @@ hipError_t launch3_sort(hipStream_t s, const Sort3 &a)
     if (a.n <= 0) return hipSuccess;
     hipError_t e = hipMemsetAsync(a.counts, 0, sizeof(int32_t) * (size_t(a.nt) + 1), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k3_sort_count, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a.n, a.key_in,
-                       a.counts);
+    hipLaunchKernelGGL(k3_sort_count, dim3(grid_for(a.n, kSortB3)), dim3(256), 0, s, a);
     const int n1 = a.nt + 1, nchunk = (n1 + 1023) / 1024;
     hipLaunchKernelGGL(k3_scan_chunks, dim3(nchunk), dim3(1024), 0, s, n1, a.counts, a.cursor,
                        a.chunk_sums);
     hipLaunchKernelGGL(k3_scan_totals, dim3(1), dim3(1024), 0, s, nchunk, a.chunk_sums);
     hipLaunchKernelGGL(k3_scan_add, dim3(nchunk), dim3(1024), 0, s, n1, a.cursor, a.chunk_sums);
     if (a.elem_bytes == 4)
-        hipLaunchKernelGGL(k3_sort_scatter<float>, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k3_sort_scatter<float>, dim3(grid_for(a.n, kSortB3)), dim3(256), 0, s,
+                           a);
     else
-        hipLaunchKernelGGL(k3_sort_scatter<double>, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k3_sort_scatter<double>, dim3(grid_for(a.n, kSortB3)), dim3(256), 0, s,
+                           a);
     return hipGetLastError();
 }
 
