@@ -168,18 +168,28 @@ def bary_to_xyz(mesh: TetMesh, tet: np.ndarray, lam: np.ndarray) -> np.ndarray:
 
 def sample_mj3d(n: int, theta: float, rng) -> np.ndarray:
     """Magnitude of p/(m c) for the 3-D Maxwell-Juttner equilibrium
-    f(p) d^3p ~ exp(-gamma/theta) d^3p, by Sobol's rejection method (draw
-    u = -theta ln(X1 X2 X3), eta = -theta ln(X1 X2 X3 X4) and keep u when
-    eta^2 - u^2 > 1)."""
-    out = np.empty(0)
-    while out.size < n:
-        m = max(1024, int(1.5 * (n - out.size)) + 16)
-        X = rng.random((m, 4))
-        X = np.where(X > 0.0, X, 1e-300)
-        u = -theta * np.log(X[:, 0] * X[:, 1] * X[:, 2])
-        eta = u - theta * np.log(X[:, 3])
-        out = np.concatenate([out, u[eta * eta - u * u > 1.0]])
-    return out[:n]
+    f(p) d^3p ~ exp(-gamma/theta) d^3p, exactly, by rejection from a Gamma
+    mixture.  With x = gamma - 1 the density of x is proportional to
+    (1 + x) sqrt(x (2 + x)) exp(-x/theta), which is at most
+    sqrt(2) (x^1/2 + 2 x^3/2 + x^5/2) exp(-x/theta): a mixture of
+    Gamma(3/2, theta), Gamma(5/2, theta) and Gamma(7/2, theta) with weights
+    G(3/2) theta^3/2, 2 G(5/2) theta^5/2 and G(7/2) theta^7/2.  A draw x of
+    the mixture is kept with probability sqrt(1 + x/2) / (1 + x), the ratio
+    of the two (about 0.9 at theta = 0.1); then |u| = sqrt(x (2 + x))."""
+    from math import gamma as G
+    wts = np.array([G(1.5) * theta ** 1.5, 2.0 * G(2.5) * theta ** 2.5, G(3.5) * theta ** 3.5])
+    wts /= wts.sum()
+    parts, got, acc = [], 0, 0.5
+    while got < n:
+        m = int((n - got) / acc * 1.1) + 64
+        shape = 1.5 + rng.choice(3, size=m, p=wts)
+        x = rng.gamma(shape, theta)
+        keep = rng.random(m) * (1.0 + x) < np.sqrt(1.0 + 0.5 * x)
+        acc = max(float(keep.mean()), 0.01)
+        parts.append(x[keep])
+        got += parts[-1].size
+    x = np.concatenate(parts)[:n]
+    return np.sqrt(x * (2.0 + x))
 
 
 def isotropic_directions(n: int, rng) -> np.ndarray:
