@@ -233,12 +233,20 @@ fetd_status fetd_particles_get(fetd_sim *sim, int32_t species, int64_t capacity,
  * Synchronises the stream. */
 fetd_status fetd_diagnostics(fetd_sim *sim, fetd_diag *out);
 
-/* Stage timing with HIP events recorded on the simulation's stream around
- * every kernel launch of the step: stage 0 = Faraday and gather record,
- * 1 = particle stage (one launch per species), 2 = Ampere, 3 = SpMV,
- * 4 = re-sort (all of its kernels).  enable != 0 starts (and resets) timing,
- * 0 stops it. */
+/* Stage timing with HIP events on the simulation's stream: stage 0 =
+ * Faraday and gather record, 1 = particle stage (one launch per species),
+ * 2 = Ampere, 3 = SpMV, 4 = re-sort (all of its kernels).  Stages 0-3 pass
+ * their events to their kernel dispatches (hipExtLaunchKernel: the start
+ * time of the stage's first kernel, the end time of its last); the re-sort
+ * records them around its launches.  enable != 0 starts (and resets)
+ * timing of every stage, 0 stops it. */
 fetd_status fetd_profile(fetd_sim *sim, int32_t enable);
+
+/* As fetd_profile, timing only the stages whose bit (1 << stage) is set in
+ * stage_mask (bits above FETD_N_STAGES are ignored; 0 stops timing).  A
+ * timed dispatch costs the step a few microseconds, so a run whose own
+ * duration is measured times only the stage it needs. */
+fetd_status fetd_profile_mask(fetd_sim *sim, int32_t stage_mask);
 
 /* Device milliseconds summed per stage since timing started, and the number
  * of timed launches per stage (arrays of FETD_N_STAGES).  Synchronises. */

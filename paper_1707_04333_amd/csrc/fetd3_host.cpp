@@ -8,6 +8,7 @@
 #include "fetd3.h"
 #include "fetd3_internal.h"
 #include "fetd_sparse.h"
+#include "stage_events.h"
 
 #include <hip/hip_runtime.h>
 
@@ -113,7 +114,7 @@ struct fetd3_sim {
     std::vector<double> q0, divd0;
 
     // stage timing
-    bool profiling = false;
+    uint32_t profile_mask = 0;  // bit k: stage k is timed
     std::vector<hipEvent_t> event_pool, all_events;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[5];  // recorded, not yet read
     double stage_ms[5] = {0, 0, 0, 0, 0};
@@ -140,6 +141,7 @@ struct fetd3_sim {
                 if (hipEventSynchronize(ab.second) == hipSuccess &&
                     hipEventElapsedTime(&ms, ab.first, ab.second) == hipSuccess)
                     stage_ms[k] += ms;
+                if (k == 1) ++particle_launches;
                 event_pool.push_back(ab.first);
                 event_pool.push_back(ab.second);
             }
@@ -822,24 +824,49 @@ fetd_status sort_all3(fetd3_sim *s)
     return FETD_OK;
 }
 
-// Stage interval of the profiled stream: two events recorded around the
-// stage's launches and read later (no wait inside the step loop).
+// Stage interval of the profiled stream, read later (no wait inside the
+// step loop).  The step stages (0-3) hand their two events to the stage's
+// kernel launches, which carry them in their own dispatches; the sort (4)
+// records them around its launches.
 struct StageTimer3 {
     fetd3_sim *s;
     int k;
-    hipEvent_t a = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
     StageTimer3(fetd3_sim *sim, int stage) : s(sim), k(stage)
     {
-        if (s->profiling && (a = s->take_event())) (void)hipEventRecord(a, s->stream);
+        if (!(s->profile_mask >> k & 1u)) return;
+        a = s->take_event();
+        b = a ? s->take_event() : nullptr;
+        if (!b) {
+            release();
+            return;
+        }
+        if (k == 4) {
+            if (hipEventRecord(a, s->stream) != hipSuccess) release();
+        } else {
+            fetd_timing::pending() = {a, b};
+        }
+    }
+    void release()
+    {
+        if (a) s->event_pool.push_back(a);
+        if (b) s->event_pool.push_back(b);
+        a = b = nullptr;
     }
     ~StageTimer3()
     {
         if (!a) return;
-        hipEvent_t b = s->take_event();
-        if (b && hipEventRecord(b, s->stream) == hipSuccess)
+        bool ok;
+        if (k == 4) {
+            ok = hipEventRecord(b, s->stream) == hipSuccess;
+        } else {
+            ok = fetd_timing::pending().start == nullptr;  // a kernel took the events
+            fetd_timing::pending() = {};
+        }
+        if (ok)
             s->timed[k].push_back({a, b});
         else
-            s->event_pool.push_back(a);
+            release();
     }
 };
 
@@ -1053,7 +1080,6 @@ fetd_status fetd3_pic_step(fetd3_sim *s, int32_t n_steps, int32_t pusher)
             a.stride = s->p_cap;
             StageTimer3 tm(s, 1);
             e = launch3_particles(s->stream, mv, a, pusher, s->fp32);
-            ++s->particle_launches;
             if (e != hipSuccess) return s->hip_fail(e, "particles");
         }
         {
@@ -1266,10 +1292,15 @@ fetd_status fetd3_diagnostics(fetd3_sim *s, fetd3_diag *out)
 
 fetd_status fetd3_profile(fetd3_sim *s, int32_t enable)
 {
+    return fetd3_profile_mask(s, enable ? 0x1F : 0);
+}
+
+fetd_status fetd3_profile_mask(fetd3_sim *s, int32_t stage_mask)
+{
     if (!s) return FETD_E_ARG;
     DeviceGuard3 g(s->device);
     s->resolve_timers();
-    s->profiling = enable != 0;
+    s->profile_mask = uint32_t(stage_mask) & 0x1Fu;
     for (double &v : s->stage_ms) v = 0;
     s->particle_launches = 0;
     return FETD_OK;

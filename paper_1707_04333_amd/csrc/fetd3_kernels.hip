@@ -11,6 +11,7 @@
 //                 e = M~ d (Sec. II.A, eq. semi.dis.curl.2 in the d form)
 //   k3_sort_*     counting sort of the particles by tetrahedron
 #include "fetd3_internal.h"
+#include "stage_events.h"
 
 namespace fetd3 {
 namespace {
@@ -912,7 +913,7 @@ hipError_t launch3_faraday(hipStream_t s, int nf, const int4 *face_edge, const d
                            double *b, double *bavg, double dt)
 {
     if (nf <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k3_faraday, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf, face_edge, e, b,
+    FETD_LAUNCH(k3_faraday, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf, face_edge, e, b,
                        bavg, dt);
     return hipGetLastError();
 }
@@ -922,10 +923,10 @@ hipError_t launch3_record(hipStream_t s, int nt, const Mesh3 &m, const double *e
 {
     if (nt <= 0) return hipSuccess;
     if (fp32)
-        hipLaunchKernelGGL(k3_record<float>, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, m, e,
+        FETD_LAUNCH(k3_record<float>, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, m, e,
                            e_ext, bavg, static_cast<float *>(rec));
     else
-        hipLaunchKernelGGL(k3_record<double>, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, m, e,
+        FETD_LAUNCH(k3_record<double>, dim3(grid_for(nt, 256)), dim3(256), 0, s, nt, m, e,
                            e_ext, bavg, static_cast<double *>(rec));
     return hipGetLastError();
 }
@@ -935,10 +936,10 @@ void launch3_particles_t(hipStream_t s, const Mesh3 &m, const Step3 &a, int push
 {
     const dim3 grid(grid_for(a.n, kBlock)), block(kBlock);
     switch (pusher) {
-    case 0: hipLaunchKernelGGL((k3_particles<0, R>), grid, block, 0, s, m, a); break;
-    case 1: hipLaunchKernelGGL((k3_particles<1, R>), grid, block, 0, s, m, a); break;
-    case 2: hipLaunchKernelGGL((k3_particles<2, R>), grid, block, 0, s, m, a); break;
-    default: hipLaunchKernelGGL((k3_particles<3, R>), grid, block, 0, s, m, a); break;
+    case 0: FETD_LAUNCH((k3_particles<0, R>), grid, block, 0, s, m, a); break;
+    case 1: FETD_LAUNCH((k3_particles<1, R>), grid, block, 0, s, m, a); break;
+    case 2: FETD_LAUNCH((k3_particles<2, R>), grid, block, 0, s, m, a); break;
+    default: FETD_LAUNCH((k3_particles<3, R>), grid, block, 0, s, m, a); break;
     }
 }
 
@@ -955,7 +956,7 @@ hipError_t launch3_particles(hipStream_t s, const Mesh3 &m, const Step3 &a, int 
 hipError_t launch3_hnu(hipStream_t s, int nf, const Sell &m, const double *b, double *h)
 {
     if (nf <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k3_hnu, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf, m.sptr, m.sw, m.col,
+    FETD_LAUNCH(k3_hnu, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf, m.sptr, m.sw, m.col,
                        m.val, b, h);
     return hipGetLastError();
 }
@@ -965,7 +966,7 @@ hipError_t launch3_ampere(hipStream_t s, int ne, const int32_t *ef_ptr, const in
                           double *cur_last, double *d, double dt)
 {
     if (ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k3_ampere, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, ef_ptr, ef_face,
+    FETD_LAUNCH(k3_ampere, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, ef_ptr, ef_face,
                        edge_free, h, cur, cur_last, d, dt);
     return hipGetLastError();
 }
@@ -974,7 +975,7 @@ hipError_t launch3_spmv(hipStream_t s, int ne, const Sell &m, const uint8_t *edg
                         const double *d, double *e)
 {
     if (ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k3_spmv, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, m.sptr, m.sw, m.col,
+    FETD_LAUNCH(k3_spmv, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, m.sptr, m.sw, m.col,
                        m.val, edge_free, d, e);
     return hipGetLastError();
 }

@@ -6,6 +6,7 @@
 #include "fetdpic.h"
 #include "fetd_internal.h"
 #include "fetd_sparse.h"
+#include "stage_events.h"
 
 #include <hip/hip_runtime.h>
 
@@ -21,6 +22,12 @@
 #include <vector>
 
 using namespace fetd;
+
+fetd_timing::Pending &fetd_timing::pending()
+{
+    thread_local Pending p;
+    return p;
+}
 
 namespace {
 
@@ -119,7 +126,7 @@ struct fetd_sim {
     int64_t device_bytes = 0;
     std::string err;
     // stage timing
-    bool profiling = false;
+    uint32_t profile_mask = 0;  // bit k: stage k is timed
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[FETD_N_STAGES];
     std::vector<hipEvent_t> event_pool;
     hipEvent_t take_event()
@@ -133,21 +140,46 @@ struct fetd_sim {
         }
         return ev;
     }
-    // Brackets a launch with events when timing is on.
+    // Times a stage when timing is on.  The step stages (0-3) hand their
+    // two events to the stage's kernel launches, which carry them in their
+    // own dispatches; the sort (4) records them around its launches.
     struct Timer {
         fetd_sim *s;
         int stage;
-        hipEvent_t a = nullptr;
+        hipEvent_t a = nullptr, b = nullptr;
         Timer(fetd_sim *s_, int st) : s(s_), stage(st)
         {
-            if (s->profiling && (a = s->take_event())) (void)hipEventRecord(a, s->stream);
+            if (!(s->profile_mask >> stage & 1u)) return;
+            a = s->take_event();
+            b = a ? s->take_event() : nullptr;
+            if (!b) {
+                release();
+                return;
+            }
+            if (stage == 4) {
+                if (hipEventRecord(a, s->stream) != hipSuccess) release();
+            } else {
+                fetd_timing::pending() = {a, b};
+            }
+        }
+        void release()
+        {
+            if (a) s->event_pool.push_back(a);
+            if (b) s->event_pool.push_back(b);
+            a = b = nullptr;
         }
         ~Timer()
         {
             if (!a) return;
-            hipEvent_t b = s->take_event();
-            if (b && hipEventRecord(b, s->stream) == hipSuccess) s->timed[stage].push_back({a, b});
-            else s->event_pool.push_back(a);
+            bool ok;
+            if (stage == 4) {
+                ok = hipEventRecord(b, s->stream) == hipSuccess;
+            } else {
+                ok = fetd_timing::pending().start == nullptr;  // a kernel took the events
+                fetd_timing::pending() = {};
+            }
+            if (ok) s->timed[stage].push_back({a, b});
+            else release();
         }
     };
 
@@ -1470,6 +1502,11 @@ fetd_status fetd_diagnostics(fetd_sim *s, fetd_diag *out)
 
 fetd_status fetd_profile(fetd_sim *s, int32_t enable)
 {
+    return fetd_profile_mask(s, enable ? (1 << FETD_N_STAGES) - 1 : 0);
+}
+
+fetd_status fetd_profile_mask(fetd_sim *s, int32_t stage_mask)
+{
     if (!s) return FETD_E_ARG;
     DeviceGuard g(s->device);
     hipError_t e = hipStreamSynchronize(s->stream);
@@ -1481,7 +1518,7 @@ fetd_status fetd_profile(fetd_sim *s, int32_t enable)
         }
         v.clear();
     }
-    s->profiling = enable != 0;
+    s->profile_mask = uint32_t(stage_mask) & ((1u << FETD_N_STAGES) - 1);
     return FETD_OK;
 }
 
@@ -1515,10 +1552,10 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     if (!s || trial_steps < 2 || pusher < 0 || pusher > 3) return FETD_E_ARG;
     DeviceGuard g(s->device);
     fetd_status st;
-    const bool was_profiling = s->profiling;
+    const int32_t was_mask = int32_t(s->profile_mask);
     const int saved = s->resort_every;
     // one timed sort
-    if ((st = fetd_profile(s, 1))) return st;
+    if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4)))) return st;
     {
         fetd_sim::Timer t(s, 4);
         if ((st = sort_all(s))) return st;
@@ -1532,7 +1569,7 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     const int nsp = int(std::count_if(s->species.begin(), s->species.end(),
                                       [](const Species &x) { return x.n > 0; }));
     std::vector<double> tp(trial_steps, 0.0);
-    if ((st = fetd_profile(s, 1))) return st;
+    if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4)))) return st;
     if ((st = fetd_pic_step(s, trial_steps, pusher))) return st;
     hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "autotune");
@@ -1556,7 +1593,7 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     }
     s->resort_every = best;
     s->steps_since_sort = trial_steps;  // the order has decayed: sort at the next step
-    if ((st = fetd_profile(s, was_profiling ? 1 : 0))) return st;
+    if ((st = fetd_profile_mask(s, was_mask))) return st;
     if (chosen) *chosen = best;
     return FETD_OK;
 }

@@ -14,6 +14,7 @@
 // (coalesced SoA particle streams, per-triangle tables read through the
 // cache, FP64 current reduced within each wavefront before the atomics).
 #include "fetd_internal.h"
+#include "stage_events.h"
 
 #include <hip/hip_runtime.h>
 
@@ -1164,11 +1165,11 @@ hipError_t launch_faraday(hipStream_t s, int nf, const int4 *tri_edge, const dou
 {
     if (nf <= 0) return hipSuccess;
     if (rec_fp32)
-        hipLaunchKernelGGL(k_faraday<float>, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
+        FETD_LAUNCH(k_faraday<float>, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
                            tri_edge, e, e_ext, e_scale, b, damp_b, h, inv_mu_area, inv_2area,
                            bz_ext, grad64, static_cast<float *>(rec), dt);
     else
-        hipLaunchKernelGGL(k_faraday<double>, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
+        FETD_LAUNCH(k_faraday<double>, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
                            tri_edge, e, e_ext, e_scale, b, damp_b, h, inv_mu_area, inv_2area,
                            bz_ext, grad64, static_cast<double *>(rec), dt);
     return hipGetLastError();
@@ -1179,9 +1180,9 @@ static void launch_particles_p(hipStream_t s, const MeshView &m, const StepArgs 
 {
     const unsigned grid = grid_for(a.n, int64_t(kBlock) * kPPT);
     if (fp32)
-        hipLaunchKernelGGL((k_particle_step<P, float>), dim3(grid), dim3(kBlock), 0, s, m, a);
+        FETD_LAUNCH((k_particle_step<P, float>), dim3(grid), dim3(kBlock), 0, s, m, a);
     else
-        hipLaunchKernelGGL((k_particle_step<P, double>), dim3(grid), dim3(kBlock), 0, s, m, a);
+        FETD_LAUNCH((k_particle_step<P, double>), dim3(grid), dim3(kBlock), 0, s, m, a);
 }
 
 hipError_t launch_particles(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
@@ -1202,7 +1203,7 @@ hipError_t launch_ampere(hipStream_t s, int ne, const int4 *edge_face, const dou
                          double *cur, double *cur_last, double *d, const double *damp, double dt)
 {
     if (ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ampere, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, edge_face, h, cur,
+    FETD_LAUNCH(k_ampere, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, edge_face, h, cur,
                        cur_last, d, damp, dt);
     return hipGetLastError();
 }
@@ -1211,7 +1212,7 @@ hipError_t launch_spmv(hipStream_t s, int ne, const int32_t *slice_ptr, const in
                        const int32_t *col, const double *val, const double *d, double *e)
 {
     if (ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, slice_ptr, slice_w,
+    FETD_LAUNCH(k_spmv, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, slice_ptr, slice_w,
                        col, val, d, e);
     return hipGetLastError();
 }

@@ -15,6 +15,7 @@ from .fetdpic import PRECISIONS, PUSHERS, FetdError, lib as _base_lib
 
 FIELDS = {"e": 0, "d": 1, "b": 2, "j": 3, "q": 4, "divd": 5, "divb": 6, "edges": 7, "faces": 8,
           "spai_ptr": 9, "spai_col": 10, "spai_val": 11}
+STAGES3 = ("faraday", "particles", "ampere", "spmv", "sort")
 _DTYPES = {"edges": np.int32, "faces": np.int32, "spai_ptr": np.int32, "spai_col": np.int32}
 
 
@@ -60,6 +61,7 @@ def lib():
                "fetd3_fields_get": [P, I32, P, I64, P],
                "fetd3_particles_get": [P, I32, I64, P, P, P, P, P, P],
                "fetd3_diagnostics": [P, P], "fetd3_profile": [P, I32],
+               "fetd3_profile_mask": [P, I32],
                "fetd3_stage_times": [P, P, P]}
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -181,14 +183,19 @@ class Sim3:
         _check(lib().fetd3_diagnostics(self.h, ctypes.byref(d)), self.h)
         return d.as_dict()
 
-    def profile(self, enable=True):
-        _check(lib().fetd3_profile(self.h, 1 if enable else 0), self.h)
+    def profile(self, enable=True, stages=None):
+        """Stage timing on (every stage, or only the named ones of STAGES3) or off."""
+        if stages is not None and enable:
+            mask = sum(1 << STAGES3.index(k) for k in set(stages))
+            _check(lib().fetd3_profile_mask(self.h, mask), self.h)
+        else:
+            _check(lib().fetd3_profile(self.h, 1 if enable else 0), self.h)
 
     def stage_times(self):
         ms = np.zeros(5)
         n = ctypes.c_int64()
         _check(lib().fetd3_stage_times(self.h, _p(ms), ctypes.byref(n)), self.h)
-        return dict(zip(("faraday", "particles", "ampere", "spmv", "sort"), ms)), n.value
+        return dict(zip(STAGES3, ms)), n.value
 
 
 def from_workload3(w, spai_level=None, **kw):

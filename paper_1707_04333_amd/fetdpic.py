@@ -95,6 +95,7 @@ def lib():
         L.fetd_last_error.argtypes = [P]
         L.fetd_last_error.restype = ctypes.c_char_p
         optional = {"fetd_profile": [P, ctypes.c_int32], "fetd_stage_times": [P, P, P],
+                    "fetd_profile_mask": [P, ctypes.c_int32],
                     "fetd_autotune": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_set_resort": [P, ctypes.c_int32],
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
@@ -309,8 +310,17 @@ def set_resort(h, every):
     _check(lib().fetd_set_resort(h, int(every)), h)
 
 
-def profile(h, enable=True):
-    _check(lib().fetd_profile(h, 1 if enable else 0), h)
+def stage_mask(stages):
+    """Bit mask of stage names (STAGES) for fetd_profile_mask."""
+    return sum(1 << STAGES.index(k) for k in set(stages))
+
+
+def profile(h, enable=True, stages=None):
+    """Stage timing on (every stage, or only the named ones) or off."""
+    if stages is not None and enable:
+        _check(lib().fetd_profile_mask(h, stage_mask(stages)), h)
+    else:
+        _check(lib().fetd_profile(h, 1 if enable else 0), h)
 
 
 def stage_times(h):
@@ -388,8 +398,8 @@ class Sim:
     def info(self):
         return info(self.h)
 
-    def profile(self, enable=True):
-        profile(self.h, enable)
+    def profile(self, enable=True, stages=None):
+        profile(self.h, enable, stages)
 
     def autotune(self, pusher="boris", trial_steps=160):
         return autotune(self.h, pusher, trial_steps)
