@@ -38,6 +38,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd_kernels.hi
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particle_step_pair_plasma_traffic.json")
 KERNEL3_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd3_kernels.hip")
 TRAFFIC3_FILE = os.path.join(ROOT, "profiles", "k3_particles_tet_pair_plasma_traffic.json")
+# Inside the timed region the particle launches of every TIMING_EVERY-th step
+# carry HIP events; 7 is coprime with every re-sort interval used (5 * 2^k),
+# so the sampled steps fall on every phase of the sort cycle.
+TIMING_EVERY = 7
 
 
 def log(msg):
@@ -85,10 +89,11 @@ def run_gpu(w, precision, steps, warmup, pusher, autotune=True):
         log(f"{precision}: autotuned re-sort interval {resort}")
     sim.step(warmup, pusher)
     sim.sync()
-    # the timed region times the particle kernel only (each timed dispatch
-    # costs the step a few microseconds); the stage breakdown comes from a
+    # the timed region times the particle kernel only, on every
+    # TIMING_EVERY-th step (a dispatch that carries events idles the device
+    # for several microseconds around it); the stage breakdown comes from a
     # separate pass after it
-    sim.profile(stages=["particles"])
+    sim.profile(stages=["particles"], every=TIMING_EVERY)
     t0 = time.perf_counter()
     sim.step(steps, pusher)
     sim.sync()
@@ -104,6 +109,44 @@ def run_gpu(w, precision, steps, warmup, pusher, autotune=True):
     sim.close()
     return dict(elapsed=t1 - t0, particles=particles, stages=stages, stage_steps=stage_steps,
                 diag=diag, info=info, resort=resort)
+
+
+def run_timing_overhead(args, window=160, reps=2):
+    """What stage timing costs the step: the 16M-particle pair plasma
+    (mixed, Boris, re-sort every 160 steps, so every window holds one sort)
+    stepped in windows of 160 steps with nothing timed, with the particle
+    stage timed on every TIMING_EVERY-th step (the timed region's setting),
+    on every step, and with every stage timed on every step; 50 ms of idle
+    between windows lets a kernel trace tell them apart."""
+    from paper_1707_04333_amd import fetdpic as fp
+    from paper_1707_04333_amd import inputs as I
+    log("timing overhead: generating the pair plasma")
+    w = I.pair_plasma(n_pairs=args.pairs, theta=args.theta, precision="mixed")
+    sim = fp.from_workload(w, precision="mixed", spai_level=1, device=0)
+    sim.set_resort(window)
+    sim.step(args.warmup, "boris")
+    sim.sync()
+    modes = (("untimed", None), ("particles_every_%d" % TIMING_EVERY, (["particles"], TIMING_EVERY)),
+             ("particles_every_step", (["particles"], 1)), ("all_stages_every_step", (None, 1)))
+    out = {k: [] for k, _ in modes}
+    for _ in range(reps):
+        for name, mode in modes:
+            time.sleep(0.05)
+            if mode is not None:
+                sim.profile(stages=mode[0], every=mode[1])
+            t0 = time.perf_counter()
+            sim.step(window, "boris")
+            sim.sync()
+            out[name].append((time.perf_counter() - t0) / window * 1e3)
+            sim.profile(False)
+            log(f"timing overhead: {name} {out[name][-1]:.4f} ms per step")
+    sim.close()
+    base = min(out["untimed"])
+    return {"metric": "ms per step by stage-timing mode", "unit": "ms",
+            "workload": "pair plasma, 199,712 triangles, 16M particles, mixed, Boris",
+            "window_steps": window, "ms_per_step": {k: min(v) for k, v in out.items()},
+            "all_windows": out,
+            "overhead_vs_untimed": {k: min(v) / base - 1.0 for k, v in out.items()}}
 
 
 def run_batched(steps, warmup, pusher):
@@ -254,7 +297,7 @@ def _run_tet_one(w, precision, steps, warmup, resort_every):
     sim.step(warmup, "boris")
     sim.sync()
     log(f"{precision}: {warmup} warm-up steps done")
-    sim.profile(stages=["particles"])
+    sim.profile(stages=["particles"], every=TIMING_EVERY)
     t0 = time.perf_counter()
     sim.step(steps, "boris")
     sim.sync()
@@ -387,12 +430,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--timing-overhead", action="store_true",
+                    help="step time of the pair plasma with each stage-timing mode, in "
+                         "windows separated by idle (for a kernel trace)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device with torch (a plain copy kernel "
                          "of known size, for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
@@ -404,6 +450,9 @@ def main():
         del src, dst
         log("copied 1 GiB device-to-device")
 
+    if args.timing_overhead:
+        print(json.dumps(run_timing_overhead(args)))
+        return
     if args.workload.startswith("synchro"):
         print(json.dumps(run_synchro(args)))
         return

@@ -152,14 +152,15 @@ fetd_status fetd3_diagnostics(fetd3_sim *sim, fetd3_diag *out);
 /* Per-stage device time with HIP events: enable != 0 starts (and resets)
  * timing of every stage, 0 stops it; fetd3_profile_mask times only the
  * stages whose bit (1 << stage) is set (stages: 0 Faraday + record,
- * 1 particles, 2 Ampere, 3 SpMV, 4 sort).  Stages 0-3 pass their events to
- * their kernel dispatches (hipExtLaunchKernel: start of the first kernel,
- * end of the last); the sort records them around its launches.  A timed
- * dispatch costs the step a few microseconds.  fetd3_stage_times: ms[5]
- * gets the accumulated milliseconds per stage, *launches the particle
- * launches timed. */
+ * 1 particles, 2 Ampere, 3 SpMV, 4 sort), on steps whose index is a
+ * multiple of every (>= 1, else FETD_E_ARG).  Stages 0-3 pass their events
+ * to their kernel dispatches (hipExtLaunchKernel: start of the first
+ * kernel, end of the last); the sort records them around its launches.  A
+ * dispatch that carries events leaves the device idle for several
+ * microseconds around it.  fetd3_stage_times: ms[5] gets the accumulated
+ * milliseconds per stage, *launches the particle launches timed. */
 fetd_status fetd3_profile(fetd3_sim *sim, int32_t enable);
-fetd_status fetd3_profile_mask(fetd3_sim *sim, int32_t stage_mask);
+fetd_status fetd3_profile_mask(fetd3_sim *sim, int32_t stage_mask, int32_t every);
 fetd_status fetd3_stage_times(fetd3_sim *sim, double *ms, int64_t *launches);
 
 /* Message of the last failed call on sim (thread-local one if sim is NULL). */

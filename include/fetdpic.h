@@ -243,10 +243,13 @@ fetd_status fetd_diagnostics(fetd_sim *sim, fetd_diag *out);
 fetd_status fetd_profile(fetd_sim *sim, int32_t enable);
 
 /* As fetd_profile, timing only the stages whose bit (1 << stage) is set in
- * stage_mask (bits above FETD_N_STAGES are ignored; 0 stops timing).  A
- * timed dispatch costs the step a few microseconds, so a run whose own
- * duration is measured times only the stage it needs. */
-fetd_status fetd_profile_mask(fetd_sim *sim, int32_t stage_mask);
+ * stage_mask (bits above FETD_N_STAGES are ignored; 0 stops timing), and
+ * only on steps whose index is a multiple of every (>= 1, else FETD_E_ARG).
+ * A dispatch that carries events leaves the device idle for several
+ * microseconds around it, so a run whose own duration is measured times
+ * only the stage it needs, on a sample of its steps (an every coprime with
+ * the re-sort interval samples every phase of the sort cycle). */
+fetd_status fetd_profile_mask(fetd_sim *sim, int32_t stage_mask, int32_t every);
 
 /* Device milliseconds summed per stage since timing started, and the number
  * of timed launches per stage (arrays of FETD_N_STAGES).  Synchronises. */

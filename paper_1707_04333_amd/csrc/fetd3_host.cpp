@@ -115,6 +115,7 @@ struct fetd3_sim {
 
     // stage timing
     uint32_t profile_mask = 0;  // bit k: stage k is timed
+    int64_t profile_every = 1;  // on steps that are multiples of this
     std::vector<hipEvent_t> event_pool, all_events;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[5];  // recorded, not yet read
     double stage_ms[5] = {0, 0, 0, 0, 0};
@@ -834,7 +835,7 @@ struct StageTimer3 {
     hipEvent_t a = nullptr, b = nullptr;
     StageTimer3(fetd3_sim *sim, int stage) : s(sim), k(stage)
     {
-        if (!(s->profile_mask >> k & 1u)) return;
+        if (!(s->profile_mask >> k & 1u) || s->step % s->profile_every != 0) return;
         a = s->take_event();
         b = a ? s->take_event() : nullptr;
         if (!b) {
@@ -1292,15 +1293,16 @@ fetd_status fetd3_diagnostics(fetd3_sim *s, fetd3_diag *out)
 
 fetd_status fetd3_profile(fetd3_sim *s, int32_t enable)
 {
-    return fetd3_profile_mask(s, enable ? 0x1F : 0);
+    return fetd3_profile_mask(s, enable ? 0x1F : 0, 1);
 }
 
-fetd_status fetd3_profile_mask(fetd3_sim *s, int32_t stage_mask)
+fetd_status fetd3_profile_mask(fetd3_sim *s, int32_t stage_mask, int32_t every)
 {
-    if (!s) return FETD_E_ARG;
+    if (!s || every < 1) return FETD_E_ARG;
     DeviceGuard3 g(s->device);
     s->resolve_timers();
     s->profile_mask = uint32_t(stage_mask) & 0x1Fu;
+    s->profile_every = every;
     for (double &v : s->stage_ms) v = 0;
     s->particle_launches = 0;
     return FETD_OK;

@@ -127,6 +127,7 @@ struct fetd_sim {
     std::string err;
     // stage timing
     uint32_t profile_mask = 0;  // bit k: stage k is timed
+    int64_t profile_every = 1;  // on steps that are multiples of this
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[FETD_N_STAGES];
     std::vector<hipEvent_t> event_pool;
     hipEvent_t take_event()
@@ -149,7 +150,7 @@ struct fetd_sim {
         hipEvent_t a = nullptr, b = nullptr;
         Timer(fetd_sim *s_, int st) : s(s_), stage(st)
         {
-            if (!(s->profile_mask >> stage & 1u)) return;
+            if (!(s->profile_mask >> stage & 1u) || s->step % s->profile_every != 0) return;
             a = s->take_event();
             b = a ? s->take_event() : nullptr;
             if (!b) {
@@ -1502,12 +1503,12 @@ fetd_status fetd_diagnostics(fetd_sim *s, fetd_diag *out)
 
 fetd_status fetd_profile(fetd_sim *s, int32_t enable)
 {
-    return fetd_profile_mask(s, enable ? (1 << FETD_N_STAGES) - 1 : 0);
+    return fetd_profile_mask(s, enable ? (1 << FETD_N_STAGES) - 1 : 0, 1);
 }
 
-fetd_status fetd_profile_mask(fetd_sim *s, int32_t stage_mask)
+fetd_status fetd_profile_mask(fetd_sim *s, int32_t stage_mask, int32_t every)
 {
-    if (!s) return FETD_E_ARG;
+    if (!s || every < 1) return FETD_E_ARG;
     DeviceGuard g(s->device);
     hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "profile");
@@ -1519,6 +1520,7 @@ fetd_status fetd_profile_mask(fetd_sim *s, int32_t stage_mask)
         v.clear();
     }
     s->profile_mask = uint32_t(stage_mask) & ((1u << FETD_N_STAGES) - 1);
+    s->profile_every = every;
     return FETD_OK;
 }
 
@@ -1553,9 +1555,10 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     DeviceGuard g(s->device);
     fetd_status st;
     const int32_t was_mask = int32_t(s->profile_mask);
+    const int32_t was_every = int32_t(s->profile_every);
     const int saved = s->resort_every;
     // one timed sort
-    if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4)))) return st;
+    if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4), 1))) return st;
     {
         fetd_sim::Timer t(s, 4);
         if ((st = sort_all(s))) return st;
@@ -1569,7 +1572,7 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     const int nsp = int(std::count_if(s->species.begin(), s->species.end(),
                                       [](const Species &x) { return x.n > 0; }));
     std::vector<double> tp(trial_steps, 0.0);
-    if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4)))) return st;
+    if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4), 1))) return st;
     if ((st = fetd_pic_step(s, trial_steps, pusher))) return st;
     hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "autotune");
@@ -1593,7 +1596,7 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     }
     s->resort_every = best;
     s->steps_since_sort = trial_steps;  // the order has decayed: sort at the next step
-    if ((st = fetd_profile_mask(s, was_mask))) return st;
+    if ((st = fetd_profile_mask(s, was_mask, was_every))) return st;
     if (chosen) *chosen = best;
     return FETD_OK;
 }

@@ -61,7 +61,7 @@ def lib():
                "fetd3_fields_get": [P, I32, P, I64, P],
                "fetd3_particles_get": [P, I32, I64, P, P, P, P, P, P],
                "fetd3_diagnostics": [P, P], "fetd3_profile": [P, I32],
-               "fetd3_profile_mask": [P, I32],
+               "fetd3_profile_mask": [P, I32, I32],
                "fetd3_stage_times": [P, P, P]}
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -183,11 +183,12 @@ class Sim3:
         _check(lib().fetd3_diagnostics(self.h, ctypes.byref(d)), self.h)
         return d.as_dict()
 
-    def profile(self, enable=True, stages=None):
-        """Stage timing on (every stage, or only the named ones of STAGES3) or off."""
-        if stages is not None and enable:
-            mask = sum(1 << STAGES3.index(k) for k in set(stages))
-            _check(lib().fetd3_profile_mask(self.h, mask), self.h)
+    def profile(self, enable=True, stages=None, every=1):
+        """Stage timing on (every stage, or only the named ones of STAGES3;
+        on every step, or on steps that are multiples of every) or off."""
+        if enable and (stages is not None or every != 1):
+            mask = sum(1 << STAGES3.index(k) for k in set(STAGES3 if stages is None else stages))
+            _check(lib().fetd3_profile_mask(self.h, mask, int(every)), self.h)
         else:
             _check(lib().fetd3_profile(self.h, 1 if enable else 0), self.h)
 

@@ -95,7 +95,7 @@ def lib():
         L.fetd_last_error.argtypes = [P]
         L.fetd_last_error.restype = ctypes.c_char_p
         optional = {"fetd_profile": [P, ctypes.c_int32], "fetd_stage_times": [P, P, P],
-                    "fetd_profile_mask": [P, ctypes.c_int32],
+                    "fetd_profile_mask": [P, ctypes.c_int32, ctypes.c_int32],
                     "fetd_autotune": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_set_resort": [P, ctypes.c_int32],
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
@@ -315,10 +315,12 @@ def stage_mask(stages):
     return sum(1 << STAGES.index(k) for k in set(stages))
 
 
-def profile(h, enable=True, stages=None):
-    """Stage timing on (every stage, or only the named ones) or off."""
-    if stages is not None and enable:
-        _check(lib().fetd_profile_mask(h, stage_mask(stages)), h)
+def profile(h, enable=True, stages=None, every=1):
+    """Stage timing on (every stage, or only the named ones; on every
+    step, or on steps that are multiples of every) or off."""
+    if enable and (stages is not None or every != 1):
+        mask = stage_mask(STAGES if stages is None else stages)
+        _check(lib().fetd_profile_mask(h, mask, int(every)), h)
     else:
         _check(lib().fetd_profile(h, 1 if enable else 0), h)
 
@@ -398,8 +400,8 @@ class Sim:
     def info(self):
         return info(self.h)
 
-    def profile(self, enable=True, stages=None):
-        profile(self.h, enable, stages)
+    def profile(self, enable=True, stages=None, every=1):
+        profile(self.h, enable, stages, every)
 
     def autotune(self, pusher="boris", trial_steps=160):
         return autotune(self.h, pusher, trial_steps)

@@ -45,7 +45,7 @@ def test_argument_errors_without_device():
     assert L.fetd_mesh_create(None, None, None) == fetdpic.FETD_E_ARG
     assert b"out is NULL" in L.fetd_last_error(None)
     assert L.fetd_pic_step(None, 1, 0) == fetdpic.FETD_E_ARG
-    assert L.fetd_profile_mask(None, 2) == fetdpic.FETD_E_ARG
+    assert L.fetd_profile_mask(None, 2, 1) == fetdpic.FETD_E_ARG
     L.fetd_destroy(None)
 
 
@@ -57,5 +57,5 @@ def test_tet_argument_errors_without_device():
     assert L.fetd3_mesh_create(None, None, None) == -1
     assert b"out is NULL" in L.fetd3_last_error(None)
     assert L.fetd3_pic_step(None, 1, 0) == -1
-    assert L.fetd3_profile_mask(None, 2) == -1
+    assert L.fetd3_profile_mask(None, 2, 1) == -1
     L.fetd3_destroy(None)

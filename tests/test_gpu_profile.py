@@ -1,7 +1,8 @@
 """Stage timing through the C-ABI (fetd_profile_mask, fetd3_profile_mask):
-a mask times only its stages, the events carried by the kernel dispatches
-give one positive interval per launch, and the timed stages, which run one
-after another on one stream, never add up to more than the run's wall time."""
+a mask times only its stages, a sampling period only the steps whose index
+is its multiple, the events carried by the kernel dispatches give one
+positive interval per launch, and the timed stages, which run one after
+another on one stream, never add up to more than the run's wall time."""
 import time
 
 import pytest
@@ -40,6 +41,13 @@ def test_stage_mask_triangles():
     assert st["particles"][1] == 10 * len(w.species)
     assert st["sort"][1] >= 1 and st["sort"][0] > 0
     assert sum(v[0] for v in st.values()) <= wall
+    s0 = sim.diagnostics()["step"]
+    sim.profile(stages=["particles"], every=4)
+    _timed(sim, 12)
+    st = sim.stage_times()
+    sampled = sum(1 for k in range(s0, s0 + 12) if k % 4 == 0)
+    assert st["particles"][1] == sampled * len(w.species) and st["particles"][0] > 0
+    assert st["faraday"] == (0.0, 0)
     sim.profile(False)
     _timed(sim, 5)
     assert all(v == (0.0, 0) for v in sim.stage_times().values())
@@ -63,6 +71,12 @@ def test_stage_mask_tetrahedra():
     st, n = sim.stage_times()
     assert n == 10 * len(w.species)
     assert min(st.values()) > 0 and sum(st.values()) <= wall
+    s0 = sim.diagnostics()["step"]
+    sim.profile(stages=["particles"], every=3)
+    _timed(sim, 10)
+    st, n = sim.stage_times()
+    assert n == sum(1 for k in range(s0, s0 + 10) if k % 3 == 0) * len(w.species)
+    assert st["particles"] > 0 and st["faraday"] == st["sort"] == 0.0
     sim.profile(False)
     d = sim.diagnostics()
     assert d["gauss_rel"] <= 1e-12 and d["divb_rel"] <= 1e-13
