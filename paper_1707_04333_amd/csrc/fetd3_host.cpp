@@ -106,7 +106,15 @@ struct fetd3_sim {
     uint32_t *d_key[2] = {nullptr, nullptr};
     char *d_lam[2] = {nullptr, nullptr}, *d_u[2] = {nullptr, nullptr};  // [3][p_cap] reals
     int32_t *d_pid[2] = {nullptr, nullptr};
+    int32_t *d_perm = nullptr;  // [p_cap] sort permutation
     int pbuf = 0;
+    // Live count of each species after its last sort, copied by the stream
+    // into pinned host memory and applied to Species3::n at the next
+    // synchronising call (until then n bounds the live particles from above:
+    // the slots past the live ones hold removed keys).
+    int32_t *h_alive = nullptr;
+    size_t h_alive_cap = 0;
+    std::vector<char> alive_pending;
 
     // state
     int64_t step = 0, steps_since_sort = 0;
@@ -700,8 +708,13 @@ Mesh3 mesh_view(const fetd3_sim *s)
 fetd_status check_errors3(fetd3_sim *s)
 {
     unsigned long long c[4];
-    fetd_status st = download3(s, c, s->d_counters, sizeof c);
+    fetd_status st = download3(s, c, s->d_counters, sizeof c);  // synchronises
     if (st) return st;
+    for (size_t i = 0; i < s->alive_pending.size() && i < s->species.size(); ++i)
+        if (s->alive_pending[i]) {
+            s->species[i].n = s->h_alive[i];
+            s->alive_pending[i] = 0;
+        }
     if (c[2]) {
         return s->fail(FETD_E_TRACK, std::string(c[2] & 1 ? "crossing cap exceeded" :
                                                               "non-finite momentum") +
@@ -785,6 +798,9 @@ fetd_status grow_particles3(fetd3_sim *s, int64_t extra)
         s->d_u[b] = u;
         s->d_pid[b] = pid;
     }
+    s->release(s->d_perm);
+    s->d_perm = nullptr;
+    if (!s->alloc(&s->d_perm, cap)) return s->fail(FETD_E_OOM, "particle allocation failed");
     s->p_cap = cap;
     return FETD_OK;
 }
@@ -792,7 +808,23 @@ fetd_status grow_particles3(fetd3_sim *s, int64_t extra)
 fetd_status sort_all3(fetd3_sim *s)
 {
     const int cb = s->pbuf, ob = 1 - s->pbuf;
-    for (Species3 &sp : s->species) {
+    if (s->h_alive_cap < s->species.size()) {
+        // a copy into the old buffer may be in flight
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (e == hipSuccess && s->h_alive) e = hipHostFree(s->h_alive);
+        s->h_alive = nullptr;
+        s->h_alive_cap = 0;
+        s->alive_pending.clear();
+        const size_t cap = std::max<size_t>(16, 2 * s->species.size());
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&s->h_alive), sizeof(int32_t) * cap,
+                              hipHostMallocDefault);
+        if (e != hipSuccess) return s->hip_fail(e, "sort");
+        s->h_alive_cap = cap;
+        s->alive_pending.assign(cap, 0);
+    }
+    for (size_t si = 0; si < s->species.size(); ++si) {
+        Species3 &sp = s->species[si];
         if (sp.n == 0) continue;
         Sort3 a;
         a.n = sp.n;
@@ -810,15 +842,16 @@ fetd_status sort_all3(fetd3_sim *s)
         a.counts = s->d_counts;
         a.cursor = s->d_cursor;
         a.chunk_sums = s->d_chunk_sums;
+        a.perm = s->d_perm + sp.offset;
         // the tail beyond the live particles keeps lost keys
         hipError_t e = hipMemsetAsync(a.key_out, 0xFF, 4 * size_t(sp.n), s->stream);
         if (e == hipSuccess) e = launch3_sort(s->stream, a);
-        int32_t alive = 0;
+        // cursor[nt] ends at the total of live particles
         if (e == hipSuccess)
-            e = hipMemcpyAsync(&alive, s->d_cursor + s->nt, 4, hipMemcpyDeviceToHost, s->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+            e = hipMemcpyAsync(s->h_alive + si, s->d_cursor + s->nt, 4, hipMemcpyDeviceToHost,
+                               s->stream);
         if (e != hipSuccess) return s->hip_fail(e, "sort");
-        sp.n = alive;  // cursor[nt] ends at the total of live particles
+        s->alive_pending[si] = 1;
     }
     s->pbuf = ob;
     s->steps_since_sort = 0;
@@ -1328,6 +1361,7 @@ void fetd3_destroy(fetd3_sim *s)
         if (s->stream) (void)hipStreamSynchronize(s->stream);
         for (void *p : s->allocs) (void)hipFree(p);
         s->allocs.clear();
+        if (s->h_alive) (void)hipHostFree(s->h_alive);
         for (hipEvent_t e : s->all_events) (void)hipEventDestroy(e);
         if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     }

@@ -82,6 +82,7 @@ struct Sort3 {
     int32_t *counts;      // [nt + 1]
     int32_t *cursor;      // [nt + 1]
     int32_t *chunk_sums;  // [ceil((nt + 1) / 1024)]
+    int32_t *perm;        // [n] input index of each output slot
 };
 
 // Sliced-ELL sparse matrix: 64-row slices, column-major inside a slice.

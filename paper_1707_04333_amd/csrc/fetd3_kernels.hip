@@ -766,11 +766,13 @@ __global__ __launch_bounds__(1024) void k3_scan_add(int n, int32_t *__restrict__
     if (i < n) cursor[i] += sums[blockIdx.x];
 }
 
-// ... and scatter: every block ranks its particles inside their window
+// ... then scatter: every block ranks its particles inside their window
 // bins, reserves each touched tetrahedron's places with one atomic, and
-// writes its particles out in destination order through an LDS
-// permutation (particles outside the window reserve their place alone).
-template <typename R>
+// writes, in destination order through an LDS permutation, the input index
+// of each place (particles outside the window reserve their place alone).
+// Only this 4-byte index is scattered: particles that moved to a
+// neighbouring tetrahedron land a few at a time in many places, and each
+// such write fills part of a line ...
 __global__ __launch_bounds__(256) void k3_sort_scatter(Sort3 a)
 {
     __shared__ int32_t cnt[kSortBins3];  // count per bin, then its global base
@@ -844,19 +846,29 @@ __global__ __launch_bounds__(256) void k3_sort_scatter(Sort3 a)
     }
     __syncthreads();
     const int nin = n_in, nout = n_out;
-    const R *li = static_cast<const R *>(a.lam_in), *ui = static_cast<const R *>(a.u_in);
-    R *lo = static_cast<R *>(a.lam_out), *uo = static_cast<R *>(a.u_out);
     for (int s = tid; s < kSortB3; s += 256) {
         if (s >= nin && s < kSortB3 - nout) continue;
-        const int64_t i = b0 + s_src[s];
-        const int64_t q = s_dst[s];
-        a.key_out[q] = a.key_in[i];
-        a.pid_out[q] = a.pid_in[i];
+        a.perm[s_dst[s]] = int32_t(b0 + s_src[s]);
+    }
+}
+
+// ... and every output slot below the live total gathers its particle:
+// the writes are sequential and the reads come from nearby slots of the
+// nearly sorted input.
+template <typename R>
+__global__ __launch_bounds__(256) void k3_sort_gather(Sort3 a)
+{
+    const int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (q >= int64_t(a.cursor[a.nt])) return;
+    const int64_t i = a.perm[q];
+    const R *li = static_cast<const R *>(a.lam_in), *ui = static_cast<const R *>(a.u_in);
+    R *lo = static_cast<R *>(a.lam_out), *uo = static_cast<R *>(a.u_out);
+    a.key_out[q] = a.key_in[i];
+    a.pid_out[q] = a.pid_in[i];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            lo[c * a.stride_out + q] = li[c * a.stride_in + i];
-            uo[c * a.stride_out + q] = ui[c * a.stride_in + i];
-        }
+    for (int c = 0; c < 3; ++c) {
+        lo[c * a.stride_out + q] = li[c * a.stride_in + i];
+        uo[c * a.stride_out + q] = ui[c * a.stride_in + i];
     }
 }
 
@@ -991,12 +1003,11 @@ hipError_t launch3_sort(hipStream_t s, const Sort3 &a)
                        a.chunk_sums);
     hipLaunchKernelGGL(k3_scan_totals, dim3(1), dim3(1024), 0, s, nchunk, a.chunk_sums);
     hipLaunchKernelGGL(k3_scan_add, dim3(nchunk), dim3(1024), 0, s, n1, a.cursor, a.chunk_sums);
+    hipLaunchKernelGGL(k3_sort_scatter, dim3(grid_for(a.n, kSortB3)), dim3(256), 0, s, a);
     if (a.elem_bytes == 4)
-        hipLaunchKernelGGL(k3_sort_scatter<float>, dim3(grid_for(a.n, kSortB3)), dim3(256), 0, s,
-                           a);
+        hipLaunchKernelGGL(k3_sort_gather<float>, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(k3_sort_scatter<double>, dim3(grid_for(a.n, kSortB3)), dim3(256), 0, s,
-                           a);
+        hipLaunchKernelGGL(k3_sort_gather<double>, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
