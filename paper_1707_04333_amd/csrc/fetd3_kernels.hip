@@ -435,23 +435,35 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
     __shared__ double s_hval[kHash3];
     __shared__ int s_hkey[kHash3];
     __shared__ int s_base;
+    const int64_t n = a.stride;
+    R *lam = static_cast<R *>(a.lam);
+    R *u = static_cast<R *>(a.u);
+    // The particle's streams are requested first, so they are in flight
+    // while the block sets up its current window.
+    uint32_t key = kLost;
+    R s0 = R(0), s1 = R(0), s2 = R(0), v0 = R(0), v1 = R(0), v2 = R(0);
+    if (p < a.n) {
+        key = a.key[p];
+        s0 = lam[p];
+        s1 = lam[n + p];
+        s2 = lam[2 * n + p];
+        v0 = u[p];
+        v1 = u[n + p];
+        v2 = u[2 * n + p];
+    }
     for (int j = threadIdx.x; j < kWin3; j += blockDim.x) s_win[j] = 0.0;
     for (int j = threadIdx.x; j < kHash3; j += blockDim.x) {
         s_hkey[j] = -1;
         s_hval[j] = 0.0;
     }
     if (threadIdx.x == 0) {
-        // home: the tetrahedron of the block's first particle (read before
-        // any thread of the block writes its key)
-        const uint32_t k0 = a.key[blk * blockDim.x];
-        const int home = k0 == kLost ? 0 : int(k0 & kTetMask);
+        // home: the tetrahedron of the block's first particle (thread 0's
+        // own, read before any thread of the block writes its key)
+        const int home = key == kLost ? 0 : int(key & kTetMask);
         s_base = int(m.tet_ebase[home]) - kBack3;
     }
     __syncthreads();
     const Window3 win{s_win, s_hkey, s_hval, a.cur, s_base};
-    const int64_t n = a.stride;
-    R *lam = static_cast<R *>(a.lam);
-    R *u = static_cast<R *>(a.u);
     const R *rec = static_cast<const R *>(a.rec);
     const R *grad = static_cast<const R *>(sizeof(R) == 4 ? static_cast<const void *>(m.grad32)
                                                           : static_cast<const void *>(m.grad));
@@ -462,11 +474,10 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
     double L[4] = {0.0, 0.0, 0.0, 0.0};
     R rx = R(0), ry = R(0), rz = R(0);
     if (p < a.n) {
-        const uint32_t key = a.key[p];
         if (key != kLost) {
             t = int(key & kTetMask);
             r = int(key >> 30);
-            unpack_lambda(r, double(lam[p]), double(lam[n + p]), double(lam[2 * n + p]), L);
+            unpack_lambda(r, double(s0), double(s1), double(s2), L);
             const R *rc = rec + size_t(kRec) * t;
             V3<R> E{R(0), R(0), R(0)}, B{R(0), R(0), R(0)};
 #pragma unroll
@@ -477,7 +488,7 @@ __global__ __launch_bounds__(256) void k3_particles(Mesh3 m, Step3 a)
             }
             if (a.b_ext)
                 B = B + V3<R>{R(a.b_ext[3 * t]), R(a.b_ext[3 * t + 1]), R(a.b_ext[3 * t + 2])};
-            const V3<R> u0{u[p], u[n + p], u[2 * n + p]};
+            const V3<R> u0{v0, v1, v2};
             const R al = R(a.alpha);
             const V3<R> u1 = push3<P, R>(u0, al * E, al * B, R(a.c), R(a.inv_c2));
             u[p] = u1.x;
