@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/sec + achieved HBM GB/s; mixed/batched vs FP64 at Gauss residual"
 HBM_PEAK_GBS = 8000.0
+DEFAULT_PAIRS = 8_000_000
 KERNEL_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particle_step_pair_plasma_traffic.json")
 KERNEL3_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd3_kernels.hip")
@@ -346,7 +347,8 @@ def run_tet(args):
                      "roofline": {"bound": "hbm", "kernel": "k3_particles", "achieved": achieved,
                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                   "frac": achieved / HBM_PEAK_GBS,
-                                  "traffic": measured_traffic(prec, TRAFFIC3_FILE, KERNEL3_SRC),
+                                  "traffic": (measured_traffic(prec, TRAFFIC3_FILE, KERNEL3_SRC)
+                                              if args.pairs == DEFAULT_PAIRS else None),
                                   "avg_launch_ms": avg_s * 1e3,
                                   "algorithmic_bytes_per_launch": per_launch},
                      "stage_ms_per_step": stages,
@@ -425,7 +427,7 @@ def main():
     ap.add_argument("--workload", default="pair")
     ap.add_argument("--theta", type=float, default=0.1)
     ap.add_argument("--pusher", default=None)
-    ap.add_argument("--pairs", type=int, default=8_000_000)
+    ap.add_argument("--pairs", type=int, default=DEFAULT_PAIRS)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -476,7 +478,9 @@ def main():
     per_launch_bytes = float(np.mean([particle_launch_bytes(n, nf, ne, True) for n in species_n]))
     avg_s = ms / 1e3 / max(launches, 1)
     achieved = per_launch_bytes / avg_s / 1e9
-    traffic = measured_traffic("mixed") if args.workload == "pair" else None
+    # the counters were taken on the default workload size only
+    counted = args.workload == "pair" and args.pairs == DEFAULT_PAIRS
+    traffic = measured_traffic("mixed") if counted else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -514,8 +518,7 @@ def main():
                        "ms_per_step": r64["elapsed"] / args.steps * 1e3,
                        "gauss_rel": r64["diag"]["gauss_rel"], "resort_every": r64["resort"],
                        "particle_kernel_gbs": a64, "particle_kernel_frac": a64 / HBM_PEAK_GBS,
-                       "particle_kernel_traffic": (measured_traffic("fp64")
-                                                   if args.workload == "pair" else None),
+                       "particle_kernel_traffic": measured_traffic("fp64") if counted else None,
                        "stage_ms_per_step": {k: v[0] / r64["stage_steps"]
                                              for k, v in r64["stages"].items()}}
         out["mixed_vs_fp64"] = value / out["fp64"]["value"]

@@ -1,0 +1,66 @@
+"""bench.py's output contract: one GPU only; the oracle baseline record;
+the committed HBM counter records still match the kernel sources they were
+taken on (else the bench would report traffic as null); and, on the GPU,
+one JSON line carrying every field of the contract."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_traffic_records_match_the_kernel_sources():
+    for prec in ("mixed", "fp64"):
+        for rec, src in ((bench.TRAFFIC_FILE, bench.KERNEL_SRC),
+                         (bench.TRAFFIC3_FILE, bench.KERNEL3_SRC)):
+            t = bench.measured_traffic(prec, rec, src)
+            assert t is not None and t > 0, (rec, prec)
+
+
+def test_traffic_is_null_for_another_source(tmp_path):
+    other = tmp_path / "k.hip"
+    other.write_text("// not the kernel the counters were taken on\n")
+    assert bench.measured_traffic("mixed", bench.TRAFFIC_FILE, str(other)) is None
+
+
+def test_cpu_baseline_record(oracle_lib):
+    cb = bench.cpu_baseline(0.1, 16_000_000, "boris", sample_pairs=2000, sample_steps=2)
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["unit"] == "particle-steps/s"
+    assert cb["value"] > 0 and "4000 of the 16000000 particles, 2 steps" in cb["sample"]
+
+
+@pytest.mark.gpu
+def test_bench_json_line():
+    r = subprocess.run([sys.executable, "bench.py", "--pairs", "50000", "--steps", "20",
+                        "--warmup", "5", "--no-batched", "--no-autotune", "--no-cpu",
+                        "--no-fp64"], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = r.stdout.strip().splitlines()
+    assert len(lines) == 1
+    out = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+              "roofline"):
+        assert k in out, k
+    assert out["n_gpus"] == 1 and out["steps"] == 20 and out["warmup"] == 5
+    assert out["config"]["workload"] == "pair" and out["value"] > 0
+    rl = out["roofline"]
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in rl, k
+    assert rl["bound"] == "hbm" and rl["unit"] == "GB/s" and rl["peak"] == 8000.0
+    assert rl["traffic"] is None  # the counters were taken on the default size only
+    assert abs(rl["frac"] - rl["achieved"] / rl["peak"]) < 1e-12
