@@ -437,3 +437,33 @@ def test_field_probes_match_oracle(oracle_lib):
     want = np.array(want)
     assert got.shape == (5, 40, 2)
     assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
+
+
+def test_crossing_sequence_step_by_step(oracle_lib):
+    """FP64, one step at a time for 100 steps: after every step the triangle
+    and slot of every particle are bit-exact, the step's number of straight
+    pieces (one per triangle visited) is equal, and the step's edge current,
+    which sums every piece's W1 integral, agrees to 1e-12 of its scale, so
+    each particle's crossing sequence is the oracle's."""
+    w = I.pair_plasma(n_side=16, length=0.025, n_pairs=3001, theta=0.3, steps=100,
+                      precision="fp64")
+    osim = _oracle_sim(oracle_lib, w, 1)
+    g = _gpu_sim(w, 1)
+    seg0 = g.diagnostics()["n_segments"]
+    oseg0 = osim.segments
+    for step in range(100):
+        osim.step(1, "vay")
+        g.step(1, "vay")
+        for si, s in enumerate(osim.species):
+            gp = g.particles(si)
+            alive = np.nonzero(s.tri >= 0)[0]
+            assert np.array_equal(gp["id"], alive), step
+            assert np.array_equal(gp["tri"], s.tri[alive]), step
+            assert np.array_equal(gp["slot"], s.slot[alive]), step
+        seg = g.diagnostics()["n_segments"]
+        assert seg - seg0 == osim.segments - oseg0, step
+        seg0, oseg0 = seg, osim.segments
+        j = g.field("j")
+        scale = max(float(np.abs(osim.last_cur).max()), 1e-300)
+        assert np.abs(j - osim.last_cur).max() <= 1e-12 * scale, step
+    g.close()
