@@ -1299,17 +1299,33 @@ hipError_t launch_spmv_batched(hipStream_t s, const FieldDesc *d, const uint32_t
     return hipGetLastError();
 }
 
+// Blocks of a kernel resident per CU (HIP's occupancy calculator), so a
+// persistent launch holds no block that would wait for others to finish
+// their whole tile lists before it starts.
+static unsigned resident_per_cu(const void *kernel, unsigned fallback)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess ||
+        nb < 1)
+        return fallback;
+    return unsigned(nb);
+}
+
 template <int P>
 static void launch_particles_batched_p(hipStream_t s, const SegDesc *segs, const uint32_t *prefix,
                                        int nseg, uint32_t total, bool fp32)
 {
-    const unsigned grid = persistent_grid(total, 6);
-    if (fp32)
-        hipLaunchKernelGGL((k_particle_batched<P, float>), dim3(grid), dim3(kBlock), 0, s, segs,
-                           prefix, nseg, total);
-    else
-        hipLaunchKernelGGL((k_particle_batched<P, double>), dim3(grid), dim3(kBlock), 0, s, segs,
-                           prefix, nseg, total);
+    if (fp32) {
+        static const unsigned per_cu = resident_per_cu(
+            reinterpret_cast<const void *>(&k_particle_batched<P, float>), 4);
+        hipLaunchKernelGGL((k_particle_batched<P, float>), dim3(persistent_grid(total, per_cu)),
+                           dim3(kBlock), 0, s, segs, prefix, nseg, total);
+    } else {
+        static const unsigned per_cu = resident_per_cu(
+            reinterpret_cast<const void *>(&k_particle_batched<P, double>), 4);
+        hipLaunchKernelGGL((k_particle_batched<P, double>), dim3(persistent_grid(total, per_cu)),
+                           dim3(kBlock), 0, s, segs, prefix, nseg, total);
+    }
 }
 
 hipError_t launch_particles_batched(hipStream_t s, const SegDesc *segs, const uint32_t *prefix,
