@@ -13,12 +13,14 @@ gather/push/track/deposit stage for both species, Ampere, the SPAI SpMV,
 and the counting sort when due.  Beside it: the same workload in FP64, the
 batched sweep (64 independent uneven runs, one launch per phase per step,
 graph replay) against the same runs stepped one by one, the Gauss residual
-of each, the fused particle kernel on the HBM roofline from HIP-event
-timings of its launches inside the timed region, and the FP64 CPU oracle on
-a bounded sample of the same workload.
+of each, the fused particle kernel on the HBM roofline from HIP events
+that its launches on every 7th step of the timed region carry in their own
+dispatches, and the FP64 CPU oracle on a bounded sample of the same
+workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
                        [--workload pair|large|boosted|cyclotron|bernstein|synchro|tet]
+                       [--timing-overhead]
 """
 import argparse
 import hashlib
