@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < newest:
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, *srcs, "-lm"])
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, *srcs, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -81,6 +81,8 @@ def _declare(L):
                               ctypes.c_double, ctypes.c_int, ctypes.c_int64, P, P, P, P, P,
                               P, P]
     L.o_particles.restype = ctypes.c_int
+    L.o_particles_omp.argtypes = [ctypes.c_int] + L.o_particles.argtypes
+    L.o_particles_omp.restype = ctypes.c_int
     L.o_charge.argtypes = [P, ctypes.c_double, ctypes.c_int64, P, P, P, P]
     L.o_charge.restype = None
     L.o_spai.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, ctypes.c_int64]
@@ -353,7 +355,11 @@ class OracleSim:
                                              "edge_tsign", "edge_free", "mt_ptr", "mt_col",
                                              "mt_val"]])
 
-    def step(self, n_steps=1, pusher="boris"):
+    def step(self, n_steps=1, pusher="boris", threads=1):
+        """n_steps steps with the given pusher.  threads > 1 runs the
+        particle stage on that many OpenMP threads (the timing mode:
+        contiguous chunks of particles, private currents added in thread
+        order); the default single thread is the parity mode."""
         L = lib()
         pid = PUSHERS[pusher] if isinstance(pusher, str) else int(pusher)
         ms = ctypes.byref(self.ms)
@@ -363,10 +369,14 @@ class OracleSim:
             counts = np.zeros(2, dtype=np.int64)
             bad = np.zeros(1, dtype=np.int64)
             for s in self.species:
-                rc = L.o_particles(ms, _p(self.e), _p(self.e_ext), _p(self.b), _p(b_new),
-                                   _p(self.bz_ext), _p(self.affine), pid, s.q, s.m, s.w,
-                                   self.dt, self.c, self.cap, s.n, _p(s.tri), _p(s.slot),
-                                   _p(s.lam), _p(s.u), _p(self.cur), _p(counts), _p(bad))
+                args = (ms, _p(self.e), _p(self.e_ext), _p(self.b), _p(b_new),
+                        _p(self.bz_ext), _p(self.affine), pid, s.q, s.m, s.w,
+                        self.dt, self.c, self.cap, s.n, _p(s.tri), _p(s.slot),
+                        _p(s.lam), _p(s.u), _p(self.cur), _p(counts), _p(bad))
+                if threads > 1:
+                    rc = L.o_particles_omp(int(threads), *args)
+                else:
+                    rc = L.o_particles(*args)
                 if rc != 0:
                     raise RuntimeError(f"oracle particle stage failed rc={rc} at particle {bad[0]}")
             L.o_ampere(ms, _p(b_new), _p(self.cur), self.dt, self.mu0, _p(self.damp),

@@ -586,3 +586,56 @@ int64_t o_spai(int n, const int32_t *ptr, const int32_t *col, const double *val,
     free(cptr);
     return ok;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Timing mode: the particle stage of o_particles spread over nthreads      */
+/* OpenMP threads.  The particles are cut into nthreads contiguous chunks;  */
+/* each thread runs o_particles on its chunk with a private current array,  */
+/* and the private arrays are added into cur in thread order (a fixed        */
+/* order: the result does not depend on scheduling, though its rounding     */
+/* differs from the single-threaded sum).  Used to time the oracle on all   */
+/* host cores; parity runs use o_particles.  Returns as o_particles; on an  */
+/* error the first failing chunk's code and particle are reported.          */
+/* ---------------------------------------------------------------------- */
+int o_particles_omp(int nthreads, const o_mesh *M, const double *e, const double *e_ext,
+                    const double *b_old, const double *b_new, const double *bz_ext,
+                    const double *affine, int pusher, double q, double m, double w,
+                    double dt, double c, int cap, int64_t n, int32_t *tri, int8_t *slot,
+                    double *lam, double *u, double *cur, int64_t *counts, int64_t *bad)
+{
+    if (nthreads < 1) nthreads = 1;
+    double *priv = calloc((size_t)nthreads * (size_t)M->ne, sizeof(double));
+    int64_t *pc = calloc((size_t)nthreads * 2, sizeof(int64_t));
+    int64_t *pbad = calloc((size_t)nthreads, sizeof(int64_t));
+    int *prc = calloc((size_t)nthreads, sizeof(int));
+    if (!priv || !pc || !pbad || !prc) {
+        free(priv);
+        free(pc);
+        free(pbad);
+        free(prc);
+        return -3;
+    }
+#pragma omp parallel for num_threads(nthreads) schedule(static, 1)
+    for (int t = 0; t < nthreads; ++t) {
+        int64_t lo = n * t / nthreads, hi = n * (t + 1) / nthreads;
+        prc[t] = o_particles(M, e, e_ext, b_old, b_new, bz_ext, affine, pusher, q, m, w, dt, c,
+                             cap, hi - lo, tri + lo, slot + lo, lam + 2 * lo, u + 2 * lo,
+                             priv + (size_t)t * M->ne, pc + 2 * t, pbad + t);
+        if (prc[t] != 0) pbad[t] += lo;
+    }
+    int rc = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        for (int ed = 0; ed < M->ne; ++ed) cur[ed] += priv[(size_t)t * M->ne + ed];
+        counts[0] += pc[2 * t];
+        counts[1] += pc[2 * t + 1];
+        if (rc == 0 && prc[t] != 0) {
+            rc = prc[t];
+            *bad = pbad[t];
+        }
+    }
+    free(priv);
+    free(pc);
+    free(pbad);
+    free(prc);
+    return rc;
+}
