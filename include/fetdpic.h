@@ -71,11 +71,25 @@ typedef enum {
 /* Pushers of Sec. II.C. */
 typedef enum { FETD_BORIS = 0, FETD_BORIS_TAN = 1, FETD_VAY = 2, FETD_HC = 3 } fetd_pusher;
 
-/* FETD_FP64: every stage in FP64.  FETD_MIXED: particle positions
- * (barycentric pair) and momenta stored in FP32, gather/push/track in FP32;
- * the current deposit, its accumulation, the field update and the Gauss
- * accounting stay FP64 (charge is conserved to FP64 rounding). */
-typedef enum { FETD_FP64 = 0, FETD_MIXED = 1 } fetd_precision;
+/* FETD_FP64: every stage in FP64; a particle's gather, push, move and
+ * tracking take the operations of their definitions in order (no fused
+ * multiply-adds, IEEE divisions and square roots), so given the same field
+ * values its state is the one a plain FP64 evaluation gives, bit for bit.
+ * FETD_MIXED: particle positions (barycentric pair) and momenta stored in
+ * FP32, gather/push/track in FP32; the current weights and their
+ * accumulation, the primary electric state d and the Gauss accounting in
+ * FP64 (charge is conserved to FP64 rounding); e, b and the values of the
+ * approximate inverse M~ stored in FP32 (the field update reads and writes
+ * them in FP32 and computes in FP64).
+ * FETD_MIXED_F64FIELD: as FETD_MIXED with e, b and M~ in FP64. */
+typedef enum { FETD_FP64 = 0, FETD_MIXED = 1, FETD_MIXED_F64FIELD = 2 } fetd_precision;
+
+/* Largest particle count of one species and largest mesh: the particle
+ * kernel addresses its streams and per-triangle tables with 32-bit byte
+ * offsets.  Larger loads and meshes are rejected with FETD_E_ARG before
+ * any device work. */
+#define FETD_MAX_SPECIES_PARTICLES ((int64_t)268434432) /* 2^28 - 1024 */
+#define FETD_MAX_TRIS ((int32_t)67108864)               /* 2^26 */
 
 typedef struct fetd_sim fetd_sim;
 typedef void *(*fetd_alloc_fn)(size_t bytes, void *user);
@@ -104,6 +118,13 @@ typedef struct {
     void *alloc_user;
     int32_t crossing_cap; /* maximum edge crossings per particle per step; 0 = 64 */
     int32_t resort_every; /* re-sort particles by triangle every k steps; 0 = 20 */
+    int32_t deterministic; /* != 0: every result is independent of the order in which
+                              particles are stored, tiled, sorted or batched, bit for
+                              bit: each current contribution is added as an integer to
+                              a fixed-point accumulator per edge (3 x 32 bits below the
+                              largest contribution's power of two, one device integer
+                              atomic per limb), converted to FP64 once per step.  The
+                              sum differs from a sequential FP64 sum only by rounding. */
 } fetd_opts;
 
 /* Field / table selectors for fetd_fields_get. */
@@ -202,9 +223,14 @@ fetd_status fetd_particles_load_bary(fetd_sim *sim, double q, double m, double w
                                      int32_t *species_out);
 
 /* Same, from Cartesian positions xy[2n]: each point is located in the
- * lowest-id triangle that contains it (periodic images included). */
+ * lowest-id triangle that contains it (periodic images included).
+ * tri_hint [n] or NULL: a triangle expected to contain each point; where it
+ * does (the point or a periodic image inside or on its boundary) it is
+ * taken without a search, else the point is searched for as without a
+ * hint; hints out of range are ignored. */
 fetd_status fetd_particles_load(fetd_sim *sim, double q, double m, double w, int64_t n,
-                                const double *xy, const double *u, int32_t *species_out);
+                                const double *xy, const double *u, const int32_t *tri_hint,
+                                int32_t *species_out);
 
 /* Advance n_steps PIC steps with the given pusher (fetd_pusher).
  * Asynchronous on the simulation's stream. */
@@ -260,9 +286,12 @@ fetd_status fetd_stage_times(fetd_sim *sim, double *ms, int64_t *launches);
  * steps with the given pusher while timing the particle stage of every step
  * and the sort with HIP events, then set the re-sort interval K that
  * minimises (T_sort + sum_{j<K} T_particles(j)) / K over the candidates
- * 5, 10, 20, 40, 80, 160 (up to trial_steps).  *chosen gets K.  The
+ * 5, 10, 20, 40, 80, 160 (up to trial_steps).  *chosen gets K; cost_ms
+ * ([6] or NULL) gets that cost per step in ms for each candidate, -1 for
+ * candidates beyond trial_steps.  The trial steps are ordinary steps: the
  * simulation advances by trial_steps steps. */
-fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps, int32_t *chosen);
+fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps, int32_t *chosen,
+                          double *cost_ms);
 
 /* Set the re-sort interval directly (k >= 1). */
 fetd_status fetd_set_resort(fetd_sim *sim, int32_t every);
@@ -275,11 +304,21 @@ fetd_status fetd_set_resort(fetd_sim *sim, int32_t every);
  * stream and have the same precision; they stay individually usable
  * (fields_get, particles_get, diagnostics) between batch steps.  The batch
  * keeps pointers to the simulations: destroy it before them.  Re-sorting
- * follows resort_every of the first simulation. */
+ * follows resort_every of the first simulation.  Members must also agree
+ * on the deterministic option.  The batch runs on a non-blocking stream
+ * of its own and orders itself after the members' earlier work and before
+ * their later work with events, so a graph can be captured also when the
+ * members use the legacy default stream.  The particle launch takes its
+ * tiles from a queue, the (run, species) segments ordered largest first. */
 typedef struct fetd_batch fetd_batch;
 fetd_status fetd_batch_create(fetd_sim *const *sims, int32_t n, int32_t use_graph,
                               fetd_batch **out);
 fetd_status fetd_batch_step(fetd_batch *batch, int32_t n_steps, int32_t pusher);
+
+/* Counters of a batch: graphs captured, graph replays (each a cycle of two
+ * re-sort intervals) and steps enqueued eagerly. */
+fetd_status fetd_batch_stats(fetd_batch *batch, int64_t *graph_captures, int64_t *graph_replays,
+                             int64_t *eager_steps);
 void fetd_batch_destroy(fetd_batch *batch);
 
 /* Field probes (Sec. III.C samples E along a line at every step to obtain

@@ -12,8 +12,20 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfetdpic.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["fetd_kernels.hip", "fetd_host.cpp", "fetd_sparse.cpp", "fetd3_kernels.hip",
-           "fetd3_host.cpp"]
+# (source, object name, extra flags).  The particle kernels are built once
+# per precision: FP32 with the compiler's default contraction, FP64 and the
+# field kernels with contraction off (each FP64 update is the plain
+# sequence of rounded operations of its definition).
+SOURCES = [
+    ("fetd_kernels.hip", "fetd_kernels", ["-ffp-contract=off"]),
+    ("fetd_particles.hip", "fetd_particles_f32", ["-DFETD_REAL=float", "-DFETD_REAL_IS_DOUBLE=0"]),
+    ("fetd_particles.hip", "fetd_particles_f64",
+     ["-DFETD_REAL=double", "-DFETD_REAL_IS_DOUBLE=1", "-ffp-contract=off"]),
+    ("fetd_host.cpp", "fetd_host", []),
+    ("fetd_sparse.cpp", "fetd_sparse", []),
+    ("fetd3_kernels.hip", "fetd3_kernels", []),
+    ("fetd3_host.cpp", "fetd3_host", []),
+]
 ARCH = os.environ.get("FETD_OFFLOAD_ARCH", "gfx950")
 
 
@@ -34,9 +46,10 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     cc = hipcc()
 
-    def compile_one(src):
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+    def compile_one(item):
+        src, name, extra = item
+        obj = os.path.join(BUILD, name + ".o")
+        cmd = [cc, *flags(), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -23,6 +23,9 @@
 
 using namespace fetd;
 
+static_assert(FETD_MAX_SPECIES_PARTICLES == kMaxSpeciesParticles, "particle limit");
+static_assert(FETD_MAX_TRIS == kMaxTris, "mesh limit");
+
 fetd_timing::Pending &fetd_timing::pending()
 {
     thread_local Pending p;
@@ -81,14 +84,17 @@ struct fetd_sim {
     int4 *d_tri_edge = nullptr, *d_tri_nbr = nullptr, *d_tri_node = nullptr, *d_edge_face = nullptr;
     int2 *d_edge_nodes = nullptr;
     uint32_t *d_tri_ebase = nullptr;
-    double *d_grad64 = nullptr, *d_vxy64 = nullptr, *d_inv_mu_area = nullptr, *d_inv_2area = nullptr;
+    double *d_grad64 = nullptr, *d_vxy64 = nullptr, *d_mu_area = nullptr, *d_two_area = nullptr;
     float *d_grad32 = nullptr, *d_vxy32 = nullptr;
     int32_t *d_sl_ptr = nullptr, *d_sl_w = nullptr, *d_sl_col = nullptr;
-    double *d_sl_val = nullptr;
+    void *d_sl_val = nullptr;  // FP64, or FP32 in the FP32-field mode
     // device: fields
-    double *d_b = nullptr, *d_h = nullptr, *d_d = nullptr, *d_e = nullptr;
+    void *d_b = nullptr, *d_h = nullptr, *d_e = nullptr;  // field type (FP64 or FP32)
+    double *d_d = nullptr;
     double *d_cur = nullptr;       // current accumulator of the step in progress
     double *d_cur_last = nullptr;  // current of the last completed step
+    unsigned long long *d_fx = nullptr;  // deterministic mode: fixed-point current limbs [3 ne]
+    bool deterministic = false;
     void *d_rec = nullptr;
     double *d_bz_ext = nullptr, *d_e_ext = nullptr, *d_damp = nullptr, *d_damp_b = nullptr;
     bool has_affine = false;
@@ -225,8 +231,11 @@ struct fetd_sim {
     }
     std::vector<std::pair<void *, size_t>> allocs;
 
-    bool fp32() const { return precision == FETD_MIXED; }
+    // particle state in FP32 (both mixed modes); field state in FP32 (FETD_MIXED)
+    bool fp32() const { return precision != FETD_FP64; }
+    bool field32() const { return precision == FETD_MIXED; }
     size_t real_bytes() const { return fp32() ? 4 : 8; }
+    size_t field_bytes() const { return field32() ? 4 : 8; }
 };
 
 namespace {
@@ -524,14 +533,14 @@ fetd_status upload_mesh(fetd_sim *s)
         en[r] = make_int2(s->edge_lo[e], s->edge_hi[e]);
     }
     std::vector<float> g32(8 * size_t(nf), 0.f), v32(8 * size_t(nf), 0.f);
-    std::vector<double> imua(nf), i2a(nf);
+    std::vector<double> mua(nf), a2(nf);
     for (int f = 0; f < nf; ++f) {
         for (int k = 0; k < 6; ++k) {
             g32[8 * f + k] = float(s->grad[6 * f + k]);
             v32[8 * f + k] = float(s->vxy[6 * f + k]);
         }
-        imua[f] = 1.0 / (s->mu0 * s->area[f]);
-        i2a[f] = 1.0 / (2.0 * s->area[f]);
+        mua[f] = s->mu0 * s->area[f];
+        a2[f] = 2.0 * s->area[f];
     }
     fetd_status st;
     if ((st = upload(s, &s->d_tri_edge, te.data(), nf))) return st;
@@ -544,8 +553,8 @@ fetd_status upload_mesh(fetd_sim *s)
     if ((st = upload(s, &s->d_vxy64, s->vxy.data(), s->vxy.size()))) return st;
     if ((st = upload(s, &s->d_grad32, g32.data(), g32.size()))) return st;
     if ((st = upload(s, &s->d_vxy32, v32.data(), v32.size()))) return st;
-    if ((st = upload(s, &s->d_inv_mu_area, imua.data(), imua.size()))) return st;
-    if ((st = upload(s, &s->d_inv_2area, i2a.data(), i2a.size()))) return st;
+    if ((st = upload(s, &s->d_mu_area, mua.data(), mua.size()))) return st;
+    if ((st = upload(s, &s->d_two_area, a2.data(), a2.size()))) return st;
     // SELL-64 of M~ in device edge order (wall rows are empty: e = 0 there)
     const int nsl = (ne + kSlice - 1) / kSlice;
     std::vector<int32_t> sp(nsl + 1, 0), sw(nsl, 0);
@@ -577,16 +586,36 @@ fetd_status upload_mesh(fetd_sim *s)
     if ((st = upload(s, &s->d_sl_ptr, sp.data(), sp.size()))) return st;
     if ((st = upload(s, &s->d_sl_w, sw.data(), sw.size()))) return st;
     if ((st = upload(s, &s->d_sl_col, scol.data(), scol.size()))) return st;
-    if ((st = upload(s, &s->d_sl_val, sval.data(), sval.size()))) return st;
-    // fields
-    if ((st = alloc_zero(s, &s->d_b, nf))) return st;
-    if ((st = alloc_zero(s, &s->d_h, nf))) return st;
+    if (s->field32()) {
+        std::vector<float> sv32(sval.begin(), sval.end());
+        float *p32 = nullptr;
+        if ((st = upload(s, &p32, sv32.data(), sv32.size()))) return st;
+        s->d_sl_val = p32;
+    } else {
+        double *p64 = nullptr;
+        if ((st = upload(s, &p64, sval.data(), sval.size()))) return st;
+        s->d_sl_val = p64;
+    }
+    // fields (e, b, h in the field type; d and the currents in FP64)
+    const size_t fb = s->field_bytes();
+    for (void **fld : {&s->d_b, &s->d_h}) {
+        char *p = nullptr;
+        std::vector<char> z(fb * size_t(nf), 0);
+        if ((st = upload(s, &p, z.data(), z.size()))) return st;
+        *fld = p;
+    }
+    {
+        char *p = nullptr;
+        std::vector<char> z(fb * size_t(ne), 0);
+        if ((st = upload(s, &p, z.data(), z.size()))) return st;
+        s->d_e = p;
+    }
     if ((st = alloc_zero(s, &s->d_d, ne))) return st;
-    if ((st = alloc_zero(s, &s->d_e, ne))) return st;
     if ((st = alloc_zero(s, &s->d_cur, ne))) return st;
     if ((st = alloc_zero(s, &s->d_cur_last, ne))) return st;
+    if (s->deterministic && (st = alloc_zero(s, &s->d_fx, 3 * size_t(ne)))) return st;
     void *rec = nullptr;
-    if (!s->dev_alloc(&rec, 8 * s->real_bytes() * size_t(nf)))
+    if (!s->dev_alloc(&rec, 32 * size_t(nf)))
         return s->fail(FETD_E_OOM, "device allocation failed");
     s->d_rec = rec;
     if ((st = alloc_zero(s, &s->d_counts, size_t(nf) + 1))) return st;
@@ -727,7 +756,7 @@ fetd_status grow_particles(fetd_sim *s, int64_t extra)
     return FETD_OK;
 }
 
-fetd_status sort_all(fetd_sim *s)
+fetd_status sort_all(fetd_sim *s, hipStream_t stream)
 {
     const int cb = s->pbuf, ob = 1 - s->pbuf;
     const size_t rb = s->real_bytes();
@@ -750,7 +779,7 @@ fetd_status sort_all(fetd_sim *s)
         a.elem_bytes = int(2 * rb);
         a.tile_home = s->d_tile_home + sp.bc_offset;
         // launch_sort fills key_out with the lost key first (slots past the alive count)
-        hipError_t e = launch_sort(s->stream, a);
+        hipError_t e = launch_sort(stream, a);
         if (e != hipSuccess) return s->hip_fail(e, "sort");
     }
     s->pbuf = ob;
@@ -801,6 +830,111 @@ fetd_status take_baseline(fetd_sim *s)
     return FETD_OK;
 }
 
+// Exponent E of the deterministic accumulator: a current contribution is
+// sigma (Q/dt) w_k with |w_k| <= 1 up to rounding, so every contribution of
+// the step is below 2^E in magnitude.
+int fx_exponent(const fetd_sim *s)
+{
+    double m = 0.0;
+    for (const Species &sp : s->species) m = std::max(m, std::fabs(sp.q * sp.w / s->dt));
+    return m > 0.0 ? std::ilogb(m) + 2 : 0;
+}
+
+MeshView mesh_view(const fetd_sim *s)
+{
+    MeshView mv;
+    mv.tri_edge = s->d_tri_edge;
+    mv.tri_nbr = s->d_tri_nbr;
+    mv.grad64 = s->d_grad64;
+    mv.grad32 = s->d_grad32;
+    mv.vxy64 = s->d_vxy64;
+    mv.vxy32 = s->d_vxy32;
+    mv.tri_ebase = s->d_tri_ebase;
+    return mv;
+}
+
+FieldDesc field_desc(const fetd_sim *s)
+{
+    FieldDesc d{};
+    d.nf = s->nf;
+    d.ne = s->ne;
+    d.rec_fp32 = s->fp32() ? 1 : 0;
+    d.field32 = s->field32() ? 1 : 0;
+    d.tri_edge = s->d_tri_edge;
+    d.e = s->d_e;
+    d.e_ext = s->d_e_ext;
+    d.e_scale = s->e_scale;
+    d.b = s->d_b;
+    d.damp_b = s->d_damp_b;
+    d.h = s->d_h;
+    d.mu_area = s->d_mu_area;
+    d.two_area = s->d_two_area;
+    d.bz_ext = s->d_bz_ext;
+    d.grad64 = s->d_grad64;
+    d.rec = s->d_rec;
+    d.dt = s->dt;
+    d.edge_face = s->d_edge_face;
+    d.cur = s->d_cur;
+    d.cur_last = s->d_cur_last;
+    d.d = s->d_d;
+    d.damp = s->d_damp;
+    d.fx = s->d_fx;
+    d.fx_unscale = std::ldexp(1.0, fx_exponent(s) - 96);
+    d.sl_ptr = s->d_sl_ptr;
+    d.sl_w = s->d_sl_w;
+    d.sl_col = s->d_sl_col;
+    d.sl_val = s->d_sl_val;
+    d.e_out = s->d_e;
+    return d;
+}
+
+StepArgs step_args(const fetd_sim *s, const Species &sp, int pbuf)
+{
+    const size_t rb = s->real_bytes();
+    StepArgs a;
+    a.n = sp.n;
+    a.key = s->d_key[pbuf] + sp.offset;
+    a.lam = static_cast<char *>(s->d_lam[pbuf]) + 2 * rb * sp.offset;
+    a.u = static_cast<char *>(s->d_u[pbuf]) + 2 * rb * sp.offset;
+    a.pid = s->d_pid[pbuf] + sp.offset;
+    a.rec = s->d_rec;
+    a.cur = s->d_cur;
+    a.fx = s->d_fx;
+    a.fx_scale = std::ldexp(1.0, 96 - fx_exponent(s));
+    a.qdt = sp.q * sp.w / s->dt;
+    a.alpha = sp.q * s->dt / (2.0 * sp.m);
+    a.dt = s->dt;
+    a.c = s->c;
+    a.c2 = s->c * s->c;
+    a.inv_c2 = 1.0 / (s->c * s->c);
+    a.cap = s->cap;
+    a.has_affine = s->has_affine ? 1 : 0;
+    for (int k = 0; k < 6; ++k) a.aff[k] = s->affine[k];
+    a.counters = s->d_counters;
+    a.block_counts = s->d_block_counts + 2 * sp.bc_offset;
+    a.tile_home = s->d_tile_home + sp.bc_offset;
+    return a;
+}
+
+// A field array (e, b: the field type) to host doubles; edge arrays are
+// permuted from device to canonical order.
+fetd_status download_field(fetd_sim *s, double *dst, const void *src, int64_t n, bool edge)
+{
+    std::vector<double> tmp(static_cast<size_t>(n));
+    if (s->field32()) {
+        std::vector<float> f(static_cast<size_t>(n));
+        if (fetd_status st = download(s, f.data(), src, 4 * size_t(n))) return st;
+        for (int64_t i = 0; i < n; ++i) tmp[i] = double(f[i]);
+    } else if (fetd_status st = download(s, tmp.data(), src, 8 * size_t(n))) {
+        return st;
+    }
+    if (edge)
+        for (int64_t e = 0; e < n; ++e) dst[e] = tmp[s->edev[e]];
+    else
+        std::copy(tmp.begin(), tmp.end(), dst);
+    return FETD_OK;
+}
+
 }  // namespace
 
 // =====================================================================
@@ -816,13 +950,18 @@ fetd_status fetd_mesh_create(const fetd_mesh_desc *mesh, const fetd_opts *opts, 
     }
     *out = nullptr;
     if (!mesh || !opts || !mesh->node_xy || !mesh->tri_nodes || mesh->n_nodes <= 0 ||
-        mesh->n_tris <= 0 || mesh->n_tris > int32_t(kTriMask)) {
+        mesh->n_tris <= 0) {
         g_last_error = "invalid mesh description";
         return FETD_E_ARG;
     }
+    if (mesh->n_tris > FETD_MAX_TRIS) {
+        g_last_error = "mesh has more than FETD_MAX_TRIS triangles";
+        return FETD_E_ARG;
+    }
     if (!(opts->dt > 0) || !(opts->eps0 > 0) || !(opts->mu0 > 0) || !(opts->c > 0) ||
-        (opts->precision != FETD_FP64 && opts->precision != FETD_MIXED) || opts->spai_level < -1 ||
-        opts->spai_level > 4) {
+        (opts->precision != FETD_FP64 && opts->precision != FETD_MIXED &&
+         opts->precision != FETD_MIXED_F64FIELD) ||
+        opts->spai_level < -1 || opts->spai_level > 4) {
         g_last_error = "invalid options";
         return FETD_E_ARG;
     }
@@ -844,6 +983,7 @@ fetd_status fetd_mesh_create(const fetd_mesh_desc *mesh, const fetd_opts *opts, 
     s->alloc_user = opts->alloc_user;
     s->cap = opts->crossing_cap > 0 ? opts->crossing_cap : 64;
     s->resort_every = opts->resort_every > 0 ? opts->resort_every : 20;
+    s->deterministic = opts->deterministic != 0;
     if ((s->alloc_cb == nullptr) != (s->free_cb == nullptr)) {
         delete s;
         g_last_error = "alloc and free callbacks must be given together";
@@ -997,8 +1137,14 @@ fetd_status fetd_fields_load(fetd_sim *s, const double *b, const double *d)
             if (!std::isfinite(d[e])) return s->fail(FETD_E_ARG, "d must be finite");
     if (hipError_t e = hipStreamSynchronize(s->stream)) return s->hip_fail(e, "fields_load");
     if (b) {
-        hipError_t e = hipMemcpyAsync(s->d_b, b, 8 * size_t(s->nf), hipMemcpyHostToDevice,
-                                      s->stream);
+        std::vector<float> b32;
+        const void *src = b;
+        if (s->field32()) {
+            b32.assign(b, b + s->nf);
+            src = b32.data();
+        }
+        hipError_t e = hipMemcpyAsync(s->d_b, src, s->field_bytes() * size_t(s->nf),
+                                      hipMemcpyHostToDevice, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) return s->hip_fail(e, "b upload");
     }
@@ -1009,8 +1155,7 @@ fetd_status fetd_fields_load(fetd_sim *s, const double *b, const double *d)
             if (!s->edge_free[e]) df[e] = 0.0;
         fetd_status st = upload_edges(s, &s->d_d, df.data());
         if (st) return st;
-        hipError_t e = launch_spmv(s->stream, s->ne, s->d_sl_ptr, s->d_sl_w, s->d_sl_col,
-                                   s->d_sl_val, s->d_d, s->d_e);
+        hipError_t e = launch_spmv(s->stream, field_desc(s));
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) return s->hip_fail(e, "fields_load spmv");
     }
@@ -1024,7 +1169,9 @@ fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, 
                                      const double *u, int32_t *species_out)
 {
     if (!s) return FETD_E_ARG;
-    if (n < 0 || (n > 0 && (!tri || !lam || !u)) || !(m > 0) || n > (int64_t(1) << 31) - 1)
+    if (n > FETD_MAX_SPECIES_PARTICLES)
+        return s->fail(FETD_E_ARG, "species has more than FETD_MAX_SPECIES_PARTICLES particles");
+    if (n < 0 || (n > 0 && (!tri || !lam || !u)) || !(m > 0))
         return s->fail(FETD_E_ARG, "invalid particle arguments");
     DeviceGuard g(s->device);
     for (int64_t i = 0; i < n; ++i) {
@@ -1080,7 +1227,7 @@ fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, 
     if (species_out) *species_out = int32_t(s->species.size() - 1);
     s->have_baseline = false;
     // sorted order for the segmented deposit
-    if (n > 0 && (st = sort_all(s))) return st;
+    if (n > 0 && (st = sort_all(s, s->stream))) return st;
     return FETD_OK;
 }
 
@@ -1088,7 +1235,8 @@ fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, 
 // periodic axes, the point or an image one period away) and its barycentric
 // pair (lambda_1, lambda_2).  `what` names the points in the error message.
 fetd_status locate_points(fetd_sim *s, int64_t n, const double *xy, std::vector<int32_t> &tri,
-                          std::vector<double> &lam, const char *what)
+                          std::vector<double> &lam, const char *what,
+                          const int32_t *hint = nullptr)
 {
 #pragma clang fp contract(off)
     // uniform bucket grid over triangle bounding boxes
@@ -1121,9 +1269,35 @@ fetd_status locate_points(fetd_sim *s, int64_t n, const double *xy, std::vector<
     tri.assign(size_t(n), -1);
     lam.assign(2 * size_t(n), 0.0);
     const int mx = s->period[0] > 0 ? 1 : 0, my = s->period[1] > 0 ? 1 : 0;
+    // barycentric pair of (qx, qy) in triangle f, true if inside or on it
+    auto inside = [s](int f, double qx, double qy, double &l1, double &l2) {
+        const double *v = &s->vxy[6 * f];
+        const double den = (v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1]);
+        l1 = ((qx - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (qy - v[1])) / den;
+        l2 = ((v[2] - v[0]) * (qy - v[1]) - (qx - v[0]) * (v[3] - v[1])) / den;
+        return l1 >= 0 && l2 >= 0 && l1 + l2 <= 1;
+    };
     for (int64_t p = 0; p < n; ++p) {
         int best = -1;
         double bl1 = 0, bl2 = 0;
+        if (hint && hint[p] >= 0 && hint[p] < s->nf) {
+            for (int sx = -mx; sx <= mx && best < 0; ++sx)
+                for (int sy = -my; sy <= my && best < 0; ++sy) {
+                    double l1, l2;
+                    if (inside(hint[p], xy[2 * p] + double(sx) * s->period[0],
+                               xy[2 * p + 1] + double(sy) * s->period[1], l1, l2)) {
+                        best = hint[p];
+                        bl1 = l1;
+                        bl2 = l2;
+                    }
+                }
+            if (best >= 0) {
+                tri[p] = best;
+                lam[2 * p] = bl1;
+                lam[2 * p + 1] = bl2;
+                continue;
+            }
+        }
         for (int sx = -mx; sx <= mx; ++sx)
             for (int sy = -my; sy <= my; ++sy) {
                 const double qx = xy[2 * p] + double(sx) * s->period[0];
@@ -1133,11 +1307,8 @@ fetd_status locate_points(fetd_sim *s, int64_t n, const double *xy, std::vector<
                 const int bj = std::clamp(int((qy - y0) / by), 0, nb - 1);
                 for (int f : bucket[size_t(bj) * nb + bi]) {
                     if (best >= 0 && f >= best) break;
-                    const double *v = &s->vxy[6 * f];
-                    const double den = (v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1]);
-                    const double l1 = ((qx - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (qy - v[1])) / den;
-                    const double l2 = ((v[2] - v[0]) * (qy - v[1]) - (qx - v[0]) * (v[3] - v[1])) / den;
-                    if (l1 >= 0 && l2 >= 0 && l1 + l2 <= 1) {
+                    double l1, l2;
+                    if (inside(f, qx, qy, l1, l2)) {
                         best = f;
                         bl1 = l1;
                         bl2 = l2;
@@ -1156,13 +1327,16 @@ fetd_status locate_points(fetd_sim *s, int64_t n, const double *xy, std::vector<
 }
 
 fetd_status fetd_particles_load(fetd_sim *s, double q, double m, double w, int64_t n,
-                                const double *xy, const double *u, int32_t *species_out)
+                                const double *xy, const double *u, const int32_t *tri_hint,
+                                int32_t *species_out)
 {
     if (!s) return FETD_E_ARG;
+    if (n > FETD_MAX_SPECIES_PARTICLES)
+        return s->fail(FETD_E_ARG, "species has more than FETD_MAX_SPECIES_PARTICLES particles");
     if (n < 0 || (n > 0 && (!xy || !u))) return s->fail(FETD_E_ARG, "invalid particle arguments");
     std::vector<int32_t> tri;
     std::vector<double> lam;
-    if (fetd_status st = locate_points(s, n, xy, tri, lam, "particle")) return st;
+    if (fetd_status st = locate_points(s, n, xy, tri, lam, "particle", tri_hint)) return st;
     return fetd_particles_load_bary(s, q, m, w, n, tri.data(), nullptr, lam.data(), u, species_out);
 }
 
@@ -1171,7 +1345,7 @@ fetd_status fetd_sort(fetd_sim *s)
     if (!s) return FETD_E_ARG;
     DeviceGuard g(s->device);
     fetd_sim::Timer t(s, 4);
-    return sort_all(s);
+    return sort_all(s, s->stream);
 }
 
 fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
@@ -1181,71 +1355,41 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
     DeviceGuard g(s->device);
     fetd_status st;
     if (!s->have_baseline && (st = take_baseline(s))) return st;
-    MeshView mv;
-    mv.tri_edge = s->d_tri_edge;
-    mv.tri_nbr = s->d_tri_nbr;
-    mv.grad64 = s->d_grad64;
-    mv.grad32 = s->d_grad32;
-    mv.vxy64 = s->d_vxy64;
-    mv.vxy32 = s->d_vxy32;
-    mv.tri_ebase = s->d_tri_ebase;
-    const size_t rb = s->real_bytes();
+    const MeshView mv = mesh_view(s);
+    const FieldDesc fd = field_desc(s);
     for (int it = 0; it < n_steps; ++it) {
         if (s->steps_since_sort >= s->resort_every) {
             fetd_sim::Timer t(s, 4);
-            if ((st = sort_all(s))) return st;
+            if ((st = sort_all(s, s->stream))) return st;
         }
         hipError_t e;
         {
-        fetd_sim::Timer t(s, 0);
-        e = launch_faraday(s->stream, s->nf, s->d_tri_edge, s->d_e, s->d_e_ext, s->e_scale, s->d_b,
-                           s->d_damp_b, s->d_h, s->d_inv_mu_area, s->d_inv_2area, s->d_bz_ext,
-                           s->d_grad64, s->d_rec, s->fp32(), s->dt);
+            fetd_sim::Timer t(s, 0);
+            e = launch_faraday(s->stream, fd);
         }
         if (e != hipSuccess) return s->hip_fail(e, "faraday");
-        double *cur = s->d_cur;
         for (const Species &sp : s->species) {
-            StepArgs a;
-            a.n = sp.n;
-            a.key = s->d_key[s->pbuf] + sp.offset;
-            a.lam = static_cast<char *>(s->d_lam[s->pbuf]) + 2 * rb * sp.offset;
-            a.u = static_cast<char *>(s->d_u[s->pbuf]) + 2 * rb * sp.offset;
-            a.pid = s->d_pid[s->pbuf] + sp.offset;
-            a.rec = s->d_rec;
-            a.cur = cur;
-            a.qdt = sp.q * sp.w / s->dt;
-            a.alpha = sp.q * s->dt / (2.0 * sp.m);
-            a.dt = s->dt;
-            a.c = s->c;
-            a.inv_c2 = 1.0 / (s->c * s->c);
-            a.cap = s->cap;
-            a.has_affine = s->has_affine ? 1 : 0;
-            for (int k = 0; k < 6; ++k) a.aff[k] = s->affine[k];
-            a.counters = s->d_counters;
-            a.block_counts = s->d_block_counts + 2 * sp.bc_offset;
-            a.tile_home = s->d_tile_home + sp.bc_offset;
+            const StepArgs a = step_args(s, sp, s->pbuf);
             fetd_sim::Timer t(s, 1);
             e = launch_particles(s->stream, mv, a, pusher, s->fp32());
             if (e != hipSuccess) return s->hip_fail(e, "particle step");
         }
         {
             fetd_sim::Timer t(s, 2);
-            e = launch_ampere(s->stream, s->ne, s->d_edge_face, s->d_h, cur, s->d_cur_last, s->d_d,
-                              s->d_damp, s->dt);
+            e = launch_ampere(s->stream, fd);
         }
         if (e != hipSuccess) return s->hip_fail(e, "ampere");
         {
             fetd_sim::Timer t(s, 3);
-            e = launch_spmv(s->stream, s->ne, s->d_sl_ptr, s->d_sl_w, s->d_sl_col, s->d_sl_val,
-                            s->d_d, s->d_e);
+            e = launch_spmv(s->stream, fd);
         }
         if (e != hipSuccess) return s->hip_fail(e, "spmv");
         if (s->probe_n > 0 && s->probe_samples < s->probe_max) {
             const bool flush = ++s->probe_in_window == s->probe_every;
             double *out = flush ? s->d_probe_buf + 2 * s->probe_n * s->probe_samples : nullptr;
             e = launch_probe(s->stream, int(s->probe_n), s->d_probe_tri, s->d_probe_lam,
-                             s->d_tri_edge, s->d_grad64, s->d_e, s->d_probe_acc, out,
-                             1.0 / double(s->probe_every));
+                             s->d_tri_edge, s->d_grad64, s->d_e, s->field32(), s->d_probe_acc,
+                             out, 1.0 / double(s->probe_every));
             if (e != hipSuccess) return s->hip_fail(e, "probe");
             if (flush) {
                 ++s->probe_samples;
@@ -1318,12 +1462,12 @@ fetd_status fetd_fields_get(fetd_sim *s, int32_t which, void *dst, int64_t capac
     if (st) return st;
     const void *src = nullptr;
     size_t bytes = 0;
-    bool host = false, edge = false;
+    bool host = false, edge = false, field = false;
     std::vector<int32_t> tmp;
     switch (which) {
-    case FETD_FIELD_E: src = s->d_e; bytes = 8 * size_t(s->ne); edge = true; break;
+    case FETD_FIELD_E: src = s->d_e; bytes = 8 * size_t(s->ne); edge = true; field = true; break;
     case FETD_FIELD_D: src = s->d_d; bytes = 8 * size_t(s->ne); edge = true; break;
-    case FETD_FIELD_B: src = s->d_b; bytes = 8 * size_t(s->nf); break;
+    case FETD_FIELD_B: src = s->d_b; bytes = 8 * size_t(s->nf); field = true; break;
     case FETD_FIELD_J: src = s->d_cur_last; bytes = 8 * size_t(s->ne); edge = true; break;
     case FETD_FIELD_Q:
         if ((st = compute_charge(s))) return st;
@@ -1358,6 +1502,8 @@ fetd_status fetd_fields_get(fetd_sim *s, int32_t which, void *dst, int64_t capac
         std::memcpy(dst, src, bytes);
         return FETD_OK;
     }
+    if (field)
+        return download_field(s, static_cast<double *>(dst), src, int64_t(bytes / 8), edge);
     if (edge) return download_edges(s, static_cast<double *>(dst), static_cast<const double *>(src));
     return download(s, dst, src, bytes);
 }
@@ -1427,9 +1573,9 @@ fetd_status fetd_diagnostics(fetd_sim *s, fetd_diag *out)
     std::vector<double> q(nn), dv(nn), e(ne), d(ne), b(s->nf), jl(ne);
     if ((st = download(s, q.data(), s->d_q, 8 * size_t(nn)))) return st;
     if ((st = download(s, dv.data(), s->d_divd, 8 * size_t(nn)))) return st;
-    if ((st = download_edges(s, e.data(), s->d_e))) return st;
+    if ((st = download_field(s, e.data(), s->d_e, ne, true))) return st;
     if ((st = download_edges(s, d.data(), s->d_d))) return st;
-    if ((st = download(s, b.data(), s->d_b, 8 * size_t(s->nf)))) return st;
+    if ((st = download_field(s, b.data(), s->d_b, s->nf, false))) return st;
     if ((st = download_edges(s, jl.data(), s->d_cur_last))) return st;
     double gmax = 0, qmax = 0;
     for (int n = 0; n < nn; ++n) {
@@ -1549,7 +1695,8 @@ fetd_status fetd_set_resort(fetd_sim *s, int32_t every)
     return FETD_OK;
 }
 
-fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int32_t *chosen)
+fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int32_t *chosen,
+                          double *cost_ms)
 {
     if (!s || trial_steps < 2 || pusher < 0 || pusher > 3) return FETD_E_ARG;
     DeviceGuard g(s->device);
@@ -1561,7 +1708,7 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4), 1))) return st;
     {
         fetd_sim::Timer t(s, 4);
-        if ((st = sort_all(s))) return st;
+        if ((st = sort_all(s, s->stream))) return st;
     }
     double ms[FETD_N_STAGES];
     int64_t n[FETD_N_STAGES];
@@ -1584,15 +1731,20 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     }
     int best = saved;
     double best_cost = std::numeric_limits<double>::max();
+    int ci = 0;
     for (int K : {5, 10, 20, 40, 80, 160}) {
-        if (K > trial_steps) break;
-        double sum = t_sort;
-        for (int j = 0; j < K; ++j) sum += tp[j];
-        const double cost = sum / K;
-        if (cost < best_cost) {
-            best_cost = cost;
-            best = K;
+        if (cost_ms) cost_ms[ci] = -1.0;
+        if (K <= trial_steps) {
+            double sum = t_sort;
+            for (int j = 0; j < K; ++j) sum += tp[j];
+            const double cost = sum / K;
+            if (cost_ms) cost_ms[ci] = cost;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = K;
+            }
         }
+        ++ci;
     }
     s->resort_every = best;
     s->steps_since_sort = trial_steps;  // the order has decayed: sort at the next step
@@ -1623,15 +1775,19 @@ fetd_status fetd_info_get(fetd_sim *s, fetd_info *out)
 // ---------------------------------------------------------------------
 struct fetd_batch {
     std::vector<fetd_sim *> sims;
-    hipStream_t stream = nullptr;
+    hipStream_t member_stream = nullptr;  // the members' stream
+    hipStream_t stream = nullptr;         // the batch's own stream (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     int device = 0;
     bool fp32 = false;
+    bool det = false;
     bool use_graph = false;
     int nrun = 0, nseg = 0;
     uint32_t tri_blocks = 0, edge_blocks = 0, tiles = 0;
     FieldDesc *d_fields = nullptr;
     uint32_t *d_tri_prefix = nullptr, *d_edge_prefix = nullptr, *d_seg_prefix = nullptr;
     SegDesc *d_segs[2] = {nullptr, nullptr};  // [parity of sorts since creation]
+    uint32_t *d_queue = nullptr;              // tile queue of the particle launch: [next, done]
     std::vector<int> pbuf0;                   // particle buffer of each run at creation
     std::vector<uint64_t> gen0;               // desc_gen of each run at the last build
     int parity = 0;
@@ -1639,6 +1795,7 @@ struct fetd_batch {
     int resort_every = 20;
     hipGraphExec_t graph = nullptr;
     int graph_pusher = -1;
+    int64_t graph_captures = 0, graph_replays = 0, eager_steps = 0;
     std::string err;
 };
 
@@ -1666,33 +1823,8 @@ bool batch_upload(fetd_batch *b, T **dst, const std::vector<T> &v)
 SegDesc seg_desc(fetd_sim *s, const Species &sp, int pbuf)
 {
     SegDesc d{};
-    d.m.tri_edge = s->d_tri_edge;
-    d.m.tri_nbr = s->d_tri_nbr;
-    d.m.grad64 = s->d_grad64;
-    d.m.grad32 = s->d_grad32;
-    d.m.vxy64 = s->d_vxy64;
-    d.m.vxy32 = s->d_vxy32;
-    d.m.tri_ebase = s->d_tri_ebase;
-    const size_t rb = s->real_bytes();
-    StepArgs &a = d.a;
-    a.n = sp.n;
-    a.key = s->d_key[pbuf] + sp.offset;
-    a.lam = static_cast<char *>(s->d_lam[pbuf]) + 2 * rb * sp.offset;
-    a.u = static_cast<char *>(s->d_u[pbuf]) + 2 * rb * sp.offset;
-    a.pid = s->d_pid[pbuf] + sp.offset;
-    a.rec = s->d_rec;
-    a.cur = s->d_cur;
-    a.qdt = sp.q * sp.w / s->dt;
-    a.alpha = sp.q * s->dt / (2.0 * sp.m);
-    a.dt = s->dt;
-    a.c = s->c;
-    a.inv_c2 = 1.0 / (s->c * s->c);
-    a.cap = s->cap;
-    a.has_affine = s->has_affine ? 1 : 0;
-    for (int k = 0; k < 6; ++k) a.aff[k] = s->affine[k];
-    a.counters = s->d_counters;
-    a.block_counts = s->d_block_counts + 2 * sp.bc_offset;
-    a.tile_home = s->d_tile_home + sp.bc_offset;
+    d.m = mesh_view(s);
+    d.a = step_args(s, sp, pbuf);
     return d;
 }
 
@@ -1701,42 +1833,29 @@ fetd_status batch_build(fetd_batch *b)
     std::vector<FieldDesc> fd;
     std::vector<uint32_t> tp(1, 0), ep(1, 0), sp(1, 0);
     std::vector<SegDesc> seg[2];
-    for (fetd_sim *s : b->sims) {
-        FieldDesc d{};
-        d.nf = s->nf;
-        d.ne = s->ne;
-        d.tri_edge = s->d_tri_edge;
-        d.e = s->d_e;
-        d.e_ext = s->d_e_ext;
-        d.e_scale = s->e_scale;
-        d.b = s->d_b;
-        d.damp_b = s->d_damp_b;
-        d.h = s->d_h;
-        d.inv_mu_area = s->d_inv_mu_area;
-        d.inv_2area = s->d_inv_2area;
-        d.bz_ext = s->d_bz_ext;
-        d.grad64 = s->d_grad64;
-        d.rec = s->d_rec;
-        d.rec_fp32 = s->fp32() ? 1 : 0;
-        d.dt = s->dt;
-        d.edge_face = s->d_edge_face;
-        d.cur = s->d_cur;
-        d.cur_last = s->d_cur_last;
-        d.d = s->d_d;
-        d.damp = s->d_damp;
-        d.sl_ptr = s->d_sl_ptr;
-        d.sl_w = s->d_sl_w;
-        d.sl_col = s->d_sl_col;
-        d.sl_val = s->d_sl_val;
-        d.e_out = s->d_e;
-        fd.push_back(d);
+    // (tiles, run, species) of every non-empty segment, largest first, so
+    // the tile queue hands out the longest runs before the short ones
+    struct SegRef {
+        int64_t tiles;
+        int run, species;
+    };
+    std::vector<SegRef> refs;
+    for (size_t r = 0; r < b->sims.size(); ++r) {
+        fetd_sim *s = b->sims[r];
+        fd.push_back(field_desc(s));
         tp.push_back(tp.back() + uint32_t((s->nf + 255) / 256));
         ep.push_back(ep.back() + uint32_t((s->ne + 255) / 256));
-        for (const Species &x : s->species) {
-            if (x.n == 0) continue;
-            for (int par = 0; par < 2; ++par) seg[par].push_back(seg_desc(s, x, s->pbuf ^ par));
-            sp.push_back(sp.back() + uint32_t(tiles_of(x.n)));
-        }
+        for (size_t k = 0; k < s->species.size(); ++k)
+            if (s->species[k].n > 0)
+                refs.push_back({tiles_of(s->species[k].n), int(r), int(k)});
+    }
+    std::stable_sort(refs.begin(), refs.end(),
+                     [](const SegRef &x, const SegRef &y) { return x.tiles > y.tiles; });
+    for (const SegRef &x : refs) {
+        fetd_sim *s = b->sims[x.run];
+        for (int par = 0; par < 2; ++par)
+            seg[par].push_back(seg_desc(s, s->species[x.species], s->pbuf ^ par));
+        sp.push_back(sp.back() + uint32_t(x.tiles));
     }
     b->nrun = int(b->sims.size());
     b->nseg = int(seg[0].size());
@@ -1750,9 +1869,11 @@ fetd_status batch_build(fetd_batch *b)
         b->gen0.push_back(s->desc_gen);
     }
     b->parity = 0;
+    const std::vector<uint32_t> queue0 = {0u, 0u};
     if (!batch_upload(b, &b->d_fields, fd) || !batch_upload(b, &b->d_tri_prefix, tp) ||
         !batch_upload(b, &b->d_edge_prefix, ep) || !batch_upload(b, &b->d_seg_prefix, sp) ||
-        !batch_upload(b, &b->d_segs[0], seg[0]) || !batch_upload(b, &b->d_segs[1], seg[1]))
+        !batch_upload(b, &b->d_segs[0], seg[0]) || !batch_upload(b, &b->d_segs[1], seg[1]) ||
+        !batch_upload(b, &b->d_queue, queue0))
         return batch_fail(b, FETD_E_OOM, "batch descriptors");
     return FETD_OK;
 }
@@ -1762,11 +1883,13 @@ void batch_release(fetd_batch *b)
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
     for (void *p : {(void *)b->d_fields, (void *)b->d_tri_prefix, (void *)b->d_edge_prefix,
-                    (void *)b->d_seg_prefix, (void *)b->d_segs[0], (void *)b->d_segs[1]})
+                    (void *)b->d_seg_prefix, (void *)b->d_segs[0], (void *)b->d_segs[1],
+                    (void *)b->d_queue})
         if (p) (void)hipFree(p);
     b->d_fields = nullptr;
     b->d_tri_prefix = b->d_edge_prefix = b->d_seg_prefix = nullptr;
     b->d_segs[0] = b->d_segs[1] = nullptr;
+    b->d_queue = nullptr;
 }
 
 // Enqueue n batched steps (re-sorting when due) on the batch stream.
@@ -1775,7 +1898,7 @@ fetd_status batch_enqueue(fetd_batch *b, int n, int pusher)
     for (int it = 0; it < n; ++it) {
         if (b->steps_since_sort >= b->resort_every) {
             for (fetd_sim *s : b->sims)
-                if (fetd_status st = sort_all(s)) return batch_fail(b, st, s->err);
+                if (fetd_status st = sort_all(s, b->stream)) return batch_fail(b, st, s->err);
             b->parity ^= 1;
             b->steps_since_sort = 0;
         }
@@ -1783,7 +1906,7 @@ fetd_status batch_enqueue(fetd_batch *b, int n, int pusher)
                                               b->tri_blocks);
         if (e == hipSuccess)
             e = launch_particles_batched(b->stream, b->d_segs[b->parity], b->d_seg_prefix, b->nseg,
-                                         b->tiles, pusher, b->fp32);
+                                         b->tiles, b->d_queue, pusher, b->fp32, b->det);
         if (e == hipSuccess)
             e = launch_ampere_batched(b->stream, b->d_fields, b->d_edge_prefix, b->nrun,
                                       b->edge_blocks);
@@ -1800,86 +1923,28 @@ fetd_status batch_enqueue(fetd_batch *b, int n, int pusher)
     return FETD_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-fetd_status fetd_batch_create(fetd_sim *const *sims, int32_t n, int32_t use_graph,
-                              fetd_batch **out)
+// Steps of a batch call in graph mode: eager steps up to the next sort; a
+// first full cycle eagerly (every kernel of the cycle is then loaded, which
+// a capture forbids doing); then whole cycles of 2 re-sort intervals
+// starting right before a sort (the particle buffers and the sort parity
+// return to their state), captured once and replayed; the rest eagerly.
+fetd_status batch_graph_steps(fetd_batch *b, int left, int pusher)
 {
-    if (!out || !sims || n <= 0) {
-        g_last_error = "invalid batch arguments";
-        return FETD_E_ARG;
-    }
-    *out = nullptr;
-    fetd_batch *b = new (std::nothrow) fetd_batch();
-    if (!b) return FETD_E_OOM;
-    b->sims.assign(sims, sims + n);
-    b->stream = sims[0]->stream;
-    b->device = sims[0]->device;
-    b->fp32 = sims[0]->fp32();
-    b->use_graph = use_graph != 0;
-    b->resort_every = sims[0]->resort_every;
-    for (fetd_sim *s : b->sims) {
-        if (!s || s->stream != b->stream || s->device != b->device || s->fp32() != b->fp32) {
-            delete b;
-            g_last_error = "batch members must share device, stream and precision";
-            return FETD_E_ARG;
-        }
-    }
-    DeviceGuard g(b->device);
-    for (fetd_sim *s : b->sims)
-        if (!s->have_baseline)
-            if (fetd_status st = take_baseline(s)) {
-                delete b;
-                g_last_error = s->err;
-                return st;
-            }
-    b->steps_since_sort = 0;
-    for (fetd_sim *s : b->sims) b->steps_since_sort = std::max<int>(b->steps_since_sort, int(s->steps_since_sort));
-    if (fetd_status st = batch_build(b)) {
-        batch_release(b);
-        delete b;
-        return st;
-    }
-    *out = b;
-    return FETD_OK;
-}
-
-fetd_status fetd_batch_step(fetd_batch *b, int32_t n_steps, int32_t pusher)
-{
-    if (!b || n_steps < 0 || pusher < 0 || pusher > 3) return FETD_E_ARG;
-    DeviceGuard g(b->device);
-    // the members may have been sorted, reloaded or given new applied
-    // fields or layers individually: rebuild the descriptors
-    bool stale = false;
-    for (size_t r = 0; r < b->sims.size(); ++r)
-        if ((b->sims[r]->pbuf ^ b->parity) != b->pbuf0[r] || b->sims[r]->desc_gen != b->gen0[r])
-            stale = true;
-    if (stale) {
-        batch_release(b);
-        if (fetd_status st = batch_build(b)) return st;
-    }
-    if (!b->use_graph) return batch_enqueue(b, n_steps, pusher);
-    // Graph mode: one captured cycle = 2 re-sort intervals starting right
-    // before a sort (the particle buffers and parity return to their state).
     const int K = b->resort_every;
-    int left = n_steps;
-    // eager steps up to the next sort
     const int lead = std::min(left, std::max(0, K - b->steps_since_sort));
     if (fetd_status st = batch_enqueue(b, lead, pusher)) return st;
+    b->eager_steps += lead;
     left -= lead;
     const int cycle = 2 * K;
     if (left >= cycle && (!b->graph || b->graph_pusher != pusher)) {
-        // one eager cycle first: every kernel of the cycle is then loaded
-        // (a first launch may load code objects, which a capture forbids)
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
         if (fetd_status st = batch_enqueue(b, cycle, pusher)) return st;
+        b->eager_steps += cycle;
         left -= cycle;
     }
     if (left >= cycle) {
-        if (!b->graph || b->graph_pusher != pusher) {
-            if (b->graph) (void)hipGraphExecDestroy(b->graph);
-            b->graph = nullptr;
+        if (!b->graph) {
             // capture with the host counters advanced as during replay
             const int save_parity = b->parity, save_since = b->steps_since_sort;
             std::vector<int64_t> save_step, save_since_sim;
@@ -1910,6 +1975,7 @@ fetd_status fetd_batch_step(fetd_batch *b, int32_t n_steps, int32_t pusher)
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
             b->graph_pusher = pusher;
+            ++b->graph_captures;
         }
         while (left >= cycle) {
             hipError_t e = hipGraphLaunch(b->graph, b->stream);
@@ -1919,18 +1985,135 @@ fetd_status fetd_batch_step(fetd_batch *b, int32_t n_steps, int32_t pusher)
                 s->steps_since_sort = K;
             }
             b->steps_since_sort = K;
+            ++b->graph_replays;
             left -= cycle;
         }
     }
-    return batch_enqueue(b, left, pusher);
+    if (fetd_status st = batch_enqueue(b, left, pusher)) return st;
+    b->eager_steps += left;
+    return FETD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fetd_status fetd_batch_create(fetd_sim *const *sims, int32_t n, int32_t use_graph,
+                              fetd_batch **out)
+{
+    if (!out || !sims || n <= 0) {
+        g_last_error = "invalid batch arguments";
+        return FETD_E_ARG;
+    }
+    *out = nullptr;
+    for (int32_t i = 0; i < n; ++i)
+        if (!sims[i]) {
+            g_last_error = "invalid batch arguments";
+            return FETD_E_ARG;
+        }
+    fetd_batch *b = new (std::nothrow) fetd_batch();
+    if (!b) return FETD_E_OOM;
+    b->sims.assign(sims, sims + n);
+    b->member_stream = sims[0]->stream;
+    b->device = sims[0]->device;
+    b->fp32 = sims[0]->fp32();
+    b->det = sims[0]->deterministic;
+    b->use_graph = use_graph != 0;
+    b->resort_every = sims[0]->resort_every;
+    for (fetd_sim *s : b->sims) {
+        if (s->stream != b->member_stream || s->device != b->device || s->fp32() != b->fp32 ||
+            s->deterministic != b->det) {
+            delete b;
+            g_last_error = "batch members must share device, stream, precision and determinism";
+            return FETD_E_ARG;
+        }
+    }
+    DeviceGuard g(b->device);
+    // The batch works on a stream of its own (a non-blocking one, so a HIP
+    // graph can be captured on it even when the members use the legacy
+    // default stream) and hands over to and from the members' stream with
+    // events at every call.
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        fetd_batch_destroy(b);
+        g_last_error = "batch stream";
+        return FETD_E_HIP;
+    }
+    for (fetd_sim *s : b->sims)
+        if (!s->have_baseline)
+            if (fetd_status st = take_baseline(s)) {
+                g_last_error = s->err;
+                fetd_batch_destroy(b);
+                return st;
+            }
+    if (hipStreamSynchronize(b->member_stream) != hipSuccess) {
+        fetd_batch_destroy(b);
+        g_last_error = "member stream";
+        return FETD_E_HIP;
+    }
+    b->steps_since_sort = 0;
+    for (fetd_sim *s : b->sims) b->steps_since_sort = std::max<int>(b->steps_since_sort, int(s->steps_since_sort));
+    if (fetd_status st = batch_build(b)) {
+        fetd_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return FETD_OK;
+}
+
+fetd_status fetd_batch_step(fetd_batch *b, int32_t n_steps, int32_t pusher)
+{
+    if (!b || n_steps < 0 || pusher < 0 || pusher > 3) return FETD_E_ARG;
+    DeviceGuard g(b->device);
+    // the members may have been sorted, reloaded or given new applied
+    // fields or layers individually: rebuild the descriptors
+    bool stale = false;
+    for (size_t r = 0; r < b->sims.size(); ++r)
+        if ((b->sims[r]->pbuf ^ b->parity) != b->pbuf0[r] || b->sims[r]->desc_gen != b->gen0[r])
+            stale = true;
+    if (stale) {
+        if (hipError_t e = hipStreamSynchronize(b->stream))
+            return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
+        batch_release(b);
+        if (fetd_status st = batch_build(b)) return st;
+    }
+    // members' work first, the batch's after it, the members' next work after that
+    hipError_t e = hipEventRecord(b->ev_in, b->member_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
+    if (e != hipSuccess) return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
+    fetd_status st;
+    if (b->use_graph) {
+        st = batch_graph_steps(b, n_steps, pusher);
+    } else {
+        st = batch_enqueue(b, n_steps, pusher);
+        if (!st) b->eager_steps += n_steps;
+    }
+    e = hipEventRecord(b->ev_out, b->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->member_stream, b->ev_out, 0);
+    if (!st && e != hipSuccess) return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
+    return st;
+}
+
+fetd_status fetd_batch_stats(fetd_batch *b, int64_t *graph_captures, int64_t *graph_replays,
+                             int64_t *eager_steps)
+{
+    if (!b) return FETD_E_ARG;
+    if (graph_captures) *graph_captures = b->graph_captures;
+    if (graph_replays) *graph_replays = b->graph_replays;
+    if (eager_steps) *eager_steps = b->eager_steps;
+    return FETD_OK;
 }
 
 void fetd_batch_destroy(fetd_batch *b)
 {
     if (!b) return;
     DeviceGuard g(b->device);
-    (void)hipStreamSynchronize(b->stream);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
     batch_release(b);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
 

@@ -47,13 +47,17 @@ struct StepArgs {
     uint32_t *key;
     void *lam;        // double2 or float2 [n]: barycentric pair
     void *u;          // double2 or float2 [n]: momentum u = gamma v
-    const void *rec;  // per-triangle field record, 8 reals: V0, V1, V2 (E = sum l_n V_n), Bz, pad
+    const void *rec;  // per-triangle field record, 32 B: FP32 V0, V1, V2 (E = sum l_n V_n), Bz,
+                      // pad; FP64 the signed edge DoFs s_k e_k and Bz
     double *cur;      // FP64 current accumulator [ne]
+    unsigned long long *fx;  // deterministic mode: fixed-point current limbs [3 ne], else null
+    double fx_scale;  // 2^(96 - E) with every contribution below 2^E in magnitude
     double qdt;       // Q / dt of the species
     double alpha;     // q dt / (2 m)
     double dt;
     double c;
-    double inv_c2;
+    double c2;        // c * c
+    double inv_c2;    // 1 / (c * c)
     int cap;          // crossing cap
     int has_affine;
     double aff[6];
@@ -69,48 +73,76 @@ struct SegDesc {
     StepArgs a;
 };
 
-// Per-run field-stage descriptor of a batched launch.
+// Field stages of one run (passed by value to the single-run kernels, as
+// an array to the batched ones).  e, b, h, the values of M~ and e_out are
+// FP64, or FP32 when field32 is set; d and the currents are FP64.
 struct FieldDesc {
     int nf, ne;
+    int rec_fp32;     // field record for FP32 particles (else the FP64 record)
+    int field32;
     const int4 *tri_edge;
-    const double *e;
+    const void *e;
     const double *e_ext;
     double e_scale;   // multiplier of e_ext
-    double *b;
+    void *b;
     const double *damp_b;  // magnetic loss per triangle (absorbing layer) or null
-    double *h;
-    const double *inv_mu_area;
-    const double *inv_2area;
+    void *h;               // b / (mu0 A)
+    const double *mu_area;   // mu0 A_f
+    const double *two_area;  // 2 A_f
     const double *bz_ext;
     const double *grad64;
     void *rec;
-    int rec_fp32;
     double dt;
     const int4 *edge_face;
     double *cur;
     double *cur_last;
     double *d;
     const double *damp;
+    unsigned long long *fx;  // deterministic mode: fixed-point current limbs, else null
+    double fx_unscale;       // 2^(E - 96)
     const int32_t *sl_ptr;
     const int32_t *sl_w;
     const int32_t *sl_col;
-    const double *sl_val;
-    double *e_out;
+    const void *sl_val;
+    void *e_out;
 };
 
 // Host-callable launchers (fetd_kernels.hip).
-hipError_t launch_faraday(hipStream_t s, int nf, const int4 *tri_edge, const double *e,
-                          const double *e_ext, double e_scale, double *b, const double *damp_b,
-                          double *h,
-                          const double *inv_mu_area, const double *inv_2area,
-                          const double *bz_ext, const double *grad64, void *rec, bool rec_fp32,
-                          double dt);
-hipError_t launch_particles(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
-                            bool fp32);
-hipError_t launch_ampere(hipStream_t s, int ne, const int4 *edge_face, const double *h,
-                         double *cur, double *cur_last, double *d, const double *damp, double dt);
-hipError_t launch_spmv(hipStream_t s, int ne, const int32_t *slice_ptr, const int32_t *slice_w,
-                       const int32_t *col, const double *val, const double *d, double *e);
+hipError_t launch_faraday(hipStream_t s, const FieldDesc &d);
+hipError_t launch_ampere(hipStream_t s, const FieldDesc &d);
+hipError_t launch_spmv(hipStream_t s, const FieldDesc &d);
+
+// Particle stage (fetd_particles.hip, one object per precision).  A
+// deterministic launch is selected by a.fx != null (batched: det).
+hipError_t launch_particles_f32(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher);
+hipError_t launch_particles_f64(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher);
+// Batched: queue = [next tile, blocks done], zero before the first launch;
+// the kernel's last block leaves it at zero again.
+hipError_t launch_particles_batched_f32(hipStream_t s, const SegDesc *segs, const uint32_t *prefix,
+                                        int nseg, uint32_t total_tiles, uint32_t *queue,
+                                        int pusher, bool det);
+hipError_t launch_particles_batched_f64(hipStream_t s, const SegDesc *segs, const uint32_t *prefix,
+                                        int nseg, uint32_t total_tiles, uint32_t *queue,
+                                        int pusher, bool det);
+inline hipError_t launch_particles(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
+                                   bool fp32)
+{
+    return fp32 ? launch_particles_f32(s, m, a, pusher) : launch_particles_f64(s, m, a, pusher);
+}
+inline hipError_t launch_particles_batched(hipStream_t s, const SegDesc *segs,
+                                           const uint32_t *prefix, int nseg, uint32_t total_tiles,
+                                           uint32_t *queue, int pusher, bool fp32, bool det)
+{
+    return fp32 ? launch_particles_batched_f32(s, segs, prefix, nseg, total_tiles, queue, pusher,
+                                               det)
+                : launch_particles_batched_f64(s, segs, prefix, nseg, total_tiles, queue, pusher,
+                                               det);
+}
+
+// Largest species and mesh the 32-bit byte offsets of the particle kernel
+// address (16-byte FP64 particle records, 48-byte triangle tables).
+constexpr int64_t kMaxSpeciesParticles = (int64_t(1) << 28) - 1024;
+constexpr int64_t kMaxTris = int64_t(1) << 26;
 
 // Counting sort of one species segment by triangle (drops lost particles).
 // counts/offsets need nf+1 ints, block_sums a few thousand.
@@ -136,8 +168,6 @@ hipError_t launch_sort(hipStream_t s, const SortArgs &a);
 // Batched launches over many runs (one launch per phase).
 hipError_t launch_faraday_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,
                                   int nrun, uint32_t total_blocks);
-hipError_t launch_particles_batched(hipStream_t s, const SegDesc *segs, const uint32_t *prefix,
-                                    int nseg, uint32_t total_tiles, int pusher, bool fp32);
 hipError_t launch_ampere_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,
                                  int nrun, uint32_t total_blocks);
 hipError_t launch_spmv_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,
@@ -146,8 +176,8 @@ hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n);
 // Field probes: accumulate E at n points; when out is non-null write the
 // window average there (times inv_window) and restart the sum.
 hipError_t launch_probe(hipStream_t s, int n, const int32_t *tri, const double *lam,
-                        const int4 *tri_edge, const double *grad64, const double *e, double *acc,
-                        double *out, double inv_window);
+                        const int4 *tri_edge, const double *grad64, const void *e, bool field32,
+                        double *acc, double *out, double inv_window);
 
 // Diagnostics.
 hipError_t launch_charge(hipStream_t s, int64_t n, const uint32_t *key, const void *lam,

@@ -19,7 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libfetdpic.so")
 FETD_OK, FETD_E_ARG, FETD_E_MESH, FETD_E_OOM, FETD_E_HIP, FETD_E_TRACK, FETD_E_STATE = \
     0, -1, -2, -3, -4, -5, -6
 PUSHERS = {"boris": 0, "boris_tan": 1, "vay": 2, "hc": 3}
-PRECISIONS = {"fp64": 0, "mixed": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_f64field": 2}
+MAX_SPECIES_PARTICLES = (1 << 28) - 1024
+MAX_TRIS = 1 << 26
 FIELDS = {"e": 0, "d": 1, "b": 2, "j": 3, "q": 4, "spai_ptr": 5, "spai_col": 6, "spai_val": 7,
           "edges": 8, "tri_edge": 9, "divd": 10}
 
@@ -45,7 +47,7 @@ class Opts(ctypes.Structure):
                 ("spai_level", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_user", ctypes.c_void_p), ("crossing_cap", ctypes.c_int32),
-                ("resort_every", ctypes.c_int32)]
+                ("resort_every", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -84,7 +86,7 @@ def lib():
         L.fetd_particles_load_bary.argtypes = [P, ctypes.c_double, ctypes.c_double,
                                                ctypes.c_double, ctypes.c_int64, P, P, P, P, P]
         L.fetd_particles_load.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                          ctypes.c_int64, P, P, P]
+                                          ctypes.c_int64, P, P, P, P]
         L.fetd_pic_step.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
         L.fetd_sort.argtypes = [P]
         L.fetd_sync.argtypes = [P]
@@ -96,10 +98,11 @@ def lib():
         L.fetd_last_error.restype = ctypes.c_char_p
         optional = {"fetd_profile": [P, ctypes.c_int32], "fetd_stage_times": [P, P, P],
                     "fetd_profile_mask": [P, ctypes.c_int32, ctypes.c_int32],
-                    "fetd_autotune": [P, ctypes.c_int32, ctypes.c_int32, P],
+                    "fetd_autotune": [P, ctypes.c_int32, ctypes.c_int32, P, P],
                     "fetd_set_resort": [P, ctypes.c_int32],
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32],
+                    "fetd_batch_stats": [P, P, P, P],
                     "fetd_set_absorber": [P, P],
                     "fetd_set_ext_scale": [P, ctypes.c_double],
                     "fetd_probe_set": [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int64],
@@ -164,7 +167,7 @@ class _TorchMemory:
 # ---------------------------------------------------------------------------
 
 def mesh_create(mesh, dt, eps0, mu0, c, precision="fp64", spai_level=1, device=0,
-                crossing_cap=64, resort_every=20, use_torch=True):
+                crossing_cap=64, resort_every=20, deterministic=False, use_torch=True):
     """fetd_mesh_create.  ``mesh`` has node_xy, tri_nodes, tri_shift, period."""
     node_xy = np.ascontiguousarray(mesh.node_xy, dtype=np.float64)
     tri = np.ascontiguousarray(mesh.tri_nodes, dtype=np.int32)
@@ -184,7 +187,7 @@ def mesh_create(mesh, dt, eps0, mu0, c, precision="fp64", spai_level=1, device=0
     opts = Opts(PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                 float(dt), float(eps0), float(mu0), float(c), int(spai_level), int(device),
                 stream, mem._alloc if mem else ALLOC_FN(), mem._free if mem else FREE_FN(), None,
-                int(crossing_cap), int(resort_every))
+                int(crossing_cap), int(resort_every), 1 if deterministic else 0)
     h = ctypes.c_void_p()
     _check(lib().fetd_mesh_create(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h)))
     return h, mem
@@ -236,11 +239,13 @@ def particles_load_bary(h, q, m, w, tri, lam, u, slot=None):
     return out.value
 
 
-def particles_load(h, q, m, w, xy, u):
+def particles_load(h, q, m, w, xy, u, tri_hint=None):
     xy = np.ascontiguousarray(xy, dtype=np.float64)
     u = np.ascontiguousarray(u, dtype=np.float64)
+    th = None if tri_hint is None else np.ascontiguousarray(tri_hint, dtype=np.int32)
     out = ctypes.c_int32()
-    _check(lib().fetd_particles_load(h, q, m, w, xy.shape[0], _p(xy), _p(u), ctypes.byref(out)), h)
+    _check(lib().fetd_particles_load(h, q, m, w, xy.shape[0], _p(xy), _p(u), _p(th),
+                                     ctypes.byref(out)), h)
     return out.value
 
 
@@ -299,11 +304,19 @@ def info(h):
 STAGES = ("faraday", "particles", "ampere", "spmv", "sort")
 
 
-def autotune(h, pusher="boris", trial_steps=160):
+AUTOTUNE_CANDIDATES = (5, 10, 20, 40, 80, 160)
+
+
+def autotune(h, pusher="boris", trial_steps=160, with_costs=False):
+    """fetd_autotune: the chosen re-sort interval (and, with_costs, the
+    measured cost per step in ms of every candidate tried)."""
     pid = PUSHERS[pusher] if isinstance(pusher, str) else int(pusher)
     out = ctypes.c_int32()
-    _check(lib().fetd_autotune(h, pid, int(trial_steps), ctypes.byref(out)), h)
-    return out.value
+    costs = np.zeros(len(AUTOTUNE_CANDIDATES))
+    _check(lib().fetd_autotune(h, pid, int(trial_steps), ctypes.byref(out), _p(costs)), h)
+    if not with_costs:
+        return out.value
+    return out.value, {k: float(c) for k, c in zip(AUTOTUNE_CANDIDATES, costs) if c >= 0}
 
 
 def set_resort(h, every):
@@ -376,8 +389,8 @@ class Sim:
     def load(self, q, m, w, tri, lam, u, slot=None):
         return particles_load_bary(self.h, q, m, w, tri, lam, u, slot)
 
-    def load_xy(self, q, m, w, xy, u):
-        return particles_load(self.h, q, m, w, xy, u)
+    def load_xy(self, q, m, w, xy, u, tri_hint=None):
+        return particles_load(self.h, q, m, w, xy, u, tri_hint)
 
     def step(self, n=1, pusher="boris"):
         pic_step(self.h, n, pusher)
@@ -403,8 +416,8 @@ class Sim:
     def profile(self, enable=True, stages=None, every=1):
         profile(self.h, enable, stages, every)
 
-    def autotune(self, pusher="boris", trial_steps=160):
-        return autotune(self.h, pusher, trial_steps)
+    def autotune(self, pusher="boris", trial_steps=160, with_costs=False):
+        return autotune(self.h, pusher, trial_steps, with_costs)
 
     def set_resort(self, every):
         set_resort(self.h, every)
@@ -427,6 +440,13 @@ def batch_step(b, n_steps, pusher="boris"):
     _check(lib().fetd_batch_step(b, int(n_steps), pid))
 
 
+def batch_stats(b):
+    """(graph captures, graph replays, eager steps) of a batch."""
+    c, r, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fetd_batch_stats(b, ctypes.byref(c), ctypes.byref(r), ctypes.byref(e)))
+    return {"graph_captures": c.value, "graph_replays": r.value, "eager_steps": e.value}
+
+
 def batch_destroy(b):
     lib().fetd_batch_destroy(b)
 
@@ -440,6 +460,9 @@ class Batch:
 
     def step(self, n=1, pusher="boris"):
         batch_step(self.h, n, pusher)
+
+    def stats(self):
+        return batch_stats(self.h)
 
     def close(self):
         if self.h:

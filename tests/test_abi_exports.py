@@ -49,6 +49,23 @@ def test_argument_errors_without_device():
     L.fetd_destroy(None)
 
 
+def test_mesh_size_limit_without_device():
+    """A mesh beyond FETD_MAX_TRIS (the particle kernel's 32-bit table
+    offsets) is refused before any array is read or a device is queried."""
+    import numpy as np
+    from paper_1707_04333_amd import fetdpic
+    L = fetdpic.lib()
+    xy = np.zeros(6)
+    tri = np.zeros(3, np.int32)
+    desc = fetdpic.MeshDesc(3, fetdpic._p(xy), fetdpic.MAX_TRIS + 1, fetdpic._p(tri), None, None)
+    opts = fetdpic.Opts(0, 1e-12, 8.8e-12, 1.26e-6, 3e8, 1, 0, None, fetdpic.ALLOC_FN(),
+                        fetdpic.FREE_FN(), None, 64, 20, 0)
+    out = ctypes.c_void_p()
+    st = L.fetd_mesh_create(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(out))
+    assert st == fetdpic.FETD_E_ARG and not out.value
+    assert b"FETD_MAX_TRIS" in L.fetd_last_error(None)
+
+
 def test_tet_argument_errors_without_device():
     from paper_1707_04333_amd import fetd3
     L = fetd3.lib()

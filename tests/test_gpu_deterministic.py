@@ -1,0 +1,149 @@
+"""The deterministic option (fetd_opts.deterministic): every current
+contribution goes into a fixed-point accumulator per edge with integer
+atomics, so the step's result does not depend on the order of the adds.
+Checked bit for bit through the C-ABI:
+
+* the same run with re-sorts every 3 steps and every 50 steps (different
+  particle orders in memory, different tiles);
+* batched (graph replay, tile queue) against the same runs stepped one by
+  one;
+* a run saved after 12 steps (fields_get b, d; particles_get) and resumed
+  in a new simulation (fields_load, particles_load_bary) against the run
+  that went on;
+* the autotuner's trial steps against plain steps;
+and against the FP64 oracle within 1e-12 (the accumulator's sum differs
+from the oracle's sequential sum by rounding only)."""
+import numpy as np
+import pytest
+
+from paper_1707_04333_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _fp():
+    from paper_1707_04333_amd import fetdpic
+    return fetdpic
+
+
+def _wl(n_side=20, length=0.03, n_pairs=9_001, theta=0.3, precision="fp64"):
+    return I.pair_plasma(n_side=n_side, length=length, n_pairs=n_pairs, theta=theta, steps=40,
+                         precision=precision)
+
+
+def _state(g, n_species=2):
+    out = {name: g.field(name) for name in ("e", "d", "b", "j")}
+    for si in range(n_species):
+        p = g.particles(si)
+        for k in ("id", "tri", "slot", "lam", "u"):
+            out[f"{k}{si}"] = p[k]
+    return out
+
+
+def _assert_bitwise(a, b):
+    assert a.keys() == b.keys()
+    for k in a:
+        assert a[k].shape == b[k].shape, k
+        assert np.array_equal(a[k], b[k]), (k, float(np.abs(a[k] - b[k]).max()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_deterministic_independent_of_sort_order(precision):
+    fp = _fp()
+    w = _wl(precision=precision)
+    a = fp.from_workload(w, spai_level=1, deterministic=True, resort_every=3)
+    b = fp.from_workload(w, spai_level=1, deterministic=True, resort_every=50)
+    a.step(25, "hc")
+    b.step(25, "hc")
+    _assert_bitwise(_state(a), _state(b))
+    assert a.diagnostics()["gauss_rel"] <= (1e-12 if precision == "fp64" else 1e-6)
+    a.close()
+    b.close()
+
+
+def test_deterministic_matches_oracle(oracle_lib):
+    w = _wl()
+    sp = [(s.q, s.m, s.w, s.tri, s.lam, s.u) for s in w.species]
+    osim = oracle_lib.OracleSim(w.mesh, w.dt, sp, I.EPS0, I.MU0, I.C_LIGHT, spai_level=1,
+                                bz_ext=w.bz_ext)
+    g = _fp().from_workload(w, spai_level=1, deterministic=True, resort_every=7)
+    osim.step(30, "vay")
+    g.step(30, "vay")
+    for si, s in enumerate(osim.species):
+        gp = g.particles(si)
+        alive = np.nonzero(s.tri >= 0)[0]
+        assert np.array_equal(gp["id"], alive)
+        assert np.array_equal(gp["tri"], s.tri[alive]) and np.array_equal(gp["slot"], s.slot[alive])
+        assert np.abs(gp["lam"] - s.lam[alive]).max() <= 1e-12
+        assert np.abs(gp["u"] - s.u[alive]).max() <= 1e-12 * np.abs(s.u).max()
+    for name, ref in (("e", osim.e), ("d", osim.d), ("b", osim.b), ("j", osim.last_cur)):
+        got = g.field(name)
+        assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), name
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_deterministic_batched_equals_separate(precision):
+    fp = _fp()
+    specs = [(12, 0.02, 3001, 0.3), (20, 0.03, 9000, 0.1), (9, 0.015, 1500, 1.0)]
+    wls = [_wl(n, L, p, t, precision) for n, L, p, t in specs]
+    batched = [fp.from_workload(w, spai_level=1, deterministic=True, resort_every=4)
+               for w in wls]
+    single = [fp.from_workload(w, spai_level=1, deterministic=True, resort_every=4)
+              for w in wls]
+    b = fp.Batch(batched, use_graph=True)
+    b.step(33, "boris")
+    for s in single:
+        s.step(33, "boris")
+    st = b.stats()
+    assert st["graph_captures"] == 1 and st["graph_replays"] >= 2, st
+    for gb, gs in zip(batched, single):
+        _assert_bitwise(_state(gb), _state(gs))
+    b.close()
+    for s in batched + single:
+        s.close()
+
+
+def test_deterministic_save_and_resume():
+    fp = _fp()
+    w = _wl()
+    ref = fp.from_workload(w, spai_level=1, deterministic=True, resort_every=5)
+    ref.step(12, "hc")
+    b, d = ref.field("b"), ref.field("d")
+    parts = [ref.particles(si) for si in range(2)]
+    ref.step(13, "hc")
+    sim = fp.Sim(w.mesh, w.dt, I.EPS0, I.MU0, I.C_LIGHT, precision="fp64", spai_level=1,
+                 deterministic=True, resort_every=5)
+    sim.fields_set(bz_ext=np.full(w.mesh.n_tris, float(w.bz_ext)))
+    sim.fields_load(b=b, d=d)
+    for s, p in zip(w.species, parts):
+        sim.load(s.q, s.m, s.w, p["tri"], p["lam"], p["u"], slot=p["slot"])
+    sim.step(13, "hc")
+    a, r = _state(sim), _state(ref)
+    # the resumed run numbers its particles by their rank among the saved ones
+    for si in range(2):
+        a[f"id{si}"] = parts[si]["id"][a[f"id{si}"]]
+    _assert_bitwise(a, r)
+    ref.close()
+    sim.close()
+
+
+def test_autotune_returns_argmin_and_keeps_the_run():
+    """fetd_autotune picks the candidate interval of least measured cost
+    per step, and its trial steps are ordinary steps of the run."""
+    fp = _fp()
+    w = _wl(n_side=24, length=0.038, n_pairs=40_000)
+    tuned = fp.from_workload(w, spai_level=1, deterministic=True)
+    plain = fp.from_workload(w, spai_level=1, deterministic=True)
+    k, costs = tuned.autotune("boris", trial_steps=40, with_costs=True)
+    cands = [c for c in (5, 10, 20, 40, 80, 160) if c <= 40]
+    assert set(costs) == set(cands)
+    assert all(v > 0 for v in costs.values())
+    assert k == min(cands, key=lambda c: costs[c])
+    plain.step(40, "boris")
+    _assert_bitwise(_state(tuned), _state(plain))
+    tuned.step(7, "boris")
+    plain.step(7, "boris")
+    _assert_bitwise(_state(tuned), _state(plain))
+    tuned.close()
+    plain.close()

@@ -166,21 +166,23 @@ def _percentile_errors(osim, g):
     return mis, total, np.percentile(el, [50, 99, 100]), np.percentile(eu, [50, 99, 100])
 
 
-def test_mixed_precision_gauss_and_error(oracle_lib):
-    """Mixed mode against the FP64 oracle.  Without self-fields every
-    particle agrees to FP32 accuracy; in a self-consistent noisy plasma the
-    FP32 perturbations are amplified by the chaotic particle dynamics, so
-    the bound is on the bulk (99th percentile) and on conserved or
-    statistical quantities (Gauss's law to FP64 rounding, kinetic energy)."""
+@pytest.mark.parametrize("precision", ["mixed", "mixed_f64field"])
+def test_mixed_precision_gauss_and_error(oracle_lib, precision):
+    """Both mixed modes (FP32 or FP64 e, b and M~) against the FP64 oracle.
+    Without self-fields every particle agrees to FP32 accuracy; in a
+    self-consistent noisy plasma the FP32 perturbations are amplified by
+    the chaotic particle dynamics, so the bound is on the bulk (99th
+    percentile) and on conserved or statistical quantities (Gauss's law to
+    FP64 rounding, kinetic energy)."""
     w = I.pair_plasma(n_side=24, length=0.038, n_pairs=20_000, theta=0.3, steps=100,
-                      precision="mixed")
+                      precision=precision)
     weak = I.pair_plasma(n_side=24, length=0.038, n_pairs=20_000, theta=0.3, steps=100,
-                         precision="mixed")
+                         precision=precision)
     for s in weak.species:
         s.w = 1e-6  # negligible self-field
     for wl, tol in ((weak, None), (w, 1e-4)):
         osim = _oracle_sim(oracle_lib, wl, 1)
-        g = _gpu_sim(wl, 1, precision="mixed")
+        g = _gpu_sim(wl, 1, precision=precision)
         g.diagnostics()
         osim.step(50, "boris")
         g.step(50, "boris")
@@ -237,7 +239,9 @@ def test_error_paths_reported():
 
 def test_locate_matches_input_generator():
     """Cartesian load (library point location) gives the same triangles as
-    the input generator's locator and barycentrics to rounding."""
+    the input generator's locator and barycentrics to rounding; with
+    triangle hints (right ones, wrong ones, out of range) the same points
+    land in the same triangles."""
     w = I.boosted_oscillator(n_particles=2000)
     sp = w.species[0]
     xy = I.bary_to_xy(w.mesh, sp.tri, sp.lam)
@@ -248,6 +252,36 @@ def test_locate_matches_input_generator():
     got = g.particles(s)
     assert np.array_equal(got["tri"], t_ref)
     assert np.abs(got["lam"] - l_ref).max() < 1e-12
+    hint = t_ref.copy()
+    hint[::3] = (hint[::3] + 17) % w.mesh.n_tris   # wrong: searched instead
+    hint[1::7] = -5                                   # out of range: ignored
+    s2 = g.load_xy(sp.q, sp.m, sp.w, xy, sp.u, tri_hint=hint)
+    got2 = g.particles(s2)
+    assert np.array_equal(got2["tri"], t_ref)
+    assert np.abs(got2["lam"] - l_ref).max() < 1e-12
+    g.close()
+
+
+def test_size_limits_rejected_before_device_work():
+    """A species beyond FETD_MAX_SPECIES_PARTICLES is refused before any
+    array is read or device memory touched; the simulation stays usable."""
+    import ctypes
+    fp = _fp()
+    w = I.cyclotron()
+    g = _gpu_sim(w, 1)
+    one_i = np.zeros(1, np.int32)
+    one_d = np.zeros(2)
+    out = ctypes.c_int32()
+    n = fp.MAX_SPECIES_PARTICLES + 1
+    st = fp.lib().fetd_particles_load_bary(g.h, -I.E_CHARGE, I.M_E, 1.0, n, fp._p(one_i), None,
+                                           fp._p(one_d), fp._p(one_d), ctypes.byref(out))
+    assert st == fp.FETD_E_ARG
+    st = fp.lib().fetd_particles_load(g.h, -I.E_CHARGE, I.M_E, 1.0, n, fp._p(one_d),
+                                      fp._p(one_d), None, ctypes.byref(out))
+    assert st == fp.FETD_E_ARG
+    assert g.info()["n_species"] == 1
+    g.step(2, "boris")
+    assert g.diagnostics()["error_code"] == 0
     g.close()
 
 
@@ -262,12 +296,18 @@ def test_batched_runs_match_separate_runs(oracle_lib, use_graph):
     specs = [(12, 0.02, 3001, 0.3), (20, 0.03, 9000, 0.1), (9, 0.015, 1500, 1.0)]
     wls = [I.pair_plasma(n_side=n, length=L, n_pairs=p, theta=t, steps=40, precision="fp64")
            for n, L, p, t in specs]
-    batched = [_gpu_sim(w, 1, resort_every=6) for w in wls]
-    single = [_gpu_sim(w, 1, resort_every=6) for w in wls]
+    batched = [_gpu_sim(w, 1, resort_every=3) for w in wls]
+    single = [_gpu_sim(w, 1, resort_every=3) for w in wls]
     b = fp.Batch(batched, use_graph=use_graph)
     b.step(15, "vay")
     for s in single:
         s.step(15, "vay")
+    st = b.stats()
+    if use_graph:
+        # lead 3, an eager cycle of 6, then the captured cycle replayed once
+        assert st["graph_captures"] == 1 and st["graph_replays"] == 1, st
+    else:
+        assert st["graph_captures"] == 0 and st["eager_steps"] == 15, st
     cx = wls[0].mesh.centroids()[:, 0]
     sigma = np.where(cx < 0.2 * specs[0][1], 0.3 * I.EPS0 / wls[0].dt, 0.0)
     batched[0].set_absorber(sigma)
@@ -275,6 +315,10 @@ def test_batched_runs_match_separate_runs(oracle_lib, use_graph):
     b.step(14, "vay")
     for s in single:
         s.step(14, "vay")
+    if use_graph:
+        # the new layer rebuilt the descriptors: a new capture and replays
+        st = b.stats()
+        assert st["graph_captures"] == 2 and st["graph_replays"] >= 2, st
     for gb, gs in zip(batched, single):
         for si in range(2):
             pb, ps = gb.particles(si), gs.particles(si)
