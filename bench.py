@@ -1,31 +1,40 @@
 """Benchmark: particle-steps/s of the full PIC step on one MI355X.
 
-Default workload (the ``value`` line): relativistic pair-plasma Bernstein
-configuration — doubly periodic 0.5 m x 0.5 m mesh of 199,712 triangles
-(316 x 316 torus), 8M electrons + 8M positrons in collocated pairs,
-in-plane Maxwell-Juttner momenta (kT/mc^2 = theta), uniform B0 = 1 T with
-omega_c/omega_p = 2, dt = 0.2/omega_c, mixed precision (FP32 positions,
-momenta, gather/push/track; FP64 deposit, field update and Gauss
-accounting), re-sort interval chosen by the autotuner during warm-up.
+Default workload (the ``value`` line): the large single run — a graded
+jittered Delaunay mesh of the unit square (708 x 708 nodes, element size
+ratio 10, 1,000,000 triangles) with PEC walls and a matched absorbing outer
+layer, 128M electrons (95% in-plane Maxwell-Juttner at kT/mc^2 = 0.5, 5% a
+gamma = 20 beam), uniform B0 = 1 T with omega_c/omega_p = 2, Higuera-Cary
+pusher, particles re-sorted by triangle every 20 steps.  ``value`` is the
+FP64 path (every stage in FP64, the paper's precision); the two mixed forms
+(FP32 particle state with FP32 or FP64 fields; FP64 current accumulation
+and Gauss accounting) are reported beside it on the same workload.
 
-A step is one pass of the whole path: Faraday + gather record, the fused
-gather/push/track/deposit stage for both species, Ampere, the SPAI SpMV,
-and the counting sort when due.  Beside it: the same workload in FP64, the
-batched sweep (64 independent uneven runs, one launch per phase per step,
-graph replay) against the same runs stepped one by one, the Gauss residual
-of each, the fused particle kernel on the HBM roofline from HIP events
-that its launches on every 7th step of the timed region carry in their own
-dispatches, and the FP64 CPU oracle on a bounded sample of the same
-workload.
+A step is one pass of the whole path: Faraday + field record, the fused
+gather/push/track/deposit stage, Ampere, the SPAI SpMV, and the counting
+sort when due.  The timed window starts at a step that sorts, so it holds
+ceil(steps/K) sorts (K = the re-sort interval): the sort's cost is inside
+``value``.  Inputs are resident in HBM before the timed region.
+
+Beside it: the pair-plasma Bernstein run (199,712 triangles, 16M
+particles) in FP64 and mixed, the batched sweep (64 independent uneven
+runs, one launch per phase per step, graph replay over whole re-sort
+cycles) against the same runs stepped one by one, the fused particle kernel
+on the HBM roofline from HIP events that its launches on every 7th step of
+the timed region carry in their own dispatches, a plain device-to-device
+copy as the measured bandwidth ceiling, and the FP64 CPU oracle on a
+bounded sample of the headline workload on all host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload pair|large|boosted|cyclotron|bernstein|synchro|tet]
+                       [--workload large|pair|boosted|cyclotron|bernstein|synchro|tet]
                        [--timing-overhead]
 """
 import argparse
 import hashlib
 import json
+import math
 import os
+import platform
 import sys
 import time
 
@@ -37,14 +46,16 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/sec + achieved HBM GB/s; mixed/batched vs FP64 at Gauss residual"
 HBM_PEAK_GBS = 8000.0
 DEFAULT_PAIRS = 8_000_000
-KERNEL_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particle_step_pair_plasma_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd_particles.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particle_step_large_graded_traffic.json")
+PAIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particle_step_pair_plasma_traffic.json")
 KERNEL3_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd3_kernels.hip")
 TRAFFIC3_FILE = os.path.join(ROOT, "profiles", "k3_particles_tet_pair_plasma_traffic.json")
 # Inside the timed region the particle launches of every TIMING_EVERY-th step
 # carry HIP events; 7 is coprime with every re-sort interval used (5 * 2^k),
 # so the sampled steps fall on every phase of the sort cycle.
 TIMING_EVERY = 7
+LARGE_RESORT = 20
 
 
 def log(msg):
@@ -54,12 +65,12 @@ def log(msg):
 def particle_launch_bytes(n_particles, nf, ne, fp32):
     """Algorithmic bytes of one fused particle-stage launch: every particle
     reads and writes its state (key 4 B, barycentric pair and momentum
-    2 x 2 reals), every triangle's record (8 reals), gradients (6 reals,
+    2 x 2 reals), every triangle's field record (32 B), gradients (6 reals,
     padded to 8 in FP32), edge and neighbour tables (16 B each) are read
     once, and every edge's FP64 current is read and written once."""
     r = 4 if fp32 else 8
     per_particle = 2 * (4 + 4 * r)
-    per_tri = 8 * r + (8 if fp32 else 6) * r + 16 + 16
+    per_tri = 32 + (8 if fp32 else 6) * r + 16 + 16
     return n_particles * per_particle + nf * per_tri + ne * 16
 
 
@@ -80,22 +91,80 @@ def measured_traffic(precision, traffic_file=TRAFFIC_FILE, src=KERNEL_SRC):
     return rec.get(precision, {}).get("hbm_bytes_per_launch")
 
 
-def run_gpu(w, precision, steps, warmup, pusher, autotune=True):
+def host_info():
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "affinity_cpus": affinity,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
+def oracle_threads():
+    """Threads of the oracle's timing mode: OMP_NUM_THREADS if set, else the
+    CPUs this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return host_info()["affinity_cpus"] or 1
+
+
+def copy_ceiling_gbs(nbytes=1 << 30, reps=5):
+    """Measured device-to-device copy bandwidth (read + write bytes per
+    second) of a plain 1 GiB copy: the achievable HBM ceiling."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / best / 1e9
+
+
+def run_gpu(w, precision, steps, warmup, pusher, resort=None):
+    """One workload in one precision.  resort = None autotunes the re-sort
+    interval; an integer fixes it.  The timed window starts at a sorting
+    step and covers `steps` steps (inputs already on the device)."""
     from paper_1707_04333_amd import fetdpic as fp
     log(f"{precision}: creating simulation ({w.n_particles} particles)")
-    sim = fp.from_workload(w, precision=precision, spai_level=w.spai_level, device=0)
+    t0 = time.perf_counter()
+    sim = fp.from_workload(w, precision=precision, spai_level=w.spai_level, device=0,
+                           resort_every=resort or 20)
+    log(f"{precision}: created in {time.perf_counter() - t0:.1f} s")
     info = sim.info()
     sim.diagnostics()  # Gauss baseline at step 0
-    resort = None
-    if autotune:
+    if resort is None:
         resort = sim.autotune(pusher, trial_steps=160)
         log(f"{precision}: autotuned re-sort interval {resort}")
-    sim.step(warmup, pusher)
+        # the autotuner leaves the order decayed: the next step sorts
+        align = 0
+    else:
+        # after the load's sort the next sort is at the start of step K + 1
+        align = resort
+    # warm-up: at least `warmup` steps, ending where the next step sorts
+    w_steps = align + int(math.ceil(max(warmup, 1) / resort)) * resort
+    sim.step(w_steps, pusher)
     sim.sync()
     # the timed region times the particle kernel only, on every
     # TIMING_EVERY-th step (a dispatch that carries events idles the device
-    # for several microseconds around it); the stage breakdown comes from a
-    # separate pass after it
+    # for several microseconds around it)
     sim.profile(stages=["particles"], every=TIMING_EVERY)
     t0 = time.perf_counter()
     sim.step(steps, pusher)
@@ -103,7 +172,11 @@ def run_gpu(w, precision, steps, warmup, pusher, autotune=True):
     t1 = time.perf_counter()
     particles = sim.stage_times()["particles"]
     log(f"{precision}: {steps} steps in {t1 - t0:.3f} s")
-    stage_steps = min(steps, max(100, resort or 0))  # one re-sort interval at least
+    # stage breakdown: every stage timed over whole re-sort intervals
+    stage_steps = resort * max(1, int(math.ceil(100 / resort)))
+    back = (resort - steps % resort) % resort  # back to a sort boundary
+    if back:
+        sim.step(back, pusher)
     sim.profile(True)
     sim.step(stage_steps, pusher)
     stages = sim.stage_times()
@@ -111,7 +184,28 @@ def run_gpu(w, precision, steps, warmup, pusher, autotune=True):
     diag = sim.diagnostics()
     sim.close()
     return dict(elapsed=t1 - t0, particles=particles, stages=stages, stage_steps=stage_steps,
-                diag=diag, info=info, resort=resort)
+                diag=diag, info=info, resort=resort, warmup_steps=w_steps,
+                sorts_timed=int(math.ceil(steps / resort)))
+
+
+def leg_record(r, n_p, steps, species_n, fp32, traffic=None):
+    """JSON record of one precision leg: throughput, the particle kernel's
+    algorithmic bandwidth, the per-stage breakdown and the Gauss residual."""
+    nf, ne = r["info"]["n_tris"], r["info"]["n_edges"]
+    ms, launches = r["particles"]
+    per_launch = float(np.mean([particle_launch_bytes(n, nf, ne, fp32) for n in species_n]))
+    avg_s = ms / 1e3 / max(launches, 1)
+    achieved = per_launch / avg_s / 1e9
+    return {"value": n_p * steps / r["elapsed"], "ms_per_step": r["elapsed"] / steps * 1e3,
+            "gauss_rel": r["diag"]["gauss_rel"], "resort_every": r["resort"],
+            "sorts_in_timed_steps": r["sorts_timed"],
+            "roofline": {"bound": "hbm", "kernel": "k_particle_step", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": traffic, "avg_launch_ms": avg_s * 1e3,
+                         "algorithmic_bytes_per_launch": per_launch},
+            "stage_ms_per_step": {k: v[0] / r["stage_steps"] for k, v in r["stages"].items()},
+            "hbm_gbs_step": sum(particle_launch_bytes(n, nf, ne, fp32) for n in species_n)
+            / (r["elapsed"] / steps) / 1e9}
 
 
 def run_timing_overhead(args, window=160, reps=2):
@@ -152,8 +246,10 @@ def run_timing_overhead(args, window=160, reps=2):
             "overhead_vs_untimed": {k: min(v) / base - 1.0 for k, v in out.items()}}
 
 
-def run_batched(steps, warmup, pusher):
-    """64 uneven pair-plasma runs: batched (graph replay) vs one by one."""
+def run_batched(pusher, min_steps=100):
+    """64 uneven pair-plasma runs (mixed): batched with graph replay, timed
+    over whole replayed cycles of two re-sort intervals, against the same
+    runs stepped one by one for the same number of steps."""
     from paper_1707_04333_amd import fetdpic as fp
     from paper_1707_04333_amd import inputs as I
     log("batched: generating 64 runs")
@@ -171,12 +267,20 @@ def run_batched(steps, warmup, pusher):
         s.set_resort(K)
     log(f"batched: {n_p} particles on {n_f} triangles, re-sort every {K}")
     b = fp.Batch(sims, use_graph=True)
-    b.step(max(warmup, 2 * K + 2), pusher)
+    # after the autotuner every run sorts next: an eager cycle, then the
+    # capture and a first replay
+    b.step(4 * K, pusher)
     sims[0].sync()
+    st0 = b.stats()
+    cycles = max(1, int(math.ceil(min_steps / (2 * K))))
+    steps = 2 * K * cycles
     t0 = time.perf_counter()
     b.step(steps, pusher)
     sims[0].sync()
     t_b = time.perf_counter() - t0
+    st1 = b.stats()
+    replays = st1["graph_replays"] - st0["graph_replays"]
+    eager = st1["eager_steps"] - st0["eager_steps"]
     b.close()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -187,31 +291,43 @@ def run_batched(steps, warmup, pusher):
     gauss = max(s.diagnostics()["gauss_rel"] for s in sims)
     for s in sims:
         s.close()
-    log(f"batched: {steps} steps in {t_b:.3f} s, separate {t_s:.3f} s")
-    return {"workload": "batched_sweep_64", "n_runs": len(sims), "n_particles": n_p,
+    log(f"batched: {steps} steps in {t_b:.3f} s ({replays} graph replays, {eager} eager steps), "
+        f"separate {t_s:.3f} s")
+    return {"workload": "batched_sweep_64", "n_runs": 64, "n_particles": n_p,
             "n_tris": n_f, "precision": "mixed", "value": n_p * steps / t_b,
-            "ms_per_step": t_b / steps * 1e3, "separate_value": n_p * steps / t_s,
+            "ms_per_step": t_b / steps * 1e3, "steps": steps, "graph_replays": replays,
+            "eager_steps_timed": eager, "separate_value": n_p * steps / t_s,
             "batched_vs_separate": t_s / t_b, "resort_every": K, "gauss_rel": gauss}
 
 
-def cpu_baseline(theta, n_full, pusher, sample_pairs=500_000, sample_steps=100):
-    """The FP64 oracle on the same mesh with a bounded particle sample."""
+def cpu_baseline(w, pusher, steps=2, absorber=True):
+    """The FP64 oracle (its OpenMP timing mode: particles in contiguous
+    chunks over all host threads, private currents added in thread order;
+    the field update single-threaded) on the same workload: every particle,
+    `steps` steps after one warm-up step."""
     import oracle
     from paper_1707_04333_amd import inputs as I
-    w = I.pair_plasma(n_pairs=sample_pairs, theta=theta, precision="fp64")
+    threads = oracle_threads()
     sp = [(s.q, s.m, s.w, s.tri, s.lam, s.u) for s in w.species]
-    osim = oracle.OracleSim(w.mesh, w.dt, sp, I.EPS0, I.MU0, I.C_LIGHT,
-                            spai_level=w.spai_level, bz_ext=w.bz_ext)
-    osim.step(1, pusher)
     t0 = time.perf_counter()
-    osim.step(sample_steps, pusher)
+    osim = oracle.OracleSim(w.mesh, w.dt, sp, I.EPS0, I.MU0, I.C_LIGHT,
+                            spai_level=w.spai_level, bz_ext=w.bz_ext or None)
+    if absorber and "sigma_tri" in w.extra:
+        damp, damp_b, _ = oracle.absorber_damp(osim.T, w.extra["sigma_tri"], w.dt, I.EPS0)
+        osim.damp, osim.damp_b = np.ascontiguousarray(damp), np.ascontiguousarray(damp_b)
+    setup = time.perf_counter() - t0
+    osim.step(1, pusher, threads=threads)
+    t0 = time.perf_counter()
+    osim.step(steps, pusher, threads=threads)
     el = time.perf_counter() - t0
     n = sum(s.n for s in osim.species)
-    return {"value": n * sample_steps / el, "unit": "particle-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"same mesh ({w.mesh.n_tris} triangles, FP64 field update), "
-                       f"{n} of the {n_full} particles, {sample_steps} steps after 1 warm-up "
-                       f"step, single-threaded FP64 C oracle; {el:.1f} s")}
+    info = host_info()
+    return {"value": n * steps / el, "unit": "particle-steps/s", "cores": threads,
+            "kind": "oracle", "host": info,
+            "sample": (f"the same workload ({w.mesh.n_tris} triangles, all {n} particles), "
+                       f"{steps} FP64 steps after 1 warm-up step, oracle particle stage on "
+                       f"{threads} OpenMP threads ({info['cpu_model']}), field update "
+                       f"single-threaded; {el:.1f} s timed, {setup:.1f} s setup")}
 
 
 def run_synchro(args):
@@ -410,7 +526,7 @@ def make_workload(name, args, precision):
     if name == "pair":
         return I.pair_plasma(n_pairs=args.pairs, theta=args.theta, precision=precision)
     if name == "large":
-        return I.large_run(precision=precision)
+        return I.large_run(n_particles=args.large_particles, precision=precision)
     if name == "boosted":
         w = I.boosted_oscillator()
     elif name == "cyclotron":
@@ -421,16 +537,53 @@ def make_workload(name, args, precision):
     return w
 
 
+def workload_config(name, w, info, pusher, resort, args):
+    cfg = {"workload": w.name, "n_tris": info["n_tris"], "n_edges": info["n_edges"],
+           "n_particles": w.n_particles, "pusher": pusher, "precision": "fp64",
+           "resort_every": resort, "spai_level": w.spai_level}
+    if name == "pair":
+        cfg["theta"] = args.theta
+    if name == "large":
+        cfg.update({"grade": 10.0, "absorbing_layer": True, "theta": w.extra["theta"],
+                    "beam_fraction": 0.05, "beam_gamma": 20.0})
+    return cfg
+
+
+def run_workload(name, args, pusher=None, resort=None):
+    """FP64 (the value) and the two mixed forms of one workload."""
+    w = make_workload(name, args, "fp64")
+    pusher = pusher or args.pusher or ("boris" if name == "pair" else w.pusher)
+    species_n = [s.n for s in w.species]
+    n_p = w.n_particles
+    counted = (name == "large" and args.large_particles == 128_000_000) or \
+        (name == "pair" and args.pairs == DEFAULT_PAIRS)
+    tfile = TRAFFIC_FILE if name == "large" else PAIR_TRAFFIC_FILE
+    r64 = run_gpu(w, "fp64", args.steps, args.warmup, pusher, resort)
+    rec = {"fp64": leg_record(r64, n_p, args.steps, species_n, False,
+                              measured_traffic("fp64", tfile) if counted else None)}
+    if not args.no_mixed:
+        for prec in ("mixed", "mixed_f64field"):
+            r = run_gpu(w, prec, args.steps, args.warmup, pusher, resort or r64["resort"])
+            rec[prec] = leg_record(r, n_p, args.steps, species_n, True,
+                                   measured_traffic(prec, tfile) if counted else None)
+            rec[prec]["vs_fp64"] = rec[prec]["value"] / rec["fp64"]["value"]
+    cfg = workload_config(name, w, r64["info"], pusher, r64["resort"], args)
+    return w, cfg, rec, r64
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="pair")
+    ap.add_argument("--workload", default="large")
     ap.add_argument("--theta", type=float, default=0.1)
     ap.add_argument("--pusher", default=None)
     ap.add_argument("--pairs", type=int, default=DEFAULT_PAIRS)
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--large-particles", type=int, default=128_000_000)
+    ap.add_argument("--no-fp64", action="store_true", help="tetrahedral workload only")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-pair", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -466,69 +619,58 @@ def main():
     if args.workload == "tet":
         print(json.dumps(run_tet(args)))
         return
-    log(f"generating workload {args.workload}")
-    w = make_workload(args.workload, args, "mixed")
-    pusher = args.pusher or ("boris" if args.workload == "pair" else w.pusher)
-    n_p = w.n_particles
-    species_n = [s.n for s in w.species]
-    mixed = run_gpu(w, "mixed", args.steps, args.warmup, pusher, not args.no_autotune)
-    del w
-    value = n_p * args.steps / mixed["elapsed"]
-    info = mixed["info"]
-    nf, ne = info["n_tris"], info["n_edges"]
-    ms, launches = mixed["particles"]
-    per_launch_bytes = float(np.mean([particle_launch_bytes(n, nf, ne, True) for n in species_n]))
-    avg_s = ms / 1e3 / max(launches, 1)
-    achieved = per_launch_bytes / avg_s / 1e9
-    # the counters were taken on the default workload size only
-    counted = args.workload == "pair" and args.pairs == DEFAULT_PAIRS
-    traffic = measured_traffic("mixed") if counted else None
+    name = args.workload
+    log(f"generating workload {name}")
+    resort = None
+    if name == "large":
+        resort = LARGE_RESORT
+    elif args.no_autotune:
+        resort = 20
+    w, cfg, rec, r64 = run_workload(name, args, resort=resort)
+    f64 = rec["fp64"]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": f64["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": mixed["elapsed"] / args.steps * 1e3,
+        "ms_per_step": f64["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 particle state/push/track, f64 deposit+fields",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_tris": nf, "n_edges": ne,
-                   "n_particles": n_p, "theta": args.theta if args.workload == "pair" else None,
-                   "pusher": pusher, "precision": "mixed", "resort_every": mixed["resort"],
-                   "spai_level": 1},
-        "roofline": {"bound": "hbm", "kernel": "k_particle_step", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_launch_ms": avg_s * 1e3,
-                     "algorithmic_bytes_per_launch": per_launch_bytes},
-        "stage_ms_per_step": {k: v[0] / mixed["stage_steps"] for k, v in mixed["stages"].items()},
-        "gauss_rel": mixed["diag"]["gauss_rel"],
-        "hbm_gbs_step": sum(particle_launch_bytes(n, nf, ne, True) for n in species_n)
-        / (mixed["elapsed"] / args.steps) / 1e9,
+        "config": cfg,
+        "roofline": f64["roofline"],
+        "stage_ms_per_step": f64["stage_ms_per_step"],
+        "gauss_rel": f64["gauss_rel"],
+        "hbm_gbs_step": f64["hbm_gbs_step"],
+        "sorts_in_timed_steps": f64["sorts_in_timed_steps"],
+        "aligned_warmup_steps": r64["warmup_steps"],
     }
-    if not args.no_fp64:
-        w64 = make_workload(args.workload, args, "fp64")
-        r64 = run_gpu(w64, "fp64", args.steps, args.warmup, pusher, not args.no_autotune)
-        del w64
-        ms64, l64 = r64["particles"]
-        b64 = float(np.mean([particle_launch_bytes(n, nf, ne, False) for n in species_n]))
-        a64 = b64 / (ms64 / 1e3 / max(l64, 1)) / 1e9
-        out["fp64"] = {"value": n_p * args.steps / r64["elapsed"],
-                       "ms_per_step": r64["elapsed"] / args.steps * 1e3,
-                       "gauss_rel": r64["diag"]["gauss_rel"], "resort_every": r64["resort"],
-                       "particle_kernel_gbs": a64, "particle_kernel_frac": a64 / HBM_PEAK_GBS,
-                       "particle_kernel_traffic": measured_traffic("fp64") if counted else None,
-                       "stage_ms_per_step": {k: v[0] / r64["stage_steps"]
-                                             for k, v in r64["stages"].items()}}
-        out["mixed_vs_fp64"] = value / out["fp64"]["value"]
-    if not args.no_batched and args.workload == "pair":
-        out["batched"] = run_batched(min(args.steps, 100), args.warmup, pusher)
-    if not args.no_cpu and args.workload == "pair":
-        log("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(args.theta, n_p, pusher)
+    for prec in ("mixed", "mixed_f64field"):
+        if prec in rec:
+            out[prec] = rec[prec]
+    if "mixed" in rec:
+        out["mixed_vs_fp64"] = rec["mixed"]["vs_fp64"]
+    try:
+        ceil = copy_ceiling_gbs()
+        out["copy_ceiling_gbs"] = ceil
+        out["roofline"]["frac_of_copy_ceiling"] = out["roofline"]["achieved"] / ceil
+    except Exception as ex:  # the copy needs torch on the GPU
+        log(f"copy ceiling not measured: {ex}")
+    if name == "large" and not args.no_pair:
+        log("pair plasma leg (199,712 triangles, 16M particles)")
+        pargs = argparse.Namespace(**vars(args))
+        _, pcfg, prec_rec, _ = run_workload("pair", pargs)
+        out["pair_plasma"] = {"config": pcfg, **prec_rec}
+    if not args.no_batched and name in ("large", "pair"):
+        out["batched"] = run_batched("boris")
+    if not args.no_cpu and name in ("large", "pair"):
+        log("timing the CPU oracle on the headline workload")
+        out["cpu_baseline"] = cpu_baseline(w, cfg["pusher"])
+    del w
     print(json.dumps(out))
 
 

@@ -24,9 +24,9 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_records_match_the_kernel_sources():
-    for prec in ("mixed", "fp64"):
-        for rec, src in ((bench.TRAFFIC_FILE, bench.KERNEL_SRC),
-                         (bench.TRAFFIC3_FILE, bench.KERNEL3_SRC)):
+    for precs, rec, src in ((("fp64", "mixed"), bench.TRAFFIC_FILE, bench.KERNEL_SRC),
+                            (("mixed", "fp64"), bench.TRAFFIC3_FILE, bench.KERNEL3_SRC)):
+        for prec in precs:
             t = bench.measured_traffic(prec, rec, src)
             assert t is not None and t > 0, (rec, prec)
 
@@ -38,16 +38,22 @@ def test_traffic_is_null_for_another_source(tmp_path):
 
 
 def test_cpu_baseline_record(oracle_lib):
-    cb = bench.cpu_baseline(0.1, 16_000_000, "boris", sample_pairs=2000, sample_steps=2)
-    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["unit"] == "particle-steps/s"
-    assert cb["value"] > 0 and "4000 of the 16000000 particles, 2 steps" in cb["sample"]
+    from paper_1707_04333_amd import inputs as I
+    w = I.large_run(n_side=40, n_particles=5000, precision="fp64")
+    cb = bench.cpu_baseline(w, "hc", steps=2)
+    assert cb["kind"] == "oracle" and cb["unit"] == "particle-steps/s"
+    assert cb["cores"] == bench.oracle_threads() >= 1
+    for k in ("cpu_model", "os_cpu_count", "affinity_cpus", "OMP_NUM_THREADS"):
+        assert k in cb["host"], k
+    assert cb["value"] > 0 and "all 5000 particles" in cb["sample"] and "2 FP64 steps" in cb["sample"]
 
 
 @pytest.mark.gpu
 def test_bench_json_line():
-    r = subprocess.run([sys.executable, "bench.py", "--pairs", "50000", "--steps", "20",
-                        "--warmup", "5", "--no-batched", "--no-autotune", "--no-cpu",
-                        "--no-fp64"], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    r = subprocess.run([sys.executable, "bench.py", "--workload", "pair", "--pairs", "50000",
+                        "--steps", "20", "--warmup", "5", "--no-batched", "--no-autotune",
+                        "--no-cpu", "--no-mixed"], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = r.stdout.strip().splitlines()
     assert len(lines) == 1
@@ -57,7 +63,8 @@ def test_bench_json_line():
               "roofline"):
         assert k in out, k
     assert out["n_gpus"] == 1 and out["steps"] == 20 and out["warmup"] == 5
-    assert out["config"]["workload"] == "pair" and out["value"] > 0
+    assert out["config"]["workload"] == "pair_plasma_bernstein" and out["value"] > 0
+    assert out["dtype"] == "f64" and out["sorts_in_timed_steps"] >= 1
     rl = out["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in rl, k
