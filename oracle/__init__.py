@@ -87,6 +87,9 @@ def _declare(L):
     L.o_charge.restype = None
     L.o_spai.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, ctypes.c_int64]
     L.o_spai.restype = ctypes.c_int64
+    L.o_ampere_pml.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P,
+                               P, P, P, P, P, P, P, P, P, P, P]
+    L.o_ampere_pml.restype = None
 
 
 def _p(a):
@@ -235,6 +238,73 @@ def hodge_eps(T: Topology, eps0: float):
     return _coo_to_csr(T.ne, r, c, v)
 
 
+def hodge_eps_parts(T: Topology, eps0: float):
+    """The two parts of [*eps] (Sec. II.A) carried by the x and the y
+    components of the Whitney 1-forms: eps0 int W_i,x W_j,x and
+    eps0 int W_i,y W_j,y, assembled like hodge_eps (their sum is [*eps] on
+    the free edges).  Returns two CSR triples; wall rows are empty."""
+    nf = T.nf
+    G = T.grad.reshape(nf, 3, 2)
+    A = T.area
+    free = T.edge_free.astype(bool)
+    out = []
+    for comp in (0, 1):
+        rows, cols, vals = [], [], []
+        for k in range(3):
+            a, b = (k + 1) % 3, (k + 2) % 3
+            for l in range(3):
+                c, d = (l + 1) % 3, (l + 2) % 3
+
+                def I(i, j):
+                    return A * (2.0 if i == j else 1.0) / 12.0
+
+                def gd(i, j):
+                    return G[:, i, comp] * G[:, j, comp]
+
+                val = (gd(b, d) * I(a, c) - gd(b, c) * I(a, d)
+                       - gd(a, d) * I(b, c) + gd(a, c) * I(b, d))
+                rows.append(T.tri_edge[:, k])
+                cols.append(T.tri_edge[:, l])
+                vals.append(eps0 * T.tri_sign[:, k] * T.tri_sign[:, l] * val)
+        r = np.concatenate(rows).astype(np.int64)
+        c = np.concatenate(cols).astype(np.int64)
+        v = np.concatenate(vals)
+        keep = free[r] & free[c]
+        out.append(_coo_to_csr(T.ne, r[keep], c[keep], v[keep]))
+    return out
+
+
+def pml_setup(T: Topology, sigma_tri, dt: float, eps0: float, axis: int = 0):
+    """Uniaxial PML stretched along `axis` (0: layers normal to x, 1: to y)
+    with conductivity sigma_tri per triangle: the PML rows (free edges whose
+    conductivity, the mean of their triangles', is positive), kappa =
+    sigma/eps0 per row, the rows of the normal and tangential parts of
+    [*eps], zeroed auxiliary fluxes, and the matched magnetic loss factor
+    per triangle (as absorber_damp)."""
+    sg = np.asarray(sigma_tri, dtype=np.float64)
+    f0, f1 = T.edge_tri[:, 0], T.edge_tri[:, 1]
+    se = sg[f0].copy()
+    two = f1 >= 0
+    se[two] = 0.5 * (sg[f0[two]] + sg[f1[two]])
+    rows = np.nonzero((se > 0) & T.edge_free.astype(bool))[0].astype(np.int32)
+    parts = hodge_eps_parts(T, eps0)
+    Mn, Mt = parts[axis], parts[1 - axis]
+
+    def take(Mx):
+        ptr, col, val = Mx
+        cnt = ptr[rows + 1] - ptr[rows]
+        optr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+        idx = np.concatenate([np.arange(ptr[r], ptr[r + 1]) for r in rows]) if rows.size else \
+            np.zeros(0, np.int64)
+        return optr, col[idx].astype(np.int32), val[idx].copy()
+
+    xt = sg * dt / (2.0 * eps0)
+    damp_b = np.where(sg > 0, (1.0 - xt) / (1.0 + xt), 1.0)
+    return {"rows": rows, "kappa": se[rows] / eps0, "n": take(Mn), "t": take(Mt),
+            "psi": np.zeros(rows.size), "phi": np.zeros(rows.size), "extra": np.zeros(T.ne),
+            "damp_b": damp_b, "axis": axis}
+
+
 def _coo_to_csr(n, r, c, v):
     order = np.lexsort((c, r))
     r, c, v = r[order], c[order], v[order]
@@ -314,7 +384,7 @@ class OracleSim:
     e^{n+1} = M~ d^{n+1}."""
 
     def __init__(self, mesh, dt, species, eps0, mu0, c, spai_level=1, bz_ext=None,
-                 e_ext=None, affine=None, cap=64, damp=None, damp_b=None):
+                 e_ext=None, affine=None, cap=64, damp=None, damp_b=None, pml=None):
         self.T = Topology(mesh.node_xy, mesh.tri_nodes, mesh.tri_shift, mesh.period) \
             if not isinstance(mesh, Topology) else mesh
         T = self.T
@@ -334,6 +404,7 @@ class OracleSim:
         self.damp = None if damp is None else np.ascontiguousarray(damp, dtype=np.float64)
         self.damp_b = None if damp_b is None else np.ascontiguousarray(damp_b, dtype=np.float64)
         self.species = [OSpecies(*s) if not isinstance(s, OSpecies) else s for s in species]
+        self.pml = pml  # pml_setup() record, or None
         self.cap = cap
         self.step_count = 0
         self.segments = 0
@@ -379,8 +450,17 @@ class OracleSim:
                     rc = L.o_particles(*args)
                 if rc != 0:
                     raise RuntimeError(f"oracle particle stage failed rc={rc} at particle {bad[0]}")
-            L.o_ampere(ms, _p(b_new), _p(self.cur), self.dt, self.mu0, _p(self.damp),
-                       _p(self.d), _p(self.e))
+            if self.pml is not None:
+                P = self.pml
+                L.o_ampere_pml(ms, _p(b_new), _p(self.cur), self.dt, self.mu0,
+                               int(P["rows"].size), _p(P["rows"]), _p(P["kappa"]),
+                               _p(P["n"][0]), _p(P["n"][1]), _p(P["n"][2]),
+                               _p(P["t"][0]), _p(P["t"][1]), _p(P["t"][2]),
+                               _p(P["psi"]), _p(P["phi"]), _p(P["extra"]), _p(self.d),
+                               _p(self.e))
+            else:
+                L.o_ampere(ms, _p(b_new), _p(self.cur), self.dt, self.mu0, _p(self.damp),
+                           _p(self.d), _p(self.e))
             self.b = b_new
             self.last_cur[:] = self.cur
             self.cur[:] = 0.0

@@ -639,3 +639,61 @@ int o_particles_omp(int nthreads, const o_mesh *M, const double *e, const double
     free(prc);
     return rc;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Uniaxial perfectly matched layer (the absorbing boundary of Sec. III.C; */
+/* the construction is the build's own, the paper's references are not     */
+/* available).  For a layer stretched along axis n (s = 1 + sigma/(j w      */
+/* eps0)), the permittivity tensor is eps0 diag(1/s, s) in (n, t) and the   */
+/* permeability mu0 s.  Splitting the Hodge matrix [*eps] = M_n + M_t into   */
+/* the parts of the two field components (int W_i,n W_j,n and               */
+/* int W_i,t W_j,t) and taking the stretching per edge row                  */
+/* (kappa = sigma_edge / eps0), the update of d = C^T [*mu^-1] b - i stays   */
+/* that of the lossless medium, and                                         */
+/*   e = [*eps]^-1 (d + psi - phi),                                         */
+/*   d psi/dt = kappa (M_n e - psi),   d phi/dt = kappa M_t e,               */
+/* (the n part of the flux is divided by s, the t part multiplied by s).    */
+/* The magnetic loss is the matched one on b (damp_b of o_faraday).         */
+/* ---------------------------------------------------------------------- */
+void o_ampere_pml(const o_mesh *M, const double *b_half, const double *cur, double dt,
+                  double mu0, int npml, const int32_t *rows, const double *kappa,
+                  const int32_t *n_ptr, const int32_t *n_col, const double *n_val,
+                  const int32_t *t_ptr, const int32_t *t_col, const double *t_val,
+                  double *psi, double *phi, double *extra, double *d, double *e)
+{
+    /* d^{n+1} = d^n + dt (C^T [*mu^-1] b^{n+1/2} - i), no loss */
+    for (int ed = 0; ed < M->ne; ++ed) {
+        if (!M->edge_free[ed]) {
+            d[ed] = 0.0;
+            continue;
+        }
+        double curl = 0.0;
+        for (int j = 0; j < 2; ++j) {
+            int f = M->edge_tri[2 * ed + j];
+            if (f < 0) continue;
+            curl += M->edge_tsign[2 * ed + j] * (b_half[f] / (mu0 * M->area[f]));
+        }
+        d[ed] = d[ed] + dt * (curl - cur[ed]);
+    }
+    /* auxiliary fluxes from e^n (semi-implicit in psi, explicit in phi) */
+    for (int k = 0; k < npml; ++k) {
+        double x = 0.0, y = 0.0;
+        for (int j = n_ptr[k]; j < n_ptr[k + 1]; ++j) x += n_val[j] * e[n_col[j]];
+        for (int j = t_ptr[k]; j < t_ptr[k + 1]; ++j) y += t_val[j] * e[t_col[j]];
+        double c = kappa[k] * dt;
+        psi[k] = (psi[k] * (1.0 - 0.5 * c) + c * x) / (1.0 + 0.5 * c);
+        phi[k] = phi[k] + c * y;
+        extra[rows[k]] = psi[k] - phi[k];
+    }
+    /* e^{n+1} = M~ (d^{n+1} + psi - phi) */
+    for (int ed = 0; ed < M->ne; ++ed) {
+        if (!M->edge_free[ed]) {
+            e[ed] = 0.0;
+            continue;
+        }
+        double acc = 0.0;
+        for (int j = M->mt_ptr[ed]; j < M->mt_ptr[ed + 1]; ++j)
+            acc += M->mt_val[j] * (d[M->mt_col[j]] + extra[M->mt_col[j]]);
+        e[ed] = acc;
+    }
+}
