@@ -119,23 +119,10 @@ def oracle_threads():
 
 def copy_ceiling_gbs(nbytes=1 << 30, reps=5):
     """Measured device-to-device copy bandwidth (read + write bytes per
-    second) of a plain 1 GiB copy: the achievable HBM ceiling."""
-    import torch
-    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    best = float("inf")
-    for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        dst.copy_(src)
-        b.record()
-        b.synchronize()
-        best = min(best, a.elapsed_time(b) / 1e3)
-    del src, dst
-    torch.cuda.empty_cache()
-    return 2.0 * nbytes / best / 1e9
+    second) of the library's plain copy kernel over 1 GiB buffers: the
+    achievable HBM ceiling."""
+    from paper_1707_04333_amd import fetdpic as fp
+    return fp.copy_ceiling(0, nbytes, reps)
 
 
 def run_gpu(w, precision, steps, warmup, pusher, resort=None):

@@ -339,6 +339,13 @@ fetd_status fetd_probe_set(fetd_sim *sim, int64_t n, const double *xy, int32_t e
 fetd_status fetd_probe_get(fetd_sim *sim, double *dst, int64_t capacity_bytes,
                            int64_t *n_samples);
 
+/* Measured bandwidth ceiling of the device: a plain copy kernel (16-byte
+ * vectors, grid-stride) over two buffers of `bytes` bytes that it allocates
+ * and frees, the best of a few grid sizes and `reps` timed launches each;
+ * *gbs gets (read + write bytes) / time in GB/s.  The reference against
+ * which the particle kernel's bandwidth is also reported. */
+fetd_status fetd_copy_ceiling(int32_t device, int64_t bytes, int32_t reps, double *gbs);
+
 /* Sizes and SPAI quality. */
 fetd_status fetd_info_get(fetd_sim *sim, fetd_info *out);
 

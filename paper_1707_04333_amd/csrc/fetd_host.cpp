@@ -1753,6 +1753,52 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     return FETD_OK;
 }
 
+fetd_status fetd_copy_ceiling(int32_t device, int64_t bytes, int32_t reps, double *gbs)
+{
+    if (!gbs || bytes < (int64_t(1) << 20) || reps < 1) {
+        g_last_error = "invalid copy-ceiling arguments";
+        return FETD_E_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        g_last_error = "no such HIP device";
+        return FETD_E_HIP;
+    }
+    DeviceGuard g(device);
+    const int64_t n16 = bytes / 16;
+    void *a = nullptr, *b = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&a, size_t(n16) * 16);
+    if (e == hipSuccess) e = hipMalloc(&b, size_t(n16) * 16);
+    if (e == hipSuccess) e = hipMemset(a, 0x3c, size_t(n16) * 16);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double best = 0.0;
+    // the best of a few grid sizes, each timed `reps` times after one untimed launch
+    for (int blocks : {512, 1024, 2048, 4096}) {
+        for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+            e = hipEventRecord(e0, nullptr);
+            if (e == hipSuccess) e = launch_copy(nullptr, a, b, n16, blocks);
+            if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && r > 0 && ms > 0.f)
+                best = std::max(best, 2.0 * double(n16) * 16.0 / (double(ms) * 1e-3) / 1e9);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (e != hipSuccess) {
+        g_last_error = std::string("copy ceiling: ") + hipGetErrorString(e);
+        return FETD_E_HIP;
+    }
+    *gbs = best;
+    return FETD_OK;
+}
+
 fetd_status fetd_info_get(fetd_sim *s, fetd_info *out)
 {
     if (!s || !out) return FETD_E_ARG;

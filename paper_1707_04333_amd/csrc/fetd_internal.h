@@ -179,6 +179,9 @@ hipError_t launch_probe(hipStream_t s, int n, const int32_t *tri, const double *
                         const int4 *tri_edge, const double *grad64, const void *e, bool field32,
                         double *acc, double *out, double inv_window);
 
+// Copy of n16 16-byte vectors with `blocks` blocks of 256 threads (bandwidth ceiling).
+hipError_t launch_copy(hipStream_t s, const void *src, void *dst, int64_t n16, int blocks);
+
 // Diagnostics.
 hipError_t launch_charge(hipStream_t s, int64_t n, const uint32_t *key, const void *lam,
                          bool fp32, const int4 *tri_node, double qw, double *q);

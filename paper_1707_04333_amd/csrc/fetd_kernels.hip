@@ -556,7 +556,26 @@ __global__ __launch_bounds__(256) void k_kinetic(int64_t n, const uint32_t *__re
 
 inline unsigned grid_for(int64_t n, int block) { return unsigned((n + block - 1) / block); }
 
+// Plain 16-byte-vector copy, grid-stride: the achievable HBM bandwidth of a
+// stream that reads and writes every byte once (the reference ceiling the
+// particle kernel is compared with).
+__global__ __launch_bounds__(256) void k_copy(const float4 *__restrict__ src,
+                                              float4 *__restrict__ dst, int64_t n)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = src[i];
+}
+
 }  // namespace
+
+hipError_t launch_copy(hipStream_t s, const void *src, void *dst, int64_t n16, int blocks)
+{
+    if (n16 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, static_cast<const float4 *>(src),
+                       static_cast<float4 *>(dst), n16);
+    return hipGetLastError();
+}
 
 hipError_t launch_faraday(hipStream_t s, const FieldDesc &d)
 {

@@ -103,6 +103,7 @@ def lib():
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32],
                     "fetd_batch_stats": [P, P, P, P],
+                    "fetd_copy_ceiling": [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P],
                     "fetd_set_absorber": [P, P],
                     "fetd_set_ext_scale": [P, ctypes.c_double],
                     "fetd_probe_set": [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int64],
@@ -343,6 +344,13 @@ def stage_times(h):
     n = np.zeros(len(STAGES), dtype=np.int64)
     _check(lib().fetd_stage_times(h, _p(ms), _p(n)), h)
     return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(STAGES)}
+
+
+def copy_ceiling(device=0, nbytes=1 << 30, reps=5):
+    """fetd_copy_ceiling: measured copy bandwidth (read + write) in GB/s."""
+    out = ctypes.c_double()
+    _check(lib().fetd_copy_ceiling(int(device), int(nbytes), int(reps), ctypes.byref(out)))
+    return out.value
 
 
 def destroy(h):
