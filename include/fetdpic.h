@@ -321,6 +321,24 @@ fetd_status fetd_batch_stats(fetd_batch *batch, int64_t *graph_captures, int64_t
                              int64_t *eager_steps);
 void fetd_batch_destroy(fetd_batch *batch);
 
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid allocation): n_steps batched steps of the n simulations, as
+ * fetd_batch_create + fetd_batch_step would take them (same kernels, same
+ * results; eager launches, no graph), without a batch object and without
+ * allocating anything.  The descriptor and prefix tables and the tile queue
+ * the batched kernels read go to a fixed device array of the library
+ * (384 KiB per device, held until the process ends), which limits a call to
+ * n <= 256 simulations and 512 non-empty species in all (FETD_E_ARG
+ * beyond).  The call uploads its tables from host memory and waits for the
+ * members' stream once before its first launch; the rest is asynchronous on
+ * that stream.  Every call on a device shares that device's array: calls
+ * that overlap on one device (other threads, other streams) race.  The
+ * members must share device, stream, precision and the deterministic
+ * option; the re-sort interval is the first member's.  A member's Gauss
+ * accounting, if it has none yet, starts at its next fetd_diagnostics. */
+fetd_status fetd_batch_step_noalloc(fetd_sim *const *sims, int32_t n, int32_t n_steps,
+                                    int32_t pusher);
+
 /* Field probes (Sec. III.C samples E along a line at every step to obtain
  * the dispersion relation).  n points xy [2n] (metres; located like
  * fetd_particles_load, FETD_E_ARG if one lies outside the mesh).  After

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -2164,3 +2165,207 @@ void fetd_batch_destroy(fetd_batch *b)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------
+// Batched stepping without allocation.
+//
+// fetd_batch_step_noalloc steps a list of simulations together with the
+// batched kernels, like fetd_batch_step, but needs no batch object: the
+// tables those kernels read (per-run field descriptors, per-segment particle
+// descriptors for both sort parities, block and tile prefix tables, the tile
+// queue) go to `scratch`, a fixed device array of the library, instead of
+// device memory allocated per batch.  Every call on a device shares that
+// device's copy and rewrites it, so calls that overlap on one device race.
+// ---------------------------------------------------------------------
+namespace {
+
+constexpr int kNoAllocRuns = 256;
+constexpr int kNoAllocSegs = 512;
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t kOffFields = 0;
+constexpr size_t kOffSegs0 = align256(kOffFields + sizeof(FieldDesc) * kNoAllocRuns);
+constexpr size_t kOffSegs1 = align256(kOffSegs0 + sizeof(SegDesc) * kNoAllocSegs);
+constexpr size_t kOffTriPrefix = align256(kOffSegs1 + sizeof(SegDesc) * kNoAllocSegs);
+constexpr size_t kOffEdgePrefix = align256(kOffTriPrefix + 4 * size_t(kNoAllocRuns + 1));
+constexpr size_t kOffSegPrefix = align256(kOffEdgePrefix + 4 * size_t(kNoAllocRuns + 1));
+constexpr size_t kOffQueue = align256(kOffSegPrefix + 4 * size_t(kNoAllocSegs + 1));
+constexpr size_t kScratchBytes = align256(kOffQueue + 2 * sizeof(uint32_t));
+static_assert(kScratchBytes <= 393216, "scratch stays at 384 KiB");
+
+}  // namespace
+
+// The library's fixed device array for fetd_batch_step_noalloc (one copy
+// per device, held until the process ends).  Host code must not pass this
+// name to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_noalloc_mu;          // host staging tables and the address cache
+void *g_scratch_dev[64] = {};     // device address of `scratch` per device ordinal
+
+struct NoAllocStaging {
+    FieldDesc fields[kNoAllocRuns];
+    SegDesc segs[2][kNoAllocSegs];
+    uint32_t tri_prefix[kNoAllocRuns + 1];
+    uint32_t edge_prefix[kNoAllocRuns + 1];
+    uint32_t seg_prefix[kNoAllocSegs + 1];
+    int seg_run[kNoAllocSegs], seg_species[kNoAllocSegs];
+    int64_t seg_tiles[kNoAllocSegs];
+};
+NoAllocStaging g_staging;
+
+// Device address of `scratch` on `device` (the current device), looked up
+// once per device.
+hipError_t scratch_address(int device, char **out)
+{
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[device] = p;
+    }
+    *out = static_cast<char *>(g_scratch_dev[device]);
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" fetd_status fetd_batch_step_noalloc(fetd_sim *const *sims, int32_t n, int32_t n_steps,
+                                               int32_t pusher)
+{
+    if (!sims || n <= 0 || n_steps < 0 || pusher < 0 || pusher > 3) {
+        g_last_error = "invalid batch arguments";
+        return FETD_E_ARG;
+    }
+    for (int32_t i = 0; i < n; ++i)
+        if (!sims[i]) {
+            g_last_error = "invalid batch arguments";
+            return FETD_E_ARG;
+        }
+    fetd_sim *s0 = sims[0];
+    int nseg = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        fetd_sim *s = sims[i];
+        if (s->stream != s0->stream || s->device != s0->device || s->fp32() != s0->fp32() ||
+            s->deterministic != s0->deterministic) {
+            g_last_error = "batch members must share device, stream, precision and determinism";
+            return FETD_E_ARG;
+        }
+        for (const Species &sp : s->species) nseg += sp.n > 0 ? 1 : 0;
+    }
+    if (n > kNoAllocRuns || nseg > kNoAllocSegs) {
+        g_last_error = "fetd_batch_step_noalloc: more than 256 runs or 512 species segments";
+        return FETD_E_ARG;
+    }
+    if (n_steps == 0) return FETD_OK;
+    DeviceGuard g(s0->device);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    char *base = nullptr;
+    if (hipError_t e = scratch_address(s0->device, &base)) {
+        g_last_error = std::string("scratch address: ") + hipGetErrorString(e);
+        return FETD_E_HIP;
+    }
+    // descriptor tables (as fetd_batch_create builds them), segments largest first
+    NoAllocStaging &h = g_staging;
+    h.tri_prefix[0] = h.edge_prefix[0] = h.seg_prefix[0] = 0;
+    int k = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        fetd_sim *s = sims[r];
+        h.fields[r] = field_desc(s);
+        h.tri_prefix[r + 1] = h.tri_prefix[r] + uint32_t((s->nf + 255) / 256);
+        h.edge_prefix[r + 1] = h.edge_prefix[r] + uint32_t((s->ne + 255) / 256);
+        for (size_t q = 0; q < s->species.size(); ++q)
+            if (s->species[q].n > 0) {
+                h.seg_run[k] = r;
+                h.seg_species[k] = int(q);
+                h.seg_tiles[k] = tiles_of(s->species[q].n);
+                ++k;
+            }
+    }
+    // stable selection order by tile count, largest first (insertion sort:
+    // no allocation)
+    int order[kNoAllocSegs];
+    for (int i = 0; i < nseg; ++i) {
+        int j = i;
+        while (j > 0 && h.seg_tiles[order[j - 1]] < h.seg_tiles[i]) {
+            order[j] = order[j - 1];
+            --j;
+        }
+        order[j] = i;
+    }
+    for (int i = 0; i < nseg; ++i) {
+        const int q = order[i];
+        fetd_sim *s = sims[h.seg_run[q]];
+        const Species &sp = s->species[h.seg_species[q]];
+        for (int par = 0; par < 2; ++par) h.segs[par][i] = seg_desc(s, sp, s->pbuf ^ par);
+        h.seg_prefix[i + 1] = h.seg_prefix[i] + uint32_t(h.seg_tiles[q]);
+    }
+    const hipStream_t stream = s0->stream;
+    FieldDesc *d_fields = reinterpret_cast<FieldDesc *>(base + kOffFields);
+    SegDesc *d_segs[2] = {reinterpret_cast<SegDesc *>(base + kOffSegs0),
+                          reinterpret_cast<SegDesc *>(base + kOffSegs1)};
+    uint32_t *d_tp = reinterpret_cast<uint32_t *>(base + kOffTriPrefix);
+    uint32_t *d_ep = reinterpret_cast<uint32_t *>(base + kOffEdgePrefix);
+    uint32_t *d_sp = reinterpret_cast<uint32_t *>(base + kOffSegPrefix);
+    uint32_t *d_queue = reinterpret_cast<uint32_t *>(base + kOffQueue);
+    // the copies read the host staging tables: wait for them before the
+    // staging can be rebuilt by a later call
+    hipError_t e = hipMemcpyAsync(d_fields, h.fields, sizeof(FieldDesc) * n,
+                                  hipMemcpyHostToDevice, stream);
+    for (int par = 0; par < 2 && e == hipSuccess; ++par)
+        e = hipMemcpyAsync(d_segs[par], h.segs[par], sizeof(SegDesc) * size_t(nseg),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_tp, h.tri_prefix, 4 * size_t(n + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_ep, h.edge_prefix, 4 * size_t(n + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_sp, h.seg_prefix, 4 * size_t(nseg + 1), hipMemcpyHostToDevice,
+                           stream);
+    // the tile queue starts at zero (a fill kernel, no memset node)
+    if (e == hipSuccess) e = launch_fill_u32(stream, d_queue, 0u, 2);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        g_last_error = std::string("fetd_batch_step_noalloc upload: ") + hipGetErrorString(e);
+        return FETD_E_HIP;
+    }
+    // steps: the re-sort interval of the first simulation, counted from the
+    // members' largest steps-since-sort (as a batch does)
+    const int K = s0->resort_every;
+    int since = 0;
+    for (int32_t i = 0; i < n; ++i) since = std::max<int>(since, int(sims[i]->steps_since_sort));
+    int parity = 0;
+    const uint32_t tri_blocks = h.tri_prefix[n], edge_blocks = h.edge_prefix[n];
+    const uint32_t tiles = h.seg_prefix[nseg];
+    for (int it = 0; it < n_steps; ++it) {
+        if (since >= K) {
+            for (int32_t i = 0; i < n; ++i)
+                if (fetd_status st = sort_all(sims[i], stream)) {
+                    g_last_error = sims[i]->err;
+                    return st;
+                }
+            parity ^= 1;
+            since = 0;
+        }
+        e = launch_faraday_batched(stream, d_fields, d_tp, n, tri_blocks);
+        if (e == hipSuccess)
+            e = launch_particles_batched(stream, d_segs[parity], d_sp, nseg, tiles, d_queue, pusher,
+                                         s0->fp32(), s0->deterministic);
+        if (e == hipSuccess) e = launch_ampere_batched(stream, d_fields, d_ep, n, edge_blocks);
+        if (e == hipSuccess) e = launch_spmv_batched(stream, d_fields, d_ep, n, edge_blocks);
+        if (e != hipSuccess) {
+            g_last_error = std::string("fetd_batch_step_noalloc: ") + hipGetErrorString(e);
+            return FETD_E_HIP;
+        }
+        ++since;
+        for (int32_t i = 0; i < n; ++i) {
+            ++sims[i]->step;
+            sims[i]->steps_since_sort = since;
+        }
+    }
+    return FETD_OK;
+}

@@ -103,6 +103,8 @@ def lib():
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32],
                     "fetd_batch_stats": [P, P, P, P],
+                    "fetd_batch_step_noalloc": [P, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_int32],
                     "fetd_copy_ceiling": [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P],
                     "fetd_set_absorber": [P, P],
                     "fetd_set_ext_scale": [P, ctypes.c_double],
@@ -453,6 +455,13 @@ def batch_stats(b):
     c, r, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(lib().fetd_batch_stats(b, ctypes.byref(c), ctypes.byref(r), ctypes.byref(e)))
     return {"graph_captures": c.value, "graph_replays": r.value, "eager_steps": e.value}
+
+
+def batch_step_noalloc(sims, n_steps, pusher="boris"):
+    """fetd_batch_step_noalloc over a list of Sim objects."""
+    pid = PUSHERS[pusher] if isinstance(pusher, str) else int(pusher)
+    arr = (ctypes.c_void_p * len(sims))(*[sm.h.value for sm in sims])
+    _check(lib().fetd_batch_step_noalloc(arr, len(sims), int(n_steps), pid))
 
 
 def batch_destroy(b):
