@@ -199,8 +199,29 @@ fetd_status fetd_set_ext_scale(fetd_sim *sim, double scale);
  * lossy edge are left out of the Gauss residual of fetd_diagnostics.
  * FETD_E_ARG (nothing changed) if any sigma is negative or not finite.
  * A batch that holds the simulation takes the new layer at its next
- * fetd_batch_step, as it does after fetd_fields_set or a new species. */
+ * fetd_batch_step, as it does after fetd_fields_set or a new species.
+ * Replaces a PML set by fetd_set_pml. */
 fetd_status fetd_set_absorber(fetd_sim *sim, const double *sigma_tri);
+
+/* Uniaxial perfectly matched layer, the absorbing boundary of Sec. III.C
+ * (whose construction the paper leaves to its references; built here from
+ * the stretched-coordinate medium): conductivity sigma_tri [S/m] per
+ * triangle (nf values, host memory, read during the call; NULL clears),
+ * stretching along axis (0: layers normal to x, such as the left and right
+ * boundaries of a strip periodic in y; 1: normal to y).  With
+ * s = 1 + sigma/(j omega eps0) the layer's permittivity is eps0 diag(1/s, s)
+ * in (normal, tangential) and its permeability mu0 s: the magnetic loss on b
+ * is the matched one (as fetd_set_absorber's), d is updated without loss,
+ * and e = M~ (d + psi - phi) with two auxiliary fluxes per layer edge row,
+ * psi (the normal part of [*eps] e, divided by s) and phi (the tangential
+ * part, multiplied by s), each edge taking the mean conductivity of its
+ * triangles.  Waves at oblique incidence are absorbed as at normal
+ * incidence, and Gauss's law holds at every free node, in the layer too.
+ * Replaces an absorber set by fetd_set_absorber (and is replaced by one).
+ * fetd_fields_load restarts the auxiliary fluxes at zero.  FETD_E_ARG
+ * (nothing changed) if a sigma is negative or not finite or axis is not 0
+ * or 1. */
+fetd_status fetd_set_pml(fetd_sim *sim, const double *sigma_tri, int32_t axis);
 
 /* Load the self-consistent field state (Sec. II.A): b [nf] face fluxes
  * b^{n-1/2} [Wb/m] in triangle order, d [ne] edge fluxes d^n [C/m] in the

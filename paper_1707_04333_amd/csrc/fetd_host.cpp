@@ -98,6 +98,13 @@ struct fetd_sim {
     bool deterministic = false;
     void *d_rec = nullptr;
     double *d_bz_ext = nullptr, *d_e_ext = nullptr, *d_damp = nullptr, *d_damp_b = nullptr;
+    // uniaxial PML: rows (device edge ids), kappa, rows of the normal and
+    // tangential parts of [*eps], auxiliary fluxes, and psi - phi per edge
+    int pml_n = 0;
+    int32_t *d_pml_rows = nullptr, *d_pn_ptr = nullptr, *d_pn_col = nullptr;
+    int32_t *d_pt_ptr = nullptr, *d_pt_col = nullptr;
+    double *d_pml_kappa = nullptr, *d_pn_val = nullptr, *d_pt_val = nullptr;
+    double *d_pml_psi = nullptr, *d_pml_phi = nullptr, *d_pml_x = nullptr;
     bool has_affine = false;
     double e_scale = 1.0;  // multiplier of the applied edge field
     double affine[6] = {0, 0, 0, 0, 0, 0};
@@ -881,6 +888,18 @@ FieldDesc field_desc(const fetd_sim *s)
     d.damp = s->d_damp;
     d.fx = s->d_fx;
     d.fx_unscale = std::ldexp(1.0, fx_exponent(s) - 96);
+    d.pml_n = s->pml_n;
+    d.pml_rows = s->d_pml_rows;
+    d.pml_kappa = s->d_pml_kappa;
+    d.pn_ptr = s->d_pn_ptr;
+    d.pn_col = s->d_pn_col;
+    d.pn_val = s->d_pn_val;
+    d.pt_ptr = s->d_pt_ptr;
+    d.pt_col = s->d_pt_col;
+    d.pt_val = s->d_pt_val;
+    d.pml_psi = s->d_pml_psi;
+    d.pml_phi = s->d_pml_phi;
+    d.pml_x = s->pml_n > 0 ? s->d_pml_x : nullptr;
     d.sl_ptr = s->d_sl_ptr;
     d.sl_w = s->d_sl_w;
     d.sl_col = s->d_sl_col;
@@ -934,6 +953,71 @@ fetd_status download_field(fetd_sim *s, double *dst, const void *src, int64_t n,
     else
         std::copy(tmp.begin(), tmp.end(), dst);
     return FETD_OK;
+}
+
+// Release the uniaxial PML's device arrays (the layer's magnetic loss
+// d_damp_b stays, shared with the absorber; its owner clears it).
+void clear_pml(fetd_sim *s)
+{
+    for (void *p : {(void *)s->d_pml_rows, (void *)s->d_pn_ptr, (void *)s->d_pn_col,
+                    (void *)s->d_pt_ptr, (void *)s->d_pt_col, (void *)s->d_pml_kappa,
+                    (void *)s->d_pn_val, (void *)s->d_pt_val, (void *)s->d_pml_psi,
+                    (void *)s->d_pml_phi, (void *)s->d_pml_x})
+        s->dev_free(p);
+    s->d_pml_rows = s->d_pn_ptr = s->d_pn_col = s->d_pt_ptr = s->d_pt_col = nullptr;
+    s->d_pml_kappa = s->d_pn_val = s->d_pt_val = nullptr;
+    s->d_pml_psi = s->d_pml_phi = s->d_pml_x = nullptr;
+    s->pml_n = 0;
+}
+
+// Rows of the parts of [*eps] carried by the x (comp 0) or y (comp 1)
+// component of the Whitney 1-forms, eps0 int W_i,c W_j,c (Sec. II.A), for
+// the canonical edge rows listed; columns in increasing canonical order.
+void hodge_part_rows(const fetd_sim *s, int comp, const std::vector<int> &rows,
+                     std::vector<int32_t> &ptr, std::vector<int32_t> &col,
+                     std::vector<double> &val)
+{
+    std::vector<int> slot(s->ne, -1);
+    for (size_t k = 0; k < rows.size(); ++k) slot[rows[k]] = int(k);
+    std::vector<std::vector<std::pair<int, double>>> acc(rows.size());
+    for (int f = 0; f < s->nf; ++f) {
+        const double *g = &s->grad[6 * f];
+        const double A = s->area[f];
+        auto gd = [&](int p, int q) { return g[2 * p + comp] * g[2 * q + comp]; };
+        auto mass = [&](int p, int q) { return A * (p == q ? 2.0 : 1.0) / 12.0; };
+        for (int k = 0; k < 3; ++k) {
+            const int ek = s->tri_edge[3 * f + k];
+            if (slot[ek] < 0 || !s->edge_free[ek]) continue;
+            const int a = (k + 1) % 3, b = (k + 2) % 3;
+            for (int l = 0; l < 3; ++l) {
+                const int el = s->tri_edge[3 * f + l];
+                if (!s->edge_free[el]) continue;
+                const int cc = (l + 1) % 3, dd = (l + 2) % 3;
+                const double v = gd(b, dd) * mass(a, cc) - gd(b, cc) * mass(a, dd) -
+                                 gd(a, dd) * mass(b, cc) + gd(a, cc) * mass(b, dd);
+                acc[slot[ek]].push_back({el, s->eps0 * double(s->tri_sign[3 * f + k]) *
+                                                 double(s->tri_sign[3 * f + l]) * v});
+            }
+        }
+    }
+    ptr.assign(1, 0);
+    col.clear();
+    val.clear();
+    for (auto &r : acc) {
+        std::stable_sort(r.begin(), r.end(),
+                         [](const std::pair<int, double> &x, const std::pair<int, double> &y) {
+                             return x.first < y.first;
+                         });
+        for (size_t t = 0; t < r.size(); ++t) {
+            if (int(col.size()) > ptr.back() && col.back() == s->edev[r[t].first])
+                val.back() += r[t].second;
+            else {
+                col.push_back(s->edev[r[t].first]);
+                val.push_back(r[t].second);
+            }
+        }
+        ptr.push_back(int32_t(col.size()));
+    }
 }
 
 }  // namespace
@@ -1087,6 +1171,7 @@ fetd_status fetd_set_absorber(fetd_sim *s, const double *sigma_tri)
             if (!(sigma_tri[f] >= 0.0) || !std::isfinite(sigma_tri[f]))
                 return s->fail(FETD_E_ARG, "conductivity must be finite and >= 0");
     if (hipError_t e = hipStreamSynchronize(s->stream)) return s->hip_fail(e, "set_absorber");
+    clear_pml(s);
     s->node_gauss = s->node_free;
     ++s->desc_gen;
     if (!sigma_tri) {
@@ -1126,6 +1211,67 @@ fetd_status fetd_set_absorber(fetd_sim *s, const double *sigma_tri)
     return FETD_OK;
 }
 
+fetd_status fetd_set_pml(fetd_sim *s, const double *sigma_tri, int32_t axis)
+{
+    if (!s) return FETD_E_ARG;
+    if (axis != 0 && axis != 1) return s->fail(FETD_E_ARG, "axis must be 0 (x) or 1 (y)");
+    DeviceGuard g(s->device);
+    if (sigma_tri)
+        for (int f = 0; f < s->nf; ++f)
+            if (!(sigma_tri[f] >= 0.0) || !std::isfinite(sigma_tri[f]))
+                return s->fail(FETD_E_ARG, "conductivity must be finite and >= 0");
+    if (hipError_t e = hipStreamSynchronize(s->stream)) return s->hip_fail(e, "set_pml");
+    clear_pml(s);
+    s->dev_free(s->d_damp);
+    s->dev_free(s->d_damp_b);
+    s->d_damp = s->d_damp_b = nullptr;
+    s->node_gauss = s->node_free;  // d is updated without loss: Gauss holds everywhere
+    ++s->desc_gen;
+    if (!sigma_tri) return FETD_OK;
+    // the layer's rows: free edges whose conductivity (mean of their
+    // triangles) is positive; kappa = sigma / eps0
+    std::vector<int> rows;
+    std::vector<int32_t> drows;
+    std::vector<double> kappa;
+    for (int r = 0; r < s->ne; ++r) {
+        const int e = s->ecan[r];  // device order
+        if (!s->edge_free[e]) continue;
+        const int f0 = s->edge_f[2 * e], f1 = s->edge_f[2 * e + 1];
+        const double sg = f1 >= 0 ? 0.5 * (sigma_tri[f0] + sigma_tri[f1]) : sigma_tri[f0];
+        if (sg > 0.0) {
+            rows.push_back(e);
+            drows.push_back(r);
+            kappa.push_back(sg / s->eps0);
+        }
+    }
+    // matched magnetic loss on b (the stretched permeability mu0 s)
+    std::vector<double> damp_b(s->nf, 1.0);
+    for (int f = 0; f < s->nf; ++f) {
+        const double x = sigma_tri[f] * s->dt / (2.0 * s->eps0);
+        if (sigma_tri[f] > 0.0) damp_b[f] = (1.0 - x) / (1.0 + x);
+    }
+    fetd_status st = upload(s, &s->d_damp_b, damp_b.data(), damp_b.size());
+    if (st || rows.empty()) return st;
+    std::vector<int32_t> nptr, ncol, tptr, tcol;
+    std::vector<double> nval, tval;
+    hodge_part_rows(s, axis, rows, nptr, ncol, nval);
+    hodge_part_rows(s, 1 - axis, rows, tptr, tcol, tval);
+    const size_t n = rows.size();
+    if ((st = upload(s, &s->d_pml_rows, drows.data(), n))) return st;
+    if ((st = upload(s, &s->d_pml_kappa, kappa.data(), n))) return st;
+    if ((st = upload(s, &s->d_pn_ptr, nptr.data(), nptr.size()))) return st;
+    if ((st = upload(s, &s->d_pn_col, ncol.data(), ncol.size()))) return st;
+    if ((st = upload(s, &s->d_pn_val, nval.data(), nval.size()))) return st;
+    if ((st = upload(s, &s->d_pt_ptr, tptr.data(), tptr.size()))) return st;
+    if ((st = upload(s, &s->d_pt_col, tcol.data(), tcol.size()))) return st;
+    if ((st = upload(s, &s->d_pt_val, tval.data(), tval.size()))) return st;
+    if ((st = alloc_zero(s, &s->d_pml_psi, n))) return st;
+    if ((st = alloc_zero(s, &s->d_pml_phi, n))) return st;
+    if ((st = alloc_zero(s, &s->d_pml_x, size_t(s->ne)))) return st;
+    s->pml_n = int(n);
+    return FETD_OK;
+}
+
 fetd_status fetd_fields_load(fetd_sim *s, const double *b, const double *d)
 {
     if (!s) return FETD_E_ARG;
@@ -1137,6 +1283,19 @@ fetd_status fetd_fields_load(fetd_sim *s, const double *b, const double *d)
         for (int e = 0; e < s->ne; ++e)
             if (!std::isfinite(d[e])) return s->fail(FETD_E_ARG, "d must be finite");
     if (hipError_t e = hipStreamSynchronize(s->stream)) return s->hip_fail(e, "fields_load");
+    // the PML's auxiliary fluxes restart from zero with the loaded state
+    if (s->pml_n > 0) {
+        hipError_t e = launch_fill_u32(s->stream, reinterpret_cast<uint32_t *>(s->d_pml_psi), 0u,
+                                       2 * int64_t(s->pml_n));
+        if (e == hipSuccess)
+            e = launch_fill_u32(s->stream, reinterpret_cast<uint32_t *>(s->d_pml_phi), 0u,
+                                2 * int64_t(s->pml_n));
+        if (e == hipSuccess)
+            e = launch_fill_u32(s->stream, reinterpret_cast<uint32_t *>(s->d_pml_x), 0u,
+                                2 * int64_t(s->ne));
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return s->hip_fail(e, "fields_load pml");
+    }
     if (b) {
         std::vector<float> b32;
         const void *src = b;
@@ -1382,7 +1541,8 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
         if (e != hipSuccess) return s->hip_fail(e, "ampere");
         {
             fetd_sim::Timer t(s, 3);
-            e = launch_spmv(s->stream, fd);
+            if (s->pml_n > 0) e = launch_pml_aux(s->stream, fd);
+            if (e == hipSuccess) e = launch_spmv(s->stream, fd);
         }
         if (e != hipSuccess) return s->hip_fail(e, "spmv");
         if (s->probe_n > 0 && s->probe_samples < s->probe_max) {
@@ -1832,6 +1992,7 @@ struct fetd_batch {
     int nrun = 0, nseg = 0;
     uint32_t tri_blocks = 0, edge_blocks = 0, tiles = 0;
     FieldDesc *d_fields = nullptr;
+    std::vector<FieldDesc> pml_fields;        // runs with a PML (their auxiliary launches)
     uint32_t *d_tri_prefix = nullptr, *d_edge_prefix = nullptr, *d_seg_prefix = nullptr;
     SegDesc *d_segs[2] = {nullptr, nullptr};  // [parity of sorts since creation]
     uint32_t *d_queue = nullptr;              // tile queue of the particle launch: [next, done]
@@ -1887,9 +2048,11 @@ fetd_status batch_build(fetd_batch *b)
         int run, species;
     };
     std::vector<SegRef> refs;
+    b->pml_fields.clear();
     for (size_t r = 0; r < b->sims.size(); ++r) {
         fetd_sim *s = b->sims[r];
         fd.push_back(field_desc(s));
+        if (fd.back().pml_n > 0) b->pml_fields.push_back(fd.back());
         tp.push_back(tp.back() + uint32_t((s->nf + 255) / 256));
         ep.push_back(ep.back() + uint32_t((s->ne + 255) / 256));
         for (size_t k = 0; k < s->species.size(); ++k)
@@ -1957,6 +2120,8 @@ fetd_status batch_enqueue(fetd_batch *b, int n, int pusher)
         if (e == hipSuccess)
             e = launch_ampere_batched(b->stream, b->d_fields, b->d_edge_prefix, b->nrun,
                                       b->edge_blocks);
+        for (const FieldDesc &pf : b->pml_fields)
+            if (e == hipSuccess) e = launch_pml_aux(b->stream, pf);
         if (e == hipSuccess)
             e = launch_spmv_batched(b->stream, b->d_fields, b->d_edge_prefix, b->nrun,
                                     b->edge_blocks);
@@ -2356,6 +2521,8 @@ extern "C" fetd_status fetd_batch_step_noalloc(fetd_sim *const *sims, int32_t n,
             e = launch_particles_batched(stream, d_segs[parity], d_sp, nseg, tiles, d_queue, pusher,
                                          s0->fp32(), s0->deterministic);
         if (e == hipSuccess) e = launch_ampere_batched(stream, d_fields, d_ep, n, edge_blocks);
+        for (int32_t r = 0; r < n && e == hipSuccess; ++r)
+            if (h.fields[r].pml_n > 0) e = launch_pml_aux(stream, h.fields[r]);
         if (e == hipSuccess) e = launch_spmv_batched(stream, d_fields, d_ep, n, edge_blocks);
         if (e != hipSuccess) {
             g_last_error = std::string("fetd_batch_step_noalloc: ") + hipGetErrorString(e);

@@ -100,6 +100,19 @@ struct FieldDesc {
     const double *damp;
     unsigned long long *fx;  // deterministic mode: fixed-point current limbs, else null
     double fx_unscale;       // 2^(E - 96)
+    // uniaxial PML (pml_n rows, else 0): device edge id and kappa = sigma/eps0
+    // per row, the rows of the normal (pn) and tangential (pt) parts of
+    // [*eps] (CSR, device edge columns), the auxiliary fluxes psi, phi per
+    // row, and pml_x = psi - phi per edge (zero off the layer; null without
+    // a PML), which the SpMV adds to d
+    int pml_n;
+    const int32_t *pml_rows;
+    const double *pml_kappa;
+    const int32_t *pn_ptr, *pn_col;
+    const double *pn_val;
+    const int32_t *pt_ptr, *pt_col;
+    const double *pt_val;
+    double *pml_psi, *pml_phi, *pml_x;
     const int32_t *sl_ptr;
     const int32_t *sl_w;
     const int32_t *sl_col;
@@ -111,6 +124,8 @@ struct FieldDesc {
 hipError_t launch_faraday(hipStream_t s, const FieldDesc &d);
 hipError_t launch_ampere(hipStream_t s, const FieldDesc &d);
 hipError_t launch_spmv(hipStream_t s, const FieldDesc &d);
+// PML auxiliary fluxes from the current e (before the SpMV of the step).
+hipError_t launch_pml_aux(hipStream_t s, const FieldDesc &d);
 
 // Particle stage (fetd_particles.hip, one object per precision).  A
 // deterministic launch is selected by a.fx != null (batched: det).

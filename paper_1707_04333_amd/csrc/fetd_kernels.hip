@@ -204,11 +204,46 @@ __device__ __forceinline__ void spmv_row(int row, const FieldDesc &d)
     const int sl = row / kSlice, ln = row % kSlice;
     const int base = d.sl_ptr[sl], w = d.sl_w[sl];
     double acc = 0.0;
-    for (int j = 0; j < w; ++j) {
-        const int q = base + j * kSlice + ln;
-        acc += fget<FT>(d.sl_val, q) * d.d[d.sl_col[q]];
+    if (d.pml_x) {
+        // e = M~ (d + psi - phi) with the PML's auxiliary fluxes
+        for (int j = 0; j < w; ++j) {
+            const int q = base + j * kSlice + ln;
+            const int c = d.sl_col[q];
+            acc += fget<FT>(d.sl_val, q) * (d.d[c] + d.pml_x[c]);
+        }
+    } else {
+        for (int j = 0; j < w; ++j) {
+            const int q = base + j * kSlice + ln;
+            acc += fget<FT>(d.sl_val, q) * d.d[d.sl_col[q]];
+        }
     }
     fset<FT>(d.e_out, row, acc);
+}
+
+// Uniaxial PML along the layer normal n (stretching s = 1 + sigma/(j w
+// eps0); permittivity eps0 diag(1/s, s) in (n, t)): per layer row k, from
+// the current e, X = (M_n e)_k and Y = (M_t e)_k, then
+//   psi <- (psi (1 - c/2) + c X) / (1 + c/2),  phi <- phi + c Y,
+// c = kappa dt, and the SpMV takes e = M~ (d + psi - phi).
+template <typename FT>
+__device__ __forceinline__ void pml_row(int k, const FieldDesc &d)
+{
+    double x = 0.0, y = 0.0;
+    for (int j = d.pn_ptr[k]; j < d.pn_ptr[k + 1]; ++j) x += d.pn_val[j] * fget<FT>(d.e, d.pn_col[j]);
+    for (int j = d.pt_ptr[k]; j < d.pt_ptr[k + 1]; ++j) y += d.pt_val[j] * fget<FT>(d.e, d.pt_col[j]);
+    const double c = d.pml_kappa[k] * d.dt;
+    const double psi = (d.pml_psi[k] * (1.0 - 0.5 * c) + c * x) / (1.0 + 0.5 * c);
+    const double phi = d.pml_phi[k] + c * y;
+    d.pml_psi[k] = psi;
+    d.pml_phi[k] = phi;
+    d.pml_x[d.pml_rows[k]] = psi - phi;
+}
+
+template <typename FT>
+__global__ __launch_bounds__(256) void k_pml_aux(FieldDesc d)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < d.pml_n) pml_row<FT>(k, d);
 }
 
 template <typename FT>
@@ -598,6 +633,14 @@ hipError_t launch_spmv(hipStream_t s, const FieldDesc &d)
     if (d.ne <= 0) return hipSuccess;
     if (d.field32) FETD_LAUNCH(k_spmv<float>, dim3(grid_for(d.ne, 256)), dim3(256), 0, s, d);
     else FETD_LAUNCH(k_spmv<double>, dim3(grid_for(d.ne, 256)), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_pml_aux(hipStream_t s, const FieldDesc &d)
+{
+    if (d.pml_n <= 0) return hipSuccess;
+    if (d.field32) FETD_LAUNCH(k_pml_aux<float>, dim3(grid_for(d.pml_n, 256)), dim3(256), 0, s, d);
+    else FETD_LAUNCH(k_pml_aux<double>, dim3(grid_for(d.pml_n, 256)), dim3(256), 0, s, d);
     return hipGetLastError();
 }
 

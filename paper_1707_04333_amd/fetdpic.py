@@ -103,10 +103,11 @@ def lib():
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32],
                     "fetd_batch_stats": [P, P, P, P],
+                    "fetd_copy_ceiling": [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P],
                     "fetd_batch_step_noalloc": [P, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.c_int32],
-                    "fetd_copy_ceiling": [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P],
                     "fetd_set_absorber": [P, P],
+                    "fetd_set_pml": [P, P, ctypes.c_int32],
                     "fetd_set_ext_scale": [P, ctypes.c_double],
                     "fetd_probe_set": [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int64],
                     "fetd_probe_get": [P, P, ctypes.c_int64, P],
@@ -206,6 +207,11 @@ def fields_set(h, bz_ext=None, e_ext=None, e_affine=None):
 def set_absorber(h, sigma_tri):
     sg = None if sigma_tri is None else np.ascontiguousarray(sigma_tri, dtype=np.float64)
     _check(lib().fetd_set_absorber(h, _p(sg)), h)
+
+
+def set_pml(h, sigma_tri, axis=0):
+    sg = None if sigma_tri is None else np.ascontiguousarray(sigma_tri, dtype=np.float64)
+    _check(lib().fetd_set_pml(h, _p(sg), int(axis)), h)
 
 
 def fields_load(h, b=None, d=None):
@@ -382,6 +388,9 @@ class Sim:
 
     def set_absorber(self, sigma_tri):
         set_absorber(self.h, sigma_tri)
+
+    def set_pml(self, sigma_tri, axis=0):
+        set_pml(self.h, sigma_tri, axis)
 
     def set_ext_scale(self, scale):
         set_ext_scale(self.h, scale)
