@@ -48,6 +48,11 @@ HBM_PEAK_GBS = 8000.0
 DEFAULT_PAIRS = 8_000_000
 KERNEL_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd_particles.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particle_step_large_graded_traffic.json")
+ISSUE_FILE = os.path.join(ROOT, "profiles", "k_particle_step_large_graded_issue.json")
+# VALU issue ceiling: 256 CUs x 4 SIMDs, one wavefront-instruction (64 lanes
+# on a 16-lane SIMD: 4 cycles) per SIMD every 4 cycles at the 2.4 GHz peak
+# engine clock.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 PAIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particle_step_pair_plasma_traffic.json")
 KERNEL3_SRC = os.path.join(ROOT, "paper_1707_04333_amd", "csrc", "fetd3_kernels.hip")
 TRAFFIC3_FILE = os.path.join(ROOT, "profiles", "k3_particles_tet_pair_plasma_traffic.json")
@@ -89,6 +94,19 @@ def measured_traffic(precision, traffic_file=TRAFFIC_FILE, src=KERNEL_SRC):
     if rec.get("kernel_sha256_16") != kernel_hash(src):
         return None
     return rec.get(precision, {}).get("hbm_bytes_per_launch")
+
+
+def measured_valu(precision, issue_file=ISSUE_FILE, src=KERNEL_SRC):
+    """VALU instructions (wavefront instructions) per particle launch from
+    the committed SQ counter runs, or None when the kernel source changed
+    since they were taken."""
+    try:
+        rec = json.load(open(issue_file))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256_16") != kernel_hash(src):
+        return None
+    return rec.get(precision, {}).get("valu_per_launch")
 
 
 def host_info():
@@ -175,7 +193,7 @@ def run_gpu(w, precision, steps, warmup, pusher, resort=None):
                 sorts_timed=int(math.ceil(steps / resort)))
 
 
-def leg_record(r, n_p, steps, species_n, fp32, traffic=None):
+def leg_record(r, n_p, steps, species_n, fp32, traffic=None, valu=None):
     """JSON record of one precision leg: throughput, the particle kernel's
     algorithmic bandwidth, the per-stage breakdown and the Gauss residual."""
     nf, ne = r["info"]["n_tris"], r["info"]["n_edges"]
@@ -190,6 +208,9 @@ def leg_record(r, n_p, steps, species_n, fp32, traffic=None):
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "traffic": traffic, "avg_launch_ms": avg_s * 1e3,
                          "algorithmic_bytes_per_launch": per_launch},
+            "valu_issue": None if valu is None else {
+                "instr_per_launch": valu, "peak_per_s": VALU_ISSUE_PEAK,
+                "frac": valu / avg_s / VALU_ISSUE_PEAK},
             "stage_ms_per_step": {k: v[0] / r["stage_steps"] for k, v in r["stages"].items()},
             "hbm_gbs_step": sum(particle_launch_bytes(n, nf, ne, fp32) for n in species_n)
             / (r["elapsed"] / steps) / 1e9}
@@ -546,13 +567,16 @@ def run_workload(name, args, pusher=None, resort=None):
         (name == "pair" and args.pairs == DEFAULT_PAIRS)
     tfile = TRAFFIC_FILE if name == "large" else PAIR_TRAFFIC_FILE
     r64 = run_gpu(w, "fp64", args.steps, args.warmup, pusher, resort)
+    issue = counted and name == "large"
     rec = {"fp64": leg_record(r64, n_p, args.steps, species_n, False,
-                              measured_traffic("fp64", tfile) if counted else None)}
+                              measured_traffic("fp64", tfile) if counted else None,
+                              measured_valu("fp64") if issue else None)}
     if not args.no_mixed:
         for prec in ("mixed", "mixed_f64field"):
             r = run_gpu(w, prec, args.steps, args.warmup, pusher, resort or r64["resort"])
             rec[prec] = leg_record(r, n_p, args.steps, species_n, True,
-                                   measured_traffic(prec, tfile) if counted else None)
+                                   measured_traffic(prec, tfile) if counted else None,
+                                   measured_valu(prec) if issue else None)
             rec[prec]["vs_fp64"] = rec[prec]["value"] / rec["fp64"]["value"]
     cfg = workload_config(name, w, r64["info"], pusher, r64["resort"], args)
     return w, cfg, rec, r64
@@ -605,6 +629,9 @@ def main():
         return
     if args.workload == "tet":
         print(json.dumps(run_tet(args)))
+        return
+    if args.workload == "batched":
+        print(json.dumps(run_batched("boris")))
         return
     name = args.workload
     log(f"generating workload {name}")

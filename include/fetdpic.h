@@ -303,16 +303,35 @@ fetd_status fetd_profile_mask(fetd_sim *sim, int32_t stage_mask, int32_t every);
 #define FETD_N_STAGES 5
 fetd_status fetd_stage_times(fetd_sim *sim, double *ms, int64_t *launches);
 
-/* Autotune the re-sort cadence: sort now, advance trial_steps real PIC
- * steps with the given pusher while timing the particle stage of every step
- * and the sort with HIP events, then set the re-sort interval K that
- * minimises (T_sort + sum_{j<K} T_particles(j)) / K over the candidates
- * 5, 10, 20, 40, 80, 160 (up to trial_steps).  *chosen gets K; cost_ms
- * ([6] or NULL) gets that cost per step in ms for each candidate, -1 for
- * candidates beyond trial_steps.  The trial steps are ordinary steps: the
- * simulation advances by trial_steps steps. */
-fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps, int32_t *chosen,
-                          double *cost_ms);
+/* Autotune the particle tiling and the re-sort cadence (the tuning the
+ * method leaves to the implementation: how many particles a block of the
+ * particle kernel takes, and how often the triangle order is restored).
+ * 1. Tile: for each tile size (512, 1024, 2048 particles per block of 256
+ *    threads; the current one first) sort, then run min(trial_steps, 20)
+ *    steps timing the particle stage with HIP events; keep the tile of
+ *    least mean particle-stage time (ties keep the earlier candidate).
+ * 2. Cadence: with that tile, sort once (timed), advance trial_steps steps
+ *    timing the particle stage of every step, and set the re-sort interval
+ *    K minimising (T_sort + sum_{j<K} T_particles(j)) / K over the
+ *    candidates 5, 10, 20, 40, 80, 160 (up to trial_steps).
+ * *resort_every gets K and *tile_particles the tile (either may be NULL);
+ * cost_ms ([6] or NULL) gets the cost per step in ms of every K candidate
+ * (-1 beyond trial_steps), tile_cost_ms ([3] or NULL) the mean
+ * particle-stage ms per step of tiles 512, 1024, 2048.  Every trial step is
+ * an ordinary step: the simulation advances by 3 min(trial_steps, 20) +
+ * trial_steps steps, and its results do not depend on the choices beyond
+ * FP64 summation order (not at all in deterministic mode). */
+fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps,
+                          int32_t *resort_every, double *cost_ms, int32_t *tile_particles,
+                          double *tile_cost_ms);
+
+/* Particles per block of the single-run particle kernel: 512, 1024 (the
+ * default) or 2048, else FETD_E_ARG.  Takes effect at the next step (the
+ * tiles' current-window homes are recomputed from the current order).  Runs
+ * stepped in a batch use 1024: fetd_batch_create and
+ * fetd_batch_step_noalloc set it on their members. */
+fetd_status fetd_set_tile(fetd_sim *sim, int32_t tile_particles);
+fetd_status fetd_get_tile(fetd_sim *sim, int32_t *tile_particles);
 
 /* Set the re-sort interval directly (k >= 1). */
 fetd_status fetd_set_resort(fetd_sim *sim, int32_t every);

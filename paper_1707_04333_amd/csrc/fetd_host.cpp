@@ -45,7 +45,14 @@ struct Species {
     int64_t bc_offset = 0; // first per-tile counter slot (pairs) of the species
 };
 
-int64_t tiles_of(int64_t n) { return (n + int64_t(kBlock) * kPPT - 1) / (int64_t(kBlock) * kPPT); }
+// Tiles of n particles at ppt particles per thread (default: the batched
+// kernel's), and per-tile slots reserved per species (for the smallest tile
+// any single-run launch may use).
+int64_t tiles_of(int64_t n, int ppt = kPPT)
+{
+    return (n + int64_t(kBlock) * ppt - 1) / (int64_t(kBlock) * ppt);
+}
+int64_t slots_of(int64_t n) { return tiles_of(n, kMinPPT); }
 
 }  // namespace
 
@@ -121,6 +128,7 @@ struct fetd_sim {
     unsigned long long *d_counters = nullptr;
     unsigned long long *d_block_counts = nullptr;
     uint32_t *d_tile_home = nullptr;  // per tile, same slots as d_block_counts
+    int ppt = kPPT;                   // particles per thread of single-run particle launches
     int64_t block_count_cap = 0;  // blocks covered by d_block_counts
     double *d_q = nullptr, *d_divd = nullptr, *d_partial = nullptr;
     // field probes
@@ -692,8 +700,8 @@ fetd_status grow_block_counts(fetd_sim *s, int64_t extra)
 {
     // per-tile counter pairs: one region per species, the new one appended
     int64_t used = 0;
-    for (const Species &sp : s->species) used = std::max(used, sp.bc_offset + tiles_of(sp.n));
-    const int64_t need = used + tiles_of(extra) + 1;
+    for (const Species &sp : s->species) used = std::max(used, sp.bc_offset + slots_of(sp.n));
+    const int64_t need = used + slots_of(extra) + 1;
     if (need > s->block_count_cap) {
         std::vector<unsigned long long> old(2 * size_t(need), 0ull);
         std::vector<uint32_t> home(size_t(need), 0u);
@@ -786,12 +794,30 @@ fetd_status sort_all(fetd_sim *s, hipStream_t stream)
         a.block_sums = s->d_block_sums;
         a.elem_bytes = int(2 * rb);
         a.tile_home = s->d_tile_home + sp.bc_offset;
+        a.tile = int64_t(s->ppt) * kBlock;
         // launch_sort fills key_out with the lost key first (slots past the alive count)
         hipError_t e = launch_sort(stream, a);
         if (e != hipSuccess) return s->hip_fail(e, "sort");
     }
     s->pbuf = ob;
     s->steps_since_sort = 0;
+    return FETD_OK;
+}
+
+// Switch the single-run particle launches to ppt particles per thread and
+// recompute every tile's home triangle for the new tiling from the current
+// particle order, on the simulation's stream (no allocation).
+fetd_status set_ppt(fetd_sim *s, int ppt)
+{
+    if (!valid_ppt(ppt)) return s->fail(FETD_E_ARG, "invalid tile size");
+    if (ppt == s->ppt) return FETD_OK;
+    s->ppt = ppt;
+    for (const Species &sp : s->species) {
+        if (sp.n == 0) continue;
+        hipError_t e = launch_tile_home(s->stream, sp.n, s->d_key[s->pbuf] + sp.offset,
+                                        s->d_tile_home + sp.bc_offset, int64_t(ppt) * kBlock);
+        if (e != hipSuccess) return s->hip_fail(e, "tile homes");
+    }
     return FETD_OK;
 }
 
@@ -1349,7 +1375,7 @@ fetd_status fetd_particles_load_bary(fetd_sim *s, double q, double m, double w, 
     sp.n = n;
     sp.offset = s->species.empty() ? 0 : s->species.back().offset + s->species.back().n;
     sp.bc_offset = s->species.empty() ? 0 :
-        s->species.back().bc_offset + tiles_of(s->species.back().n);
+        s->species.back().bc_offset + slots_of(s->species.back().n);
     const size_t rb = s->real_bytes();
     std::vector<uint32_t> key(n);
     std::vector<int32_t> pid(n);
@@ -1531,7 +1557,7 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
         for (const Species &sp : s->species) {
             const StepArgs a = step_args(s, sp, s->pbuf);
             fetd_sim::Timer t(s, 1);
-            e = launch_particles(s->stream, mv, a, pusher, s->fp32());
+            e = launch_particles(s->stream, mv, a, pusher, s->fp32(), s->ppt);
             if (e != hipSuccess) return s->hip_fail(e, "particle step");
         }
         {
@@ -1856,8 +1882,31 @@ fetd_status fetd_set_resort(fetd_sim *s, int32_t every)
     return FETD_OK;
 }
 
-fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int32_t *chosen,
-                          double *cost_ms)
+// Particle-stage milliseconds of each of the last `steps` steps (the
+// events of stage 1, one launch per species and step), from a run of
+// `steps` steps with re-sorting off.
+static fetd_status timed_particle_steps(fetd_sim *s, int32_t pusher, int32_t steps,
+                                        std::vector<double> &tp)
+{
+    const int nsp = int(std::count_if(s->species.begin(), s->species.end(),
+                                      [](const Species &x) { return x.n > 0; }));
+    tp.assign(size_t(steps), 0.0);
+    fetd_status st;
+    if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4), 1))) return st;
+    if ((st = fetd_pic_step(s, steps, pusher))) return st;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "autotune");
+    const auto &ev = s->timed[1];
+    for (size_t k = 0; k < ev.size(); ++k) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[k].first, ev[k].second) == hipSuccess && nsp > 0)
+            tp[std::min<size_t>(k / nsp, size_t(steps) - 1)] += double(t);
+    }
+    return FETD_OK;
+}
+
+fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int32_t *resort_every,
+                          double *cost_ms, int32_t *tile_particles, double *tile_cost_ms)
 {
     if (!s || trial_steps < 2 || pusher < 0 || pusher > 3) return FETD_E_ARG;
     DeviceGuard g(s->device);
@@ -1865,7 +1914,36 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     const int32_t was_mask = int32_t(s->profile_mask);
     const int32_t was_every = int32_t(s->profile_every);
     const int saved = s->resort_every;
-    // one timed sort
+    s->resort_every = std::numeric_limits<int>::max();
+    std::vector<double> tp;
+
+    // 1. Tile size: each candidate runs min(trial_steps, 20) steps from a
+    //    fresh sort; the one of least mean particle-stage time is kept (the
+    //    current one first, so a tie keeps it).
+    const int tile_steps = std::min<int32_t>(trial_steps, 20);
+    int order[3] = {s->ppt, 0, 0};
+    for (int k = 0, j = 1; k < 3; ++k)
+        if (kPPTChoices[k] != s->ppt) order[j++] = kPPTChoices[k];
+    int best_ppt = s->ppt;
+    double best_tile = std::numeric_limits<double>::max();
+    for (int c : order) {
+        if ((st = set_ppt(s, c))) return st;
+        if ((st = sort_all(s, s->stream))) return st;
+        if ((st = timed_particle_steps(s, pusher, tile_steps, tp))) return st;
+        double sum = 0.0;
+        for (double t : tp) sum += t;
+        const double cost = sum / tile_steps;
+        for (int k = 0; k < 3; ++k)
+            if (kPPTChoices[k] == c && tile_cost_ms) tile_cost_ms[k] = cost;
+        if (cost < best_tile) {
+            best_tile = cost;
+            best_ppt = c;
+        }
+    }
+    if ((st = set_ppt(s, best_ppt))) return st;
+
+    // 2. Re-sort cadence with that tile: one timed sort, then the particle
+    //    stage of every step as the order decays.
     if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4), 1))) return st;
     {
         fetd_sim::Timer t(s, 4);
@@ -1875,21 +1953,7 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     int64_t n[FETD_N_STAGES];
     if ((st = fetd_stage_times(s, ms, n))) return st;
     const double t_sort = ms[4];
-    // particle-stage time per step as the order decays after the sort
-    s->resort_every = std::numeric_limits<int>::max();
-    const int nsp = int(std::count_if(s->species.begin(), s->species.end(),
-                                      [](const Species &x) { return x.n > 0; }));
-    std::vector<double> tp(trial_steps, 0.0);
-    if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4), 1))) return st;
-    if ((st = fetd_pic_step(s, trial_steps, pusher))) return st;
-    hipError_t e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return s->hip_fail(e, "autotune");
-    const auto &ev = s->timed[1];
-    for (size_t k = 0; k < ev.size(); ++k) {
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, ev[k].first, ev[k].second) == hipSuccess && nsp > 0)
-            tp[std::min<size_t>(k / nsp, size_t(trial_steps) - 1)] += double(t);
-    }
+    if ((st = timed_particle_steps(s, pusher, trial_steps, tp))) return st;
     int best = saved;
     double best_cost = std::numeric_limits<double>::max();
     int ci = 0;
@@ -1910,7 +1974,24 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     s->resort_every = best;
     s->steps_since_sort = trial_steps;  // the order has decayed: sort at the next step
     if ((st = fetd_profile_mask(s, was_mask, was_every))) return st;
-    if (chosen) *chosen = best;
+    if (resort_every) *resort_every = best;
+    if (tile_particles) *tile_particles = best_ppt * kBlock;
+    return FETD_OK;
+}
+
+fetd_status fetd_set_tile(fetd_sim *s, int32_t tile_particles)
+{
+    if (!s) return FETD_E_ARG;
+    if (tile_particles % kBlock != 0 || !valid_ppt(tile_particles / kBlock))
+        return s->fail(FETD_E_ARG, "tile_particles must be 512, 1024 or 2048");
+    DeviceGuard g(s->device);
+    return set_ppt(s, tile_particles / kBlock);
+}
+
+fetd_status fetd_get_tile(fetd_sim *s, int32_t *tile_particles)
+{
+    if (!s || !tile_particles) return FETD_E_ARG;
+    *tile_particles = s->ppt * kBlock;
     return FETD_OK;
 }
 
@@ -2252,13 +2333,20 @@ fetd_status fetd_batch_create(fetd_sim *const *sims, int32_t n, int32_t use_grap
         g_last_error = "batch stream";
         return FETD_E_HIP;
     }
-    for (fetd_sim *s : b->sims)
+    for (fetd_sim *s : b->sims) {
         if (!s->have_baseline)
             if (fetd_status st = take_baseline(s)) {
                 g_last_error = s->err;
                 fetd_batch_destroy(b);
                 return st;
             }
+        // the batched kernel tiles every run by the default tile
+        if (fetd_status st = set_ppt(s, kPPT)) {
+            g_last_error = s->err;
+            fetd_batch_destroy(b);
+            return st;
+        }
+    }
     if (hipStreamSynchronize(b->member_stream) != hipSuccess) {
         fetd_batch_destroy(b);
         g_last_error = "member stream";
@@ -2428,6 +2516,11 @@ extern "C" fetd_status fetd_batch_step_noalloc(fetd_sim *const *sims, int32_t n,
     }
     if (n_steps == 0) return FETD_OK;
     DeviceGuard g(s0->device);
+    for (int32_t i = 0; i < n; ++i)
+        if (fetd_status st = set_ppt(sims[i], kPPT)) {  // the batched kernel's tile
+            g_last_error = sims[i]->err;
+            return st;
+        }
     std::lock_guard<std::mutex> lock(g_noalloc_mu);
     char *base = nullptr;
     if (hipError_t e = scratch_address(s0->device, &base)) {

@@ -14,7 +14,14 @@ constexpr int kBlock = 256;                // threads per block of the particle 
 #ifndef FETD_PPT
 #define FETD_PPT 4
 #endif
-constexpr int kPPT = FETD_PPT;             // particles per thread of the particle kernel
+constexpr int kPPT = FETD_PPT;             // particles per thread of the particle kernel (default;
+                                           // also the batched kernel's)
+// Particles per thread the single-run particle kernel is compiled for (the
+// tile of a block is ppt * kBlock particles); per-tile slots are sized for
+// the smallest.
+constexpr int kPPTChoices[3] = {2, 4, 8};
+constexpr int kMinPPT = 2;
+inline bool valid_ppt(int p) { return p == 2 || p == 4 || p == 8; }
 constexpr int kSlice = 64;                 // rows per SELL slice of the SpMV
 
 // Per-triangle tables (device).
@@ -128,9 +135,12 @@ hipError_t launch_spmv(hipStream_t s, const FieldDesc &d);
 hipError_t launch_pml_aux(hipStream_t s, const FieldDesc &d);
 
 // Particle stage (fetd_particles.hip, one object per precision).  A
-// deterministic launch is selected by a.fx != null (batched: det).
-hipError_t launch_particles_f32(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher);
-hipError_t launch_particles_f64(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher);
+// deterministic launch is selected by a.fx != null (batched: det); ppt is
+// one of kPPTChoices.
+hipError_t launch_particles_f32(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
+                                int ppt);
+hipError_t launch_particles_f64(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
+                                int ppt);
 // Batched: queue = [next tile, blocks done], zero before the first launch;
 // the kernel's last block leaves it at zero again.
 hipError_t launch_particles_batched_f32(hipStream_t s, const SegDesc *segs, const uint32_t *prefix,
@@ -140,9 +150,10 @@ hipError_t launch_particles_batched_f64(hipStream_t s, const SegDesc *segs, cons
                                         int nseg, uint32_t total_tiles, uint32_t *queue,
                                         int pusher, bool det);
 inline hipError_t launch_particles(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
-                                   bool fp32)
+                                   bool fp32, int ppt)
 {
-    return fp32 ? launch_particles_f32(s, m, a, pusher) : launch_particles_f64(s, m, a, pusher);
+    return fp32 ? launch_particles_f32(s, m, a, pusher, ppt)
+                : launch_particles_f64(s, m, a, pusher, ppt);
 }
 inline hipError_t launch_particles_batched(hipStream_t s, const SegDesc *segs,
                                            const uint32_t *prefix, int nseg, uint32_t total_tiles,
@@ -177,8 +188,12 @@ struct SortArgs {
     int32_t *block_sums;
     int elem_bytes;    // 8 (float2) or 16 (double2)
     uint32_t *tile_home;  // [tiles of n]: triangle of each tile's first particle after the sort
+    int64_t tile;         // particles per tile of the particle kernel
 };
 hipError_t launch_sort(hipStream_t s, const SortArgs &a);
+// tile_home of n keys in their current order, tiles of `tile` particles.
+hipError_t launch_tile_home(hipStream_t s, int64_t n, const uint32_t *key, uint32_t *home,
+                            int64_t tile);
 
 // Batched launches over many runs (one launch per phase).
 hipError_t launch_faraday_batched(hipStream_t s, const FieldDesc *d, const uint32_t *prefix,

@@ -306,7 +306,7 @@ constexpr uint32_t kSortBack = 256;
 __device__ __forceinline__ uint32_t sort_window(const SortArgs &a, int64_t blk)
 {
     if (!a.tile_home) return 0u;
-    const uint32_t h = a.tile_home[(blk * kSortB) / (kPPT * kBlock)];
+    const uint32_t h = a.tile_home[(blk * kSortB) / a.tile];
     return h > kSortBack ? h - kSortBack : 0u;
 }
 
@@ -477,11 +477,12 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs a)
 
 // Home triangle of every tile of the sorted segment (its first particle).
 __global__ __launch_bounds__(256) void k_tile_home(int64_t n, const uint32_t *__restrict__ key,
-                                                   uint32_t *__restrict__ home, int64_t tiles)
+                                                   uint32_t *__restrict__ home, int64_t tiles,
+                                                   int64_t tile)
 {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= tiles) return;
-    const int64_t i = t * int64_t(kPPT * kBlock);
+    const int64_t i = t * tile;
     const uint32_t k = i < n ? key[i] : kLost;
     home[t] = k == kLost ? 0u : (k & kTriMask);
 }
@@ -690,10 +691,20 @@ hipError_t launch_sort(hipStream_t s, const SortArgs &a)
                                s, a);
     }
     if (a.tile_home && a.n > 0) {
-        const int64_t tiles = (a.n + int64_t(kPPT * kBlock) - 1) / int64_t(kPPT * kBlock);
-        hipLaunchKernelGGL(k_tile_home, dim3(grid_for(tiles, 256)), dim3(256), 0, s, a.n,
-                           a.key_out, a.tile_home, tiles);
+        err = launch_tile_home(s, a.n, a.key_out, a.tile_home, a.tile);
+        if (err != hipSuccess) return err;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_home(hipStream_t s, int64_t n, const uint32_t *key, uint32_t *home,
+                            int64_t tile)
+{
+    if (n <= 0) return hipSuccess;
+    if (tile < kBlock) return hipErrorInvalidValue;
+    const int64_t tiles = (n + tile - 1) / tile;
+    hipLaunchKernelGGL(k_tile_home, dim3(grid_for(tiles, 256)), dim3(256), 0, s, n, key, home,
+                       tiles, tile);
     return hipGetLastError();
 }
 

@@ -98,7 +98,9 @@ def lib():
         L.fetd_last_error.restype = ctypes.c_char_p
         optional = {"fetd_profile": [P, ctypes.c_int32], "fetd_stage_times": [P, P, P],
                     "fetd_profile_mask": [P, ctypes.c_int32, ctypes.c_int32],
-                    "fetd_autotune": [P, ctypes.c_int32, ctypes.c_int32, P, P],
+                    "fetd_autotune": [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P],
+                    "fetd_set_tile": [P, ctypes.c_int32],
+                    "fetd_get_tile": [P, P],
                     "fetd_set_resort": [P, ctypes.c_int32],
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32],
@@ -314,18 +316,36 @@ STAGES = ("faraday", "particles", "ampere", "spmv", "sort")
 
 
 AUTOTUNE_CANDIDATES = (5, 10, 20, 40, 80, 160)
+TILE_CANDIDATES = (512, 1024, 2048)
 
 
 def autotune(h, pusher="boris", trial_steps=160, with_costs=False):
-    """fetd_autotune: the chosen re-sort interval (and, with_costs, the
-    measured cost per step in ms of every candidate tried)."""
+    """fetd_autotune: tunes the tile size, then the re-sort interval.
+    Returns the chosen re-sort interval; with_costs, a dict with it
+    ("resort_every"), the chosen tile ("tile"), and the measured cost in ms
+    per step of every candidate tried ("costs", "tile_costs")."""
     pid = PUSHERS[pusher] if isinstance(pusher, str) else int(pusher)
-    out = ctypes.c_int32()
+    k = ctypes.c_int32()
+    tile = ctypes.c_int32()
     costs = np.zeros(len(AUTOTUNE_CANDIDATES))
-    _check(lib().fetd_autotune(h, pid, int(trial_steps), ctypes.byref(out), _p(costs)), h)
+    tcosts = np.zeros(len(TILE_CANDIDATES))
+    _check(lib().fetd_autotune(h, pid, int(trial_steps), ctypes.byref(k), _p(costs),
+                               ctypes.byref(tile), _p(tcosts)), h)
     if not with_costs:
-        return out.value
-    return out.value, {k: float(c) for k, c in zip(AUTOTUNE_CANDIDATES, costs) if c >= 0}
+        return k.value
+    return {"resort_every": k.value, "tile": tile.value,
+            "costs": {c: float(v) for c, v in zip(AUTOTUNE_CANDIDATES, costs) if v >= 0},
+            "tile_costs": {c: float(v) for c, v in zip(TILE_CANDIDATES, tcosts)}}
+
+
+def set_tile(h, tile_particles):
+    _check(lib().fetd_set_tile(h, int(tile_particles)), h)
+
+
+def get_tile(h):
+    out = ctypes.c_int32()
+    _check(lib().fetd_get_tile(h, ctypes.byref(out)), h)
+    return out.value
 
 
 def set_resort(h, every):
@@ -440,6 +460,12 @@ class Sim:
 
     def set_resort(self, every):
         set_resort(self.h, every)
+
+    def set_tile(self, tile_particles):
+        set_tile(self.h, tile_particles)
+
+    def get_tile(self):
+        return get_tile(self.h)
 
     def stage_times(self):
         return stage_times(self.h)

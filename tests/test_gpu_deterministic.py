@@ -129,21 +129,46 @@ def test_deterministic_save_and_resume():
 
 
 def test_autotune_returns_argmin_and_keeps_the_run():
-    """fetd_autotune picks the candidate interval of least measured cost
-    per step, and its trial steps are ordinary steps of the run."""
+    """fetd_autotune picks the tile and then the re-sort interval of least
+    measured cost, and its trial steps are ordinary steps of the run: in
+    deterministic mode the state equals, bit for bit, that of a plain run of
+    as many steps (3 x 20 tile trials + 40 cadence trials)."""
     fp = _fp()
     w = _wl(n_side=24, length=0.038, n_pairs=40_000)
     tuned = fp.from_workload(w, spai_level=1, deterministic=True)
     plain = fp.from_workload(w, spai_level=1, deterministic=True)
-    k, costs = tuned.autotune("boris", trial_steps=40, with_costs=True)
+    r = tuned.autotune("boris", trial_steps=40, with_costs=True)
     cands = [c for c in (5, 10, 20, 40, 80, 160) if c <= 40]
-    assert set(costs) == set(cands)
-    assert all(v > 0 for v in costs.values())
-    assert k == min(cands, key=lambda c: costs[c])
-    plain.step(40, "boris")
+    assert set(r["costs"]) == set(cands)
+    assert all(v > 0 for v in r["costs"].values())
+    assert r["resort_every"] == min(cands, key=lambda c: r["costs"][c])
+    tc = r["tile_costs"]
+    assert set(tc) == {512, 1024, 2048} and all(v > 0 for v in tc.values())
+    assert r["tile"] == min(tc, key=lambda c: tc[c]) and tuned.get_tile() == r["tile"]
+    plain.step(3 * 20 + 40, "boris")
     _assert_bitwise(_state(tuned), _state(plain))
     tuned.step(7, "boris")
     plain.step(7, "boris")
     _assert_bitwise(_state(tuned), _state(plain))
     tuned.close()
     plain.close()
+
+
+@pytest.mark.parametrize("tile", [512, 2048])
+def test_every_tile_gives_the_same_run(tile):
+    """Deterministic mode: a run at each compiled tile size equals the run at
+    the default tile bit for bit (hot plasma, re-sorts, crossings)."""
+    fp = _fp()
+    w = _wl(n_side=24, length=0.038, n_pairs=40_000)
+    a = fp.from_workload(w, spai_level=1, deterministic=True, resort_every=7)
+    b = fp.from_workload(w, spai_level=1, deterministic=True, resort_every=7)
+    assert a.get_tile() == 1024
+    b.set_tile(tile)
+    assert b.get_tile() == tile
+    a.step(30, "hc")
+    b.step(30, "hc")
+    _assert_bitwise(_state(a), _state(b))
+    with pytest.raises(Exception):
+        b.set_tile(768)
+    a.close()
+    b.close()

@@ -57,6 +57,25 @@ def _compare_fields(osim, g, tol=1e-12):
         assert err <= tol, (name, err)
 
 
+@pytest.mark.parametrize("tile", [512, 2048])
+def test_pair_plasma_fp64_parity_other_tiles(oracle_lib, tile):
+    """The particle kernel at the other compiled tile sizes (2 and 8
+    particles per thread) against the oracle: 20,011 particles (ragged last
+    tile), re-sorts every 20 steps, 60 steps of Vay."""
+    w = I.pair_plasma(n_side=24, length=0.038, n_pairs=20_011, theta=0.3, steps=60,
+                      precision="fp64")
+    osim = _oracle_sim(oracle_lib, w, 1)
+    g = _gpu_sim(w, 1)
+    g.set_tile(tile)
+    for _ in range(3):
+        osim.step(20, "vay")
+        g.step(20, "vay")
+        _compare_particles(osim, g)
+    _compare_fields(osim, g, tol=1e-11)
+    assert g.diagnostics()["gauss_rel"] <= 1e-12
+    g.close()
+
+
 def test_mesh_tables_and_spai_match(oracle_lib):
     for w, level in ((I.cyclotron(), 2), (I.pair_plasma_small(n_pairs=10), 1)):
         g = _gpu_sim(w, level)
