@@ -657,6 +657,7 @@ def main():
         "data": "synthetic",
         "config": cfg,
         "roofline": f64["roofline"],
+        "valu_issue": f64["valu_issue"],
         "stage_ms_per_step": f64["stage_ms_per_step"],
         "gauss_rel": f64["gauss_rel"],
         "hbm_gbs_step": f64["hbm_gbs_step"],

@@ -325,11 +325,11 @@ fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps,
                           int32_t *resort_every, double *cost_ms, int32_t *tile_particles,
                           double *tile_cost_ms);
 
-/* Particles per block of the single-run particle kernel: 512, 1024 (the
+/* Particles per block of the particle kernel for this run: 512, 1024 (the
  * default) or 2048, else FETD_E_ARG.  Takes effect at the next step (the
- * tiles' current-window homes are recomputed from the current order).  Runs
- * stepped in a batch use 1024: fetd_batch_create and
- * fetd_batch_step_noalloc set it on their members. */
+ * tiles' current-window homes are recomputed from the current order); a run
+ * stepped in a batch keeps its own tile there (a batch rebuilds its tile
+ * list when a member's tile changes). */
 fetd_status fetd_set_tile(fetd_sim *sim, int32_t tile_particles);
 fetd_status fetd_get_tile(fetd_sim *sim, int32_t *tile_particles);
 

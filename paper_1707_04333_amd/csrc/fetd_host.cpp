@@ -45,9 +45,8 @@ struct Species {
     int64_t bc_offset = 0; // first per-tile counter slot (pairs) of the species
 };
 
-// Tiles of n particles at ppt particles per thread (default: the batched
-// kernel's), and per-tile slots reserved per species (for the smallest tile
-// any single-run launch may use).
+// Tiles of n particles at ppt particles per thread, and per-tile slots
+// reserved per species (for the smallest tile a run may use).
 int64_t tiles_of(int64_t n, int ppt = kPPT)
 {
     return (n + int64_t(kBlock) * ppt - 1) / (int64_t(kBlock) * ppt);
@@ -128,7 +127,7 @@ struct fetd_sim {
     unsigned long long *d_counters = nullptr;
     unsigned long long *d_block_counts = nullptr;
     uint32_t *d_tile_home = nullptr;  // per tile, same slots as d_block_counts
-    int ppt = kPPT;                   // particles per thread of single-run particle launches
+    int ppt = kPPT;                   // particles per thread of the particle launches
     int64_t block_count_cap = 0;  // blocks covered by d_block_counts
     double *d_q = nullptr, *d_divd = nullptr, *d_partial = nullptr;
     // field probes
@@ -812,6 +811,7 @@ fetd_status set_ppt(fetd_sim *s, int ppt)
     if (!valid_ppt(ppt)) return s->fail(FETD_E_ARG, "invalid tile size");
     if (ppt == s->ppt) return FETD_OK;
     s->ppt = ppt;
+    ++s->desc_gen;  // a batch holding this run rebuilds its tile list
     for (const Species &sp : s->species) {
         if (sp.n == 0) continue;
         hipError_t e = launch_tile_home(s->stream, sp.n, s->d_key[s->pbuf] + sp.offset,
@@ -959,6 +959,7 @@ StepArgs step_args(const fetd_sim *s, const Species &sp, int pbuf)
     a.counters = s->d_counters;
     a.block_counts = s->d_block_counts + 2 * sp.bc_offset;
     a.tile_home = s->d_tile_home + sp.bc_offset;
+    a.ppt = s->ppt;
     return a;
 }
 
@@ -1557,7 +1558,7 @@ fetd_status fetd_pic_step(fetd_sim *s, int32_t n_steps, int32_t pusher)
         for (const Species &sp : s->species) {
             const StepArgs a = step_args(s, sp, s->pbuf);
             fetd_sim::Timer t(s, 1);
-            e = launch_particles(s->stream, mv, a, pusher, s->fp32(), s->ppt);
+            e = launch_particles(s->stream, mv, a, pusher, s->fp32());
             if (e != hipSuccess) return s->hip_fail(e, "particle step");
         }
         {
@@ -2138,7 +2139,7 @@ fetd_status batch_build(fetd_batch *b)
         ep.push_back(ep.back() + uint32_t((s->ne + 255) / 256));
         for (size_t k = 0; k < s->species.size(); ++k)
             if (s->species[k].n > 0)
-                refs.push_back({tiles_of(s->species[k].n), int(r), int(k)});
+                refs.push_back({tiles_of(s->species[k].n, s->ppt), int(r), int(k)});
     }
     std::stable_sort(refs.begin(), refs.end(),
                      [](const SegRef &x, const SegRef &y) { return x.tiles > y.tiles; });
@@ -2340,12 +2341,6 @@ fetd_status fetd_batch_create(fetd_sim *const *sims, int32_t n, int32_t use_grap
                 fetd_batch_destroy(b);
                 return st;
             }
-        // the batched kernel tiles every run by the default tile
-        if (fetd_status st = set_ppt(s, kPPT)) {
-            g_last_error = s->err;
-            fetd_batch_destroy(b);
-            return st;
-        }
     }
     if (hipStreamSynchronize(b->member_stream) != hipSuccess) {
         fetd_batch_destroy(b);
@@ -2516,11 +2511,6 @@ extern "C" fetd_status fetd_batch_step_noalloc(fetd_sim *const *sims, int32_t n,
     }
     if (n_steps == 0) return FETD_OK;
     DeviceGuard g(s0->device);
-    for (int32_t i = 0; i < n; ++i)
-        if (fetd_status st = set_ppt(sims[i], kPPT)) {  // the batched kernel's tile
-            g_last_error = sims[i]->err;
-            return st;
-        }
     std::lock_guard<std::mutex> lock(g_noalloc_mu);
     char *base = nullptr;
     if (hipError_t e = scratch_address(s0->device, &base)) {
@@ -2540,7 +2530,7 @@ extern "C" fetd_status fetd_batch_step_noalloc(fetd_sim *const *sims, int32_t n,
             if (s->species[q].n > 0) {
                 h.seg_run[k] = r;
                 h.seg_species[k] = int(q);
-                h.seg_tiles[k] = tiles_of(s->species[q].n);
+                h.seg_tiles[k] = tiles_of(s->species[q].n, s->ppt);
                 ++k;
             }
     }

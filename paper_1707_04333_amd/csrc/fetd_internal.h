@@ -14,11 +14,10 @@ constexpr int kBlock = 256;                // threads per block of the particle 
 #ifndef FETD_PPT
 #define FETD_PPT 4
 #endif
-constexpr int kPPT = FETD_PPT;             // particles per thread of the particle kernel (default;
-                                           // also the batched kernel's)
-// Particles per thread the single-run particle kernel is compiled for (the
-// tile of a block is ppt * kBlock particles); per-tile slots are sized for
-// the smallest.
+constexpr int kPPT = FETD_PPT;             // default particles per thread of the particle kernel
+// Particles per thread a run may use (its tile is ppt * kBlock particles,
+// a run-time value of the step arguments); per-tile slots are sized for the
+// smallest.
 constexpr int kPPTChoices[3] = {2, 4, 8};
 constexpr int kMinPPT = 2;
 inline bool valid_ppt(int p) { return p == 2 || p == 4 || p == 8; }
@@ -72,6 +71,7 @@ struct StepArgs {
     unsigned long long *block_counts;  // [2 * tiles]: per-tile running sums (segments, lost)
     const uint32_t *tile_home;     // [tiles]: home triangle of each tile (set by the sort)
     const int32_t *pid;            // load ids (for error reports)
+    int ppt;                       // particles per thread: a tile is ppt * kBlock particles
 };
 
 // One (run, species) segment of a batched particle launch.
@@ -135,12 +135,10 @@ hipError_t launch_spmv(hipStream_t s, const FieldDesc &d);
 hipError_t launch_pml_aux(hipStream_t s, const FieldDesc &d);
 
 // Particle stage (fetd_particles.hip, one object per precision).  A
-// deterministic launch is selected by a.fx != null (batched: det); ppt is
-// one of kPPTChoices.
-hipError_t launch_particles_f32(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
-                                int ppt);
-hipError_t launch_particles_f64(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
-                                int ppt);
+// deterministic launch is selected by a.fx != null (batched: det); a.ppt
+// is one of kPPTChoices.
+hipError_t launch_particles_f32(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher);
+hipError_t launch_particles_f64(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher);
 // Batched: queue = [next tile, blocks done], zero before the first launch;
 // the kernel's last block leaves it at zero again.
 hipError_t launch_particles_batched_f32(hipStream_t s, const SegDesc *segs, const uint32_t *prefix,
@@ -150,10 +148,9 @@ hipError_t launch_particles_batched_f64(hipStream_t s, const SegDesc *segs, cons
                                         int nseg, uint32_t total_tiles, uint32_t *queue,
                                         int pusher, bool det);
 inline hipError_t launch_particles(hipStream_t s, const MeshView &m, const StepArgs &a, int pusher,
-                                   bool fp32, int ppt)
+                                   bool fp32)
 {
-    return fp32 ? launch_particles_f32(s, m, a, pusher, ppt)
-                : launch_particles_f64(s, m, a, pusher, ppt);
+    return fp32 ? launch_particles_f32(s, m, a, pusher) : launch_particles_f64(s, m, a, pusher);
 }
 inline hipError_t launch_particles_batched(hipStream_t s, const SegDesc *segs,
                                            const uint32_t *prefix, int nseg, uint32_t total_tiles,

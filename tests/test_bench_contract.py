@@ -1,6 +1,7 @@
 """bench.py's output contract: one GPU only; the oracle baseline record;
-the committed HBM counter records still match the kernel sources they were
-taken on (else the bench would report traffic as null); and, on the GPU,
+the committed HBM and SQ counter records still match the kernel sources
+they were taken on (else the bench would report traffic and the VALU issue
+fraction as null); and, on the GPU,
 one JSON line carrying every field of the contract."""
 import json
 import os
@@ -29,6 +30,14 @@ def test_traffic_records_match_the_kernel_sources():
         for prec in precs:
             t = bench.measured_traffic(prec, rec, src)
             assert t is not None and t > 0, (rec, prec)
+
+
+def test_issue_record_matches_the_kernel_source():
+    """The committed SQ counter record (VALU instructions per launch of the
+    headline particle kernel) was taken on the current kernel source."""
+    for prec in ("fp64", "mixed"):
+        v = bench.measured_valu(prec)
+        assert v is not None and v > 0, prec
 
 
 def test_traffic_is_null_for_another_source(tmp_path):

@@ -104,6 +104,36 @@ def test_deterministic_batched_equals_separate(precision):
         s.close()
 
 
+def test_batched_members_keep_their_tiles():
+    """Runs with different tiles (512, 2048, 1024) in one batch, the tile of
+    one member changed between calls (the batch rebuilds its tile list):
+    bit for bit the runs stepped one by one, and the batch leaves each
+    member's tile as it was set."""
+    fp = _fp()
+    specs = [(12, 0.02, 3001, 0.3), (20, 0.03, 9000, 0.1), (9, 0.015, 1500, 1.0)]
+    tiles = (512, 2048, 1024)
+    wls = [_wl(n, L, p, t, "fp64") for n, L, p, t in specs]
+    batched = [fp.from_workload(w, spai_level=1, deterministic=True, resort_every=4)
+               for w in wls]
+    single = [fp.from_workload(w, spai_level=1, deterministic=True, resort_every=4)
+              for w in wls]
+    for g, t in zip(batched, tiles):
+        g.set_tile(t)
+    b = fp.Batch(batched, use_graph=True)
+    b.step(20, "vay")
+    assert [g.get_tile() for g in batched] == list(tiles)
+    batched[2].set_tile(512)
+    b.step(13, "vay")
+    for s in single:
+        s.step(33, "vay")
+    assert b.stats()["graph_replays"] >= 1
+    for gb, gs in zip(batched, single):
+        _assert_bitwise(_state(gb), _state(gs))
+    b.close()
+    for s in batched + single:
+        s.close()
+
+
 def test_deterministic_save_and_resume():
     fp = _fp()
     w = _wl()
