@@ -144,9 +144,10 @@ def copy_ceiling_gbs(nbytes=1 << 30, reps=5):
 
 
 def run_gpu(w, precision, steps, warmup, pusher, resort=None):
-    """One workload in one precision.  resort = None autotunes the re-sort
-    interval; an integer fixes it.  The timed window starts at a sorting
-    step and covers `steps` steps (inputs already on the device)."""
+    """One workload in one precision.  The autotuner chooses the particle
+    tile and scan width, and the re-sort interval unless `resort` fixes it.
+    The timed window starts at a sorting step and covers `steps` steps
+    (inputs already on the device)."""
     from paper_1707_04333_amd import fetdpic as fp
     log(f"{precision}: creating simulation ({w.n_particles} particles)")
     t0 = time.perf_counter()
@@ -155,14 +156,14 @@ def run_gpu(w, precision, steps, warmup, pusher, resort=None):
     log(f"{precision}: created in {time.perf_counter() - t0:.1f} s")
     info = sim.info()
     sim.diagnostics()  # Gauss baseline at step 0
+    tuned = sim.autotune(pusher, trial_steps=160 if resort is None else 20, with_costs=True)
     if resort is None:
-        resort = sim.autotune(pusher, trial_steps=160)
-        log(f"{precision}: autotuned re-sort interval {resort}")
-        # the autotuner leaves the order decayed: the next step sorts
-        align = 0
+        resort = tuned["resort_every"]
     else:
-        # after the load's sort the next sort is at the start of step K + 1
-        align = resort
+        sim.set_resort(resort)
+    log(f"{precision}: tile {tuned['tile']}, scan {tuned['scan']} lanes, re-sort every {resort}")
+    # the autotuner leaves the order decayed: the next step sorts
+    align = 0
     # warm-up: at least `warmup` steps, ending where the next step sorts
     w_steps = align + int(math.ceil(max(warmup, 1) / resort)) * resort
     sim.step(w_steps, pusher)
@@ -190,7 +191,8 @@ def run_gpu(w, precision, steps, warmup, pusher, resort=None):
     sim.close()
     return dict(elapsed=t1 - t0, particles=particles, stages=stages, stage_steps=stage_steps,
                 diag=diag, info=info, resort=resort, warmup_steps=w_steps,
-                sorts_timed=int(math.ceil(steps / resort)))
+                sorts_timed=int(math.ceil(steps / resort)), tile=tuned["tile"],
+                scan=tuned["scan"])
 
 
 def leg_record(r, n_p, steps, species_n, fp32, traffic=None, valu=None):
@@ -203,6 +205,7 @@ def leg_record(r, n_p, steps, species_n, fp32, traffic=None, valu=None):
     achieved = per_launch / avg_s / 1e9
     return {"value": n_p * steps / r["elapsed"], "ms_per_step": r["elapsed"] / steps * 1e3,
             "gauss_rel": r["diag"]["gauss_rel"], "resort_every": r["resort"],
+            "tile": r["tile"], "scan_lanes": r["scan"],
             "sorts_in_timed_steps": r["sorts_timed"],
             "roofline": {"bound": "hbm", "kernel": "k_particle_step", "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -658,6 +661,8 @@ def main():
         "config": cfg,
         "roofline": f64["roofline"],
         "valu_issue": f64["valu_issue"],
+        "tuning": {"tile": f64["tile"], "scan_lanes": f64["scan_lanes"],
+                   "resort_every": f64["resort_every"]},
         "stage_ms_per_step": f64["stage_ms_per_step"],
         "gauss_rel": f64["gauss_rel"],
         "hbm_gbs_step": f64["hbm_gbs_step"],

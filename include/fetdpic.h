@@ -303,27 +303,34 @@ fetd_status fetd_profile_mask(fetd_sim *sim, int32_t stage_mask, int32_t every);
 #define FETD_N_STAGES 5
 fetd_status fetd_stage_times(fetd_sim *sim, double *ms, int64_t *launches);
 
-/* Autotune the particle tiling and the re-sort cadence (the tuning the
- * method leaves to the implementation: how many particles a block of the
- * particle kernel takes, and how often the triangle order is restored).
+/* Autotune the particle kernel's tiling and current scan and the re-sort
+ * cadence (the tuning the method leaves to the implementation: how many
+ * particles a block of the particle kernel takes, over how many lanes the
+ * first-piece currents are summed before their LDS add, and how often the
+ * triangle order is restored).  With T = min(trial_steps, 20):
  * 1. Tile: for each tile size (512, 1024, 2048 particles per block of 256
- *    threads; the current one first) sort, then run min(trial_steps, 20)
- *    steps timing the particle stage with HIP events; keep the tile of
- *    least mean particle-stage time (ties keep the earlier candidate).
- * 2. Cadence: with that tile, sort once (timed), advance trial_steps steps
- *    timing the particle stage of every step, and set the re-sort interval
- *    K minimising (T_sort + sum_{j<K} T_particles(j)) / K over the
- *    candidates 5, 10, 20, 40, 80, 160 (up to trial_steps).
- * *resort_every gets K and *tile_particles the tile (either may be NULL);
- * cost_ms ([6] or NULL) gets the cost per step in ms of every K candidate
- * (-1 beyond trial_steps), tile_cost_ms ([3] or NULL) the mean
- * particle-stage ms per step of tiles 512, 1024, 2048.  Every trial step is
- * an ordinary step: the simulation advances by 3 min(trial_steps, 20) +
+ *    threads; the current one first) sort, run T steps timing the particle
+ *    stage with HIP events; keep the tile of least mean particle-stage time
+ *    (ties keep the earlier candidate).
+ * 2. Scan: the same for the scan group widths 64, 16 and 8 lanes, with that
+ *    tile (the current width first).
+ * 3. Cadence: sort once (timed), advance trial_steps steps timing the
+ *    particle stage of every step, and set the re-sort interval K
+ *    minimising (T_sort + sum_{j<K} T_particles(j)) / K over the candidates
+ *    5, 10, 20, 40, 80, 160 (up to trial_steps).
+ * out (or NULL) receives the three choices and the measured costs.  Every
+ * trial step is an ordinary step: the simulation advances by 6 T +
  * trial_steps steps, and its results do not depend on the choices beyond
  * FP64 summation order (not at all in deterministic mode). */
-fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps,
-                          int32_t *resort_every, double *cost_ms, int32_t *tile_particles,
-                          double *tile_cost_ms);
+typedef struct {
+    int32_t resort_every;       /* chosen re-sort interval K */
+    int32_t tile_particles;     /* chosen tile */
+    int32_t scan_lanes;         /* chosen scan group width */
+    double resort_cost_ms[6];   /* cost per step of K = 5, 10, 20, 40, 80, 160; -1 if untried */
+    double tile_cost_ms[3];     /* mean particle-stage ms per step, tiles 512, 1024, 2048 */
+    double scan_cost_ms[3];     /* the same for scan widths 64, 16, 8 */
+} fetd_tuning;
+fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps, fetd_tuning *out);
 
 /* Particles per block of the particle kernel for this run: 512, 1024 (the
  * default) or 2048, else FETD_E_ARG.  Takes effect at the next step (the
@@ -332,6 +339,14 @@ fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps,
  * list when a member's tile changes). */
 fetd_status fetd_set_tile(fetd_sim *sim, int32_t tile_particles);
 fetd_status fetd_get_tile(fetd_sim *sim, int32_t *tile_particles);
+
+/* Lanes per group over which the particle kernel sums the currents of
+ * particles' first pieces in one triangle before one LDS add per group:
+ * 8, 16 or 64 (the default, the whole wavefront), else FETD_E_ARG.  Changes
+ * only the FP64 summation order of the deposit (nothing in deterministic
+ * mode). */
+fetd_status fetd_set_scan(fetd_sim *sim, int32_t scan_lanes);
+fetd_status fetd_get_scan(fetd_sim *sim, int32_t *scan_lanes);
 
 /* Set the re-sort interval directly (k >= 1). */
 fetd_status fetd_set_resort(fetd_sim *sim, int32_t every);

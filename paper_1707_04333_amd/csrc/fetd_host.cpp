@@ -128,6 +128,7 @@ struct fetd_sim {
     unsigned long long *d_block_counts = nullptr;
     uint32_t *d_tile_home = nullptr;  // per tile, same slots as d_block_counts
     int ppt = kPPT;                   // particles per thread of the particle launches
+    int scan = 64;                    // lanes per group of the first-piece current scan
     int64_t block_count_cap = 0;  // blocks covered by d_block_counts
     double *d_q = nullptr, *d_divd = nullptr, *d_partial = nullptr;
     // field probes
@@ -803,6 +804,17 @@ fetd_status sort_all(fetd_sim *s, hipStream_t stream)
     return FETD_OK;
 }
 
+// Lanes per group of the particle kernel's first-piece current scan.
+fetd_status set_scan(fetd_sim *s, int lanes)
+{
+    if (!valid_scan(lanes)) return s->fail(FETD_E_ARG, "scan_lanes must be 8, 16 or 64");
+    if (lanes != s->scan) {
+        s->scan = lanes;
+        ++s->desc_gen;  // a batch holding this run rebuilds its descriptors
+    }
+    return FETD_OK;
+}
+
 // Switch the single-run particle launches to ppt particles per thread and
 // recompute every tile's home triangle for the new tiling from the current
 // particle order, on the simulation's stream (no allocation).
@@ -960,6 +972,7 @@ StepArgs step_args(const fetd_sim *s, const Species &sp, int pbuf)
     a.block_counts = s->d_block_counts + 2 * sp.bc_offset;
     a.tile_home = s->d_tile_home + sp.bc_offset;
     a.ppt = s->ppt;
+    a.scan = s->scan;
     return a;
 }
 
@@ -1906,8 +1919,7 @@ static fetd_status timed_particle_steps(fetd_sim *s, int32_t pusher, int32_t ste
     return FETD_OK;
 }
 
-fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int32_t *resort_every,
-                          double *cost_ms, int32_t *tile_particles, double *tile_cost_ms)
+fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, fetd_tuning *out)
 {
     if (!s || trial_steps < 2 || pusher < 0 || pusher > 3) return FETD_E_ARG;
     DeviceGuard g(s->device);
@@ -1917,34 +1929,64 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     const int saved = s->resort_every;
     s->resort_every = std::numeric_limits<int>::max();
     std::vector<double> tp;
-
-    // 1. Tile size: each candidate runs min(trial_steps, 20) steps from a
-    //    fresh sort; the one of least mean particle-stage time is kept (the
-    //    current one first, so a tie keeps it).
-    const int tile_steps = std::min<int32_t>(trial_steps, 20);
-    int order[3] = {s->ppt, 0, 0};
-    for (int k = 0, j = 1; k < 3; ++k)
-        if (kPPTChoices[k] != s->ppt) order[j++] = kPPTChoices[k];
-    int best_ppt = s->ppt;
-    double best_tile = std::numeric_limits<double>::max();
-    for (int c : order) {
-        if ((st = set_ppt(s, c))) return st;
-        if ((st = sort_all(s, s->stream))) return st;
-        if ((st = timed_particle_steps(s, pusher, tile_steps, tp))) return st;
+    const int short_steps = std::min<int32_t>(trial_steps, 20);
+    if (out) {
+        for (double &c : out->resort_cost_ms) c = -1.0;
+        for (double &c : out->tile_cost_ms) c = -1.0;
+        for (double &c : out->scan_cost_ms) c = -1.0;
+    }
+    // Mean particle-stage ms per step over short_steps steps from a fresh sort.
+    auto trial = [&](double &cost) -> fetd_status {
+        fetd_status e;
+        if ((e = sort_all(s, s->stream))) return e;
+        if ((e = timed_particle_steps(s, pusher, short_steps, tp))) return e;
         double sum = 0.0;
         for (double t : tp) sum += t;
-        const double cost = sum / tile_steps;
-        for (int k = 0; k < 3; ++k)
-            if (kPPTChoices[k] == c && tile_cost_ms) tile_cost_ms[k] = cost;
-        if (cost < best_tile) {
-            best_tile = cost;
-            best_ppt = c;
-        }
-    }
-    if ((st = set_ppt(s, best_ppt))) return st;
+        cost = sum / short_steps;
+        return FETD_OK;
+    };
 
-    // 2. Re-sort cadence with that tile: one timed sort, then the particle
-    //    stage of every step as the order decays.
+    // 1. Tile (the current one first, so a tie keeps it).
+    {
+        int order[3] = {s->ppt, 0, 0};
+        for (int k = 0, j = 1; k < 3; ++k)
+            if (kPPTChoices[k] != s->ppt) order[j++] = kPPTChoices[k];
+        int best = s->ppt;
+        double best_cost = std::numeric_limits<double>::max();
+        for (int c : order) {
+            double cost = 0.0;
+            if ((st = set_ppt(s, c)) || (st = trial(cost))) return st;
+            for (int k = 0; k < 3; ++k)
+                if (kPPTChoices[k] == c && out) out->tile_cost_ms[k] = cost;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = c;
+            }
+        }
+        if ((st = set_ppt(s, best))) return st;
+    }
+    // 2. Scan group width, with that tile.
+    {
+        int order[3] = {s->scan, 0, 0};
+        for (int k = 0, j = 1; k < 3; ++k)
+            if (kScanChoices[k] != s->scan) order[j++] = kScanChoices[k];
+        int best = s->scan;
+        double best_cost = std::numeric_limits<double>::max();
+        for (int c : order) {
+            double cost = 0.0;
+            if ((st = set_scan(s, c)) || (st = trial(cost))) return st;
+            for (int k = 0; k < 3; ++k)
+                if (kScanChoices[k] == c && out) out->scan_cost_ms[k] = cost;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = c;
+            }
+        }
+        if ((st = set_scan(s, best))) return st;
+    }
+
+    // 3. Re-sort cadence: one timed sort, then the particle stage of every
+    //    step as the order decays.
     if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4), 1))) return st;
     {
         fetd_sim::Timer t(s, 4);
@@ -1959,12 +2001,11 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     double best_cost = std::numeric_limits<double>::max();
     int ci = 0;
     for (int K : {5, 10, 20, 40, 80, 160}) {
-        if (cost_ms) cost_ms[ci] = -1.0;
         if (K <= trial_steps) {
             double sum = t_sort;
             for (int j = 0; j < K; ++j) sum += tp[j];
             const double cost = sum / K;
-            if (cost_ms) cost_ms[ci] = cost;
+            if (out) out->resort_cost_ms[ci] = cost;
             if (cost < best_cost) {
                 best_cost = cost;
                 best = K;
@@ -1975,8 +2016,24 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, int3
     s->resort_every = best;
     s->steps_since_sort = trial_steps;  // the order has decayed: sort at the next step
     if ((st = fetd_profile_mask(s, was_mask, was_every))) return st;
-    if (resort_every) *resort_every = best;
-    if (tile_particles) *tile_particles = best_ppt * kBlock;
+    if (out) {
+        out->resort_every = best;
+        out->tile_particles = s->ppt * kBlock;
+        out->scan_lanes = s->scan;
+    }
+    return FETD_OK;
+}
+
+fetd_status fetd_set_scan(fetd_sim *s, int32_t scan_lanes)
+{
+    if (!s) return FETD_E_ARG;
+    return set_scan(s, scan_lanes);
+}
+
+fetd_status fetd_get_scan(fetd_sim *s, int32_t *scan_lanes)
+{
+    if (!s || !scan_lanes) return FETD_E_ARG;
+    *scan_lanes = s->scan;
     return FETD_OK;
 }
 

@@ -21,6 +21,9 @@ constexpr int kPPT = FETD_PPT;             // default particles per thread of th
 constexpr int kPPTChoices[3] = {2, 4, 8};
 constexpr int kMinPPT = 2;
 inline bool valid_ppt(int p) { return p == 2 || p == 4 || p == 8; }
+// Lanes per group of the first-piece current scan (a run-time value).
+constexpr int kScanChoices[3] = {64, 16, 8};
+inline bool valid_scan(int w) { return w == 8 || w == 16 || w == 64; }
 constexpr int kSlice = 64;                 // rows per SELL slice of the SpMV
 
 // Per-triangle tables (device).
@@ -72,6 +75,7 @@ struct StepArgs {
     const uint32_t *tile_home;     // [tiles]: home triangle of each tile (set by the sort)
     const int32_t *pid;            // load ids (for error reports)
     int ppt;                       // particles per thread: a tile is ppt * kBlock particles
+    int scan;                      // lanes per group of the first-piece current scan (8, 16, 64)
 };
 
 // One (run, species) segment of a batched particle launch.

@@ -98,9 +98,11 @@ def lib():
         L.fetd_last_error.restype = ctypes.c_char_p
         optional = {"fetd_profile": [P, ctypes.c_int32], "fetd_stage_times": [P, P, P],
                     "fetd_profile_mask": [P, ctypes.c_int32, ctypes.c_int32],
-                    "fetd_autotune": [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P],
+                    "fetd_autotune": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_set_tile": [P, ctypes.c_int32],
                     "fetd_get_tile": [P, P],
+                    "fetd_set_scan": [P, ctypes.c_int32],
+                    "fetd_get_scan": [P, P],
                     "fetd_set_resort": [P, ctypes.c_int32],
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
                     "fetd_batch_step": [P, ctypes.c_int32, ctypes.c_int32],
@@ -317,25 +319,31 @@ STAGES = ("faraday", "particles", "ampere", "spmv", "sort")
 
 AUTOTUNE_CANDIDATES = (5, 10, 20, 40, 80, 160)
 TILE_CANDIDATES = (512, 1024, 2048)
+SCAN_CANDIDATES = (64, 16, 8)
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("resort_every", ctypes.c_int32), ("tile_particles", ctypes.c_int32),
+                ("scan_lanes", ctypes.c_int32), ("resort_cost_ms", ctypes.c_double * 6),
+                ("tile_cost_ms", ctypes.c_double * 3), ("scan_cost_ms", ctypes.c_double * 3)]
 
 
 def autotune(h, pusher="boris", trial_steps=160, with_costs=False):
-    """fetd_autotune: tunes the tile size, then the re-sort interval.
-    Returns the chosen re-sort interval; with_costs, a dict with it
-    ("resort_every"), the chosen tile ("tile"), and the measured cost in ms
-    per step of every candidate tried ("costs", "tile_costs")."""
+    """fetd_autotune: tunes the tile, the scan group width, then the
+    re-sort interval.  Returns the chosen re-sort interval; with_costs, a
+    dict with the three choices ("resort_every", "tile", "scan") and the
+    measured cost in ms per step of every candidate tried ("costs",
+    "tile_costs", "scan_costs")."""
     pid = PUSHERS[pusher] if isinstance(pusher, str) else int(pusher)
-    k = ctypes.c_int32()
-    tile = ctypes.c_int32()
-    costs = np.zeros(len(AUTOTUNE_CANDIDATES))
-    tcosts = np.zeros(len(TILE_CANDIDATES))
-    _check(lib().fetd_autotune(h, pid, int(trial_steps), ctypes.byref(k), _p(costs),
-                               ctypes.byref(tile), _p(tcosts)), h)
+    t = Tuning()
+    _check(lib().fetd_autotune(h, pid, int(trial_steps), ctypes.byref(t)), h)
     if not with_costs:
-        return k.value
-    return {"resort_every": k.value, "tile": tile.value,
-            "costs": {c: float(v) for c, v in zip(AUTOTUNE_CANDIDATES, costs) if v >= 0},
-            "tile_costs": {c: float(v) for c, v in zip(TILE_CANDIDATES, tcosts)}}
+        return t.resort_every
+    return {"resort_every": t.resort_every, "tile": t.tile_particles, "scan": t.scan_lanes,
+            "costs": {c: float(v) for c, v in zip(AUTOTUNE_CANDIDATES, t.resort_cost_ms)
+                      if v >= 0},
+            "tile_costs": {c: float(v) for c, v in zip(TILE_CANDIDATES, t.tile_cost_ms)},
+            "scan_costs": {c: float(v) for c, v in zip(SCAN_CANDIDATES, t.scan_cost_ms)}}
 
 
 def set_tile(h, tile_particles):
@@ -345,6 +353,16 @@ def set_tile(h, tile_particles):
 def get_tile(h):
     out = ctypes.c_int32()
     _check(lib().fetd_get_tile(h, ctypes.byref(out)), h)
+    return out.value
+
+
+def set_scan(h, lanes):
+    _check(lib().fetd_set_scan(h, int(lanes)), h)
+
+
+def get_scan(h):
+    out = ctypes.c_int32()
+    _check(lib().fetd_get_scan(h, ctypes.byref(out)), h)
     return out.value
 
 
@@ -466,6 +484,12 @@ class Sim:
 
     def get_tile(self):
         return get_tile(self.h)
+
+    def set_scan(self, lanes):
+        set_scan(self.h, lanes)
+
+    def get_scan(self):
+        return get_scan(self.h)
 
     def stage_times(self):
         return stage_times(self.h)

@@ -159,10 +159,11 @@ def test_deterministic_save_and_resume():
 
 
 def test_autotune_returns_argmin_and_keeps_the_run():
-    """fetd_autotune picks the tile and then the re-sort interval of least
-    measured cost, and its trial steps are ordinary steps of the run: in
-    deterministic mode the state equals, bit for bit, that of a plain run of
-    as many steps (3 x 20 tile trials + 40 cadence trials)."""
+    """fetd_autotune picks the tile, the scan width and then the re-sort
+    interval of least measured cost, and its trial steps are ordinary steps
+    of the run: in deterministic mode the state equals, bit for bit, that of
+    a plain run of as many steps (3 x 20 tile trials, 3 x 20 scan trials, 40
+    cadence trials)."""
     fp = _fp()
     w = _wl(n_side=24, length=0.038, n_pairs=40_000)
     tuned = fp.from_workload(w, spai_level=1, deterministic=True)
@@ -175,7 +176,10 @@ def test_autotune_returns_argmin_and_keeps_the_run():
     tc = r["tile_costs"]
     assert set(tc) == {512, 1024, 2048} and all(v > 0 for v in tc.values())
     assert r["tile"] == min(tc, key=lambda c: tc[c]) and tuned.get_tile() == r["tile"]
-    plain.step(3 * 20 + 40, "boris")
+    sc = r["scan_costs"]
+    assert set(sc) == {64, 16, 8} and all(v > 0 for v in sc.values())
+    assert r["scan"] == min(sc, key=lambda c: sc[c]) and tuned.get_scan() == r["scan"]
+    plain.step(6 * 20 + 40, "boris")
     _assert_bitwise(_state(tuned), _state(plain))
     tuned.step(7, "boris")
     plain.step(7, "boris")
@@ -184,21 +188,24 @@ def test_autotune_returns_argmin_and_keeps_the_run():
     plain.close()
 
 
-@pytest.mark.parametrize("tile", [512, 2048])
-def test_every_tile_gives_the_same_run(tile):
-    """Deterministic mode: a run at each compiled tile size equals the run at
-    the default tile bit for bit (hot plasma, re-sorts, crossings)."""
+@pytest.mark.parametrize("tile,scan", [(512, 64), (2048, 8), (1024, 16)])
+def test_every_tile_gives_the_same_run(tile, scan):
+    """Deterministic mode: a run at each tile size and scan width equals the
+    run at the defaults bit for bit (hot plasma, re-sorts, crossings)."""
     fp = _fp()
     w = _wl(n_side=24, length=0.038, n_pairs=40_000)
     a = fp.from_workload(w, spai_level=1, deterministic=True, resort_every=7)
     b = fp.from_workload(w, spai_level=1, deterministic=True, resort_every=7)
-    assert a.get_tile() == 1024
+    assert a.get_tile() == 1024 and a.get_scan() == 64
     b.set_tile(tile)
-    assert b.get_tile() == tile
+    b.set_scan(scan)
+    assert b.get_tile() == tile and b.get_scan() == scan
     a.step(30, "hc")
     b.step(30, "hc")
     _assert_bitwise(_state(a), _state(b))
     with pytest.raises(Exception):
         b.set_tile(768)
+    with pytest.raises(Exception):
+        b.set_scan(32)
     a.close()
     b.close()

@@ -57,16 +57,17 @@ def _compare_fields(osim, g, tol=1e-12):
         assert err <= tol, (name, err)
 
 
-@pytest.mark.parametrize("tile", [512, 2048])
-def test_pair_plasma_fp64_parity_other_tiles(oracle_lib, tile):
-    """The particle kernel at the other compiled tile sizes (2 and 8
-    particles per thread) against the oracle: 20,011 particles (ragged last
-    tile), re-sorts every 20 steps, 60 steps of Vay."""
+@pytest.mark.parametrize("tile,scan", [(512, 64), (2048, 8), (1024, 16)])
+def test_pair_plasma_fp64_parity_other_tiles(oracle_lib, tile, scan):
+    """The particle kernel at the other tile sizes (2 and 8 particles per
+    thread) and scan widths against the oracle: 20,011 particles (ragged
+    last tile), re-sorts every 20 steps, 60 steps of Vay."""
     w = I.pair_plasma(n_side=24, length=0.038, n_pairs=20_011, theta=0.3, steps=60,
                       precision="fp64")
     osim = _oracle_sim(oracle_lib, w, 1)
     g = _gpu_sim(w, 1)
     g.set_tile(tile)
+    g.set_scan(scan)
     for _ in range(3):
         osim.step(20, "vay")
         g.step(20, "vay")
