@@ -11,9 +11,10 @@ kernel's rarely taken branches, through the C-ABI against the FP64 oracle.
   the applied field only (the self-field starts at zero), so each sampled
   particle's step is the oracle's single-particle step; Gauss's law holds
   over the whole mesh.
-* More than half of a tile's particles leaving their triangle in one step
-  overflows the kernel's LDS crossing queue (512 of 1,024); the overflow is
-  finished in place.  A run where about 95% of the particles cross edges
+* More than 384 (FP64) or 512 (FP32) of a 1,024-particle tile's particles
+  leaving their triangle in one step overflow the kernel's LDS crossing
+  queue; the overflow is finished in place (in FP64 from the start state,
+  as phase 2 does).  A run where about 95% of the particles cross edges
   every step checks that branch against the oracle.
 """
 import os
@@ -166,7 +167,7 @@ def test_crossing_queue_overflow_parity(oracle_lib, deterministic):
         osim.step(1, "boris")
         g.step(1, "boris")
         left = sum(int((b != s.tri).sum()) for b, s in zip(before, osim.species))
-        # every tile of 1024 holds far more than 512 leavers
+        # every tile of 1024 holds far more leavers than the queue's 384 entries
         assert left > 0.85 * w.n_particles, left
         _compare_fp64(osim, g, field_tol=1e-10)
     g.close()
