@@ -125,6 +125,10 @@ typedef struct {
                               largest contribution's power of two, one device integer
                               atomic per limb), converted to FP64 once per step.  The
                               sum differs from a sequential FP64 sum only by rounding. */
+    int32_t record_crossings; /* 0..64: keep, for every particle, the triangles of the first
+                              record_crossings straight pieces of its last step's move and
+                              the number of pieces (Sec. II.D), read with
+                              fetd_crossings_get; 0 = off (no memory, no cost) */
 } fetd_opts;
 
 /* Field / table selectors for fetd_fields_get. */
@@ -274,6 +278,16 @@ fetd_status fetd_fields_get(fetd_sim *sim, int32_t which, void *host_dst,
 fetd_status fetd_particles_get(fetd_sim *sim, int32_t species, int64_t capacity,
                                int32_t *tri, int8_t *slot, double *lam, double *u,
                                int64_t *id, int64_t *n_out);
+
+/* The crossing record of the last step (fetd_opts.record_crossings = K > 0,
+ * else FETD_E_STATE), for the species' particles alive after it, in the
+ * order and count of fetd_particles_get: count[n] = the number of straight
+ * pieces of each particle's move (1 = it stayed in its triangle), tris[n*K]
+ * = the triangle of each of the first K pieces, -1 past count.  Valid until
+ * the next step or sort.  Either array may be NULL; capacity counts
+ * particles. */
+fetd_status fetd_crossings_get(fetd_sim *sim, int32_t species, int64_t capacity, int32_t *count,
+                               int32_t *tris, int64_t *n_out);
 
 /* Charge, Gauss and continuity residuals, energies and counters
  * (Sec. II.A eq. semi.dis.div.2, Sec. II.D eq. full.dis.cont).

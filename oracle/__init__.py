@@ -79,7 +79,7 @@ def _declare(L):
     L.o_particles.argtypes = [P, P, P, P, P, P, P, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, ctypes.c_int, ctypes.c_int64, P, P, P, P, P,
-                              P, P]
+                              P, P, P, ctypes.c_int, P]
     L.o_particles.restype = ctypes.c_int
     L.o_particles_omp.argtypes = [ctypes.c_int] + L.o_particles.argtypes
     L.o_particles_omp.restype = ctypes.c_int
@@ -426,11 +426,14 @@ class OracleSim:
                                              "edge_tsign", "edge_free", "mt_ptr", "mt_col",
                                              "mt_val"]])
 
-    def step(self, n_steps=1, pusher="boris", threads=1):
+    def step(self, n_steps=1, pusher="boris", threads=1, record=0):
         """n_steps steps with the given pusher.  threads > 1 runs the
         particle stage on that many OpenMP threads (the timing mode:
         contiguous chunks of particles, private currents added in thread
-        order); the default single thread is the parity mode."""
+        order); the default single thread is the parity mode.  record > 0
+        keeps, per species, the triangles of the first `record` straight
+        pieces of every particle's last move (s.seq [n, record], -1 beyond
+        the pieces) and the number of pieces (s.nseq [n])."""
         L = lib()
         pid = PUSHERS[pusher] if isinstance(pusher, str) else int(pusher)
         ms = ctypes.byref(self.ms)
@@ -440,10 +443,15 @@ class OracleSim:
             counts = np.zeros(2, dtype=np.int64)
             bad = np.zeros(1, dtype=np.int64)
             for s in self.species:
+                if record > 0:
+                    s.seq = np.full((s.n, record), -1, dtype=np.int32)
+                    s.nseq = np.zeros(s.n, dtype=np.int32)
                 args = (ms, _p(self.e), _p(self.e_ext), _p(self.b), _p(b_new),
                         _p(self.bz_ext), _p(self.affine), pid, s.q, s.m, s.w,
                         self.dt, self.c, self.cap, s.n, _p(s.tri), _p(s.slot),
-                        _p(s.lam), _p(s.u), _p(self.cur), _p(counts), _p(bad))
+                        _p(s.lam), _p(s.u), _p(self.cur), _p(counts), _p(bad),
+                        _p(s.seq) if record > 0 else None, int(record),
+                        _p(s.nseq) if record > 0 else None)
                 if threads > 1:
                     rc = L.o_particles_omp(int(threads), *args)
                 else:

@@ -342,17 +342,34 @@ void o_ampere(const o_mesh *M, const double *b_half, const double *cur, double d
 /* deposit.  Particles with tri < 0 are lost and skipped.                  */
 /* Returns 0, or -1 (crossing cap) / -2 (non-finite momentum) with *bad    */
 /* the first offending particle.  counts[0] += segments, counts[1] += lost */
+/* seq / nseq (optional): the triangle of each straight piece of particle  */
+/* p's move, the first seqcap of them at seq[p * seqcap], and the number   */
+/* of pieces in nseq[p] (0 for a particle lost before the step).           */
 /* ---------------------------------------------------------------------- */
 int o_particles(const o_mesh *M, const double *e, const double *e_ext,
                 const double *b_old, const double *b_new, const double *bz_ext,
                 const double *affine, int pusher, double q, double m, double w,
                 double dt, double c, int cap, int64_t n, int32_t *tri, int8_t *slot,
-                double *lam, double *u, double *cur, int64_t *counts, int64_t *bad)
+                double *lam, double *u, double *cur, int64_t *counts, int64_t *bad,
+                int32_t *seq, int seqcap, int32_t *nseq)
 {
     double alpha = q * dt / (2.0 * m);
     double qdt = q * w / dt;
+    int32_t *seg_tri = NULL;
+    double *seg_L = NULL;
+    if (seq) {
+        seg_tri = malloc(sizeof(int32_t) * (size_t)(cap > 0 ? cap : 1));
+        seg_L = malloc(sizeof(double) * 6 * (size_t)(cap > 0 ? cap : 1));
+        if (!seg_tri || !seg_L) {
+            free(seg_tri);
+            free(seg_L);
+            return -3;
+        }
+    }
+    int rc = 0;
     for (int64_t p = 0; p < n; ++p) {
         int f = tri[p];
+        if (nseq) nseq[p] = 0;
         if (f < 0) continue;
         double L[3];
         local_lambda(slot[p], lam + 2 * p, L);
@@ -375,7 +392,8 @@ int o_particles(const o_mesh *M, const double *e, const double *e_ext,
         o_push(pusher, u0, eps, beta, c, u1);
         if (!isfinite(u1[0]) || !isfinite(u1[1])) {
             *bad = p;
-            return -2;
+            rc = -2;
+            break;
         }
         u[2 * p] = u1[0];
         u[2 * p + 1] = u1[1];
@@ -386,10 +404,15 @@ int o_particles(const o_mesh *M, const double *e, const double *e_ext,
         int32_t t32 = f;
         int8_t s8 = slot[p];
         int lost = 0;
-        int ns = o_move(M, &t32, &s8, lam + 2 * p, dx, dy, qdt, cur, cap, &lost, NULL, NULL);
+        int ns = o_move(M, &t32, &s8, lam + 2 * p, dx, dy, qdt, cur, cap, &lost, seg_tri, seg_L);
         if (ns < 0) {
             *bad = p;
-            return -1;
+            rc = -1;
+            break;
+        }
+        if (seq) {
+            for (int k = 0; k < ns && k < seqcap; ++k) seq[p * seqcap + k] = seg_tri[k];
+            nseq[p] = ns;
         }
         counts[0] += ns;
         if (lost) {
@@ -400,7 +423,9 @@ int o_particles(const o_mesh *M, const double *e, const double *e_ext,
         }
         slot[p] = s8;
     }
-    return 0;
+    free(seg_tri);
+    free(seg_L);
+    return rc;
 }
 
 /* Nodal charge q_i = sum_p Q lambda_i(r_p) (Sec. II.D, eq.
@@ -601,7 +626,8 @@ int o_particles_omp(int nthreads, const o_mesh *M, const double *e, const double
                     const double *b_old, const double *b_new, const double *bz_ext,
                     const double *affine, int pusher, double q, double m, double w,
                     double dt, double c, int cap, int64_t n, int32_t *tri, int8_t *slot,
-                    double *lam, double *u, double *cur, int64_t *counts, int64_t *bad)
+                    double *lam, double *u, double *cur, int64_t *counts, int64_t *bad,
+                    int32_t *seq, int seqcap, int32_t *nseq)
 {
     if (nthreads < 1) nthreads = 1;
     double *priv = calloc((size_t)nthreads * (size_t)M->ne, sizeof(double));
@@ -620,7 +646,8 @@ int o_particles_omp(int nthreads, const o_mesh *M, const double *e, const double
         int64_t lo = n * t / nthreads, hi = n * (t + 1) / nthreads;
         prc[t] = o_particles(M, e, e_ext, b_old, b_new, bz_ext, affine, pusher, q, m, w, dt, c,
                              cap, hi - lo, tri + lo, slot + lo, lam + 2 * lo, u + 2 * lo,
-                             priv + (size_t)t * M->ne, pc + 2 * t, pbad + t);
+                             priv + (size_t)t * M->ne, pc + 2 * t, pbad + t,
+                             seq ? seq + lo * seqcap : NULL, seqcap, nseq ? nseq + lo : NULL);
         if (prc[t] != 0) pbad[t] += lo;
     }
     int rc = 0;

@@ -128,6 +128,8 @@ struct fetd_sim {
     unsigned long long *d_block_counts = nullptr;
     uint32_t *d_tile_home = nullptr;  // per tile, same slots as d_block_counts
     int ppt = kPPT;                   // particles per thread of the particle launches
+    int xcap = 0;                     // crossing record: pieces kept per particle (0 = off)
+    int32_t *d_xcount = nullptr, *d_xtris = nullptr;  // [p_cap], [p_cap * xcap]
     int scan = 64;                    // lanes per group of the first-piece current scan
     int64_t block_count_cap = 0;  // blocks covered by d_block_counts
     double *d_q = nullptr, *d_divd = nullptr, *d_partial = nullptr;
@@ -769,6 +771,15 @@ fetd_status grow_particles(fetd_sim *s, int64_t extra)
     }
     s->pbuf = 0;
     s->p_cap = ncap;
+    if (s->xcap > 0) {
+        s->dev_free(s->d_xcount);
+        s->dev_free(s->d_xtris);
+        s->d_xcount = s->d_xtris = nullptr;
+        fetd_status st = alloc_zero(s, &s->d_xcount, size_t(ncap));
+        if (!st) st = alloc_zero(s, &s->d_xtris, size_t(ncap) * size_t(s->xcap));
+        if (st) return st;
+        ++s->desc_gen;
+    }
     return FETD_OK;
 }
 
@@ -973,6 +984,9 @@ StepArgs step_args(const fetd_sim *s, const Species &sp, int pbuf)
     a.tile_home = s->d_tile_home + sp.bc_offset;
     a.ppt = s->ppt;
     a.scan = s->scan;
+    a.xcap = s->xcap;
+    a.xcount = s->d_xcount ? s->d_xcount + sp.offset : nullptr;
+    a.xtris = s->d_xtris ? s->d_xtris + sp.offset * s->xcap : nullptr;
     return a;
 }
 
@@ -1109,6 +1123,12 @@ fetd_status fetd_mesh_create(const fetd_mesh_desc *mesh, const fetd_opts *opts, 
     s->cap = opts->crossing_cap > 0 ? opts->crossing_cap : 64;
     s->resort_every = opts->resort_every > 0 ? opts->resort_every : 20;
     s->deterministic = opts->deterministic != 0;
+    s->xcap = opts->record_crossings;
+    if (s->xcap < 0 || s->xcap > 64) {
+        delete s;
+        g_last_error = "record_crossings must be 0..64";
+        return FETD_E_ARG;
+    }
     if ((s->alloc_cb == nullptr) != (s->free_cb == nullptr)) {
         delete s;
         g_last_error = "alloc and free callbacks must be given together";
@@ -1754,6 +1774,44 @@ fetd_status fetd_particles_get(fetd_sim *s, int32_t species, int64_t capacity, i
                 if (u) u[2 * o + c] = reinterpret_cast<double *>(ub.data())[2 * i + c];
             }
         }
+    }
+    return FETD_OK;
+}
+
+fetd_status fetd_crossings_get(fetd_sim *s, int32_t species, int64_t capacity, int32_t *count,
+                               int32_t *tris, int64_t *n_out)
+{
+    if (!s) return FETD_E_ARG;
+    if (s->xcap <= 0) return s->fail(FETD_E_STATE, "record_crossings is off");
+    if (species < 0 || species >= int32_t(s->species.size()))
+        return s->fail(FETD_E_ARG, "no such species");
+    DeviceGuard g(s->device);
+    fetd_status st = check_device_errors(s);
+    if (st) return st;
+    const Species &sp = s->species[species];
+    const int K = s->xcap;
+    std::vector<uint32_t> key(sp.n);
+    std::vector<int32_t> pid(sp.n), cnt(sp.n), seq(size_t(sp.n) * K);
+    if (sp.n) {
+        if ((st = download(s, key.data(), s->d_key[s->pbuf] + sp.offset, 4 * sp.n))) return st;
+        if ((st = download(s, pid.data(), s->d_pid[s->pbuf] + sp.offset, 4 * sp.n))) return st;
+        if ((st = download(s, cnt.data(), s->d_xcount + sp.offset, 4 * sp.n))) return st;
+        if ((st = download(s, seq.data(), s->d_xtris + sp.offset * K, 4 * size_t(sp.n) * K)))
+            return st;
+    }
+    std::vector<std::pair<int32_t, int64_t>> order;
+    order.reserve(sp.n);
+    for (int64_t i = 0; i < sp.n; ++i)
+        if (key[i] != kLost) order.push_back({pid[i], i});
+    std::sort(order.begin(), order.end());
+    if (n_out) *n_out = int64_t(order.size());
+    if (capacity < int64_t(order.size())) return s->fail(FETD_E_ARG, "capacity too small");
+    for (size_t o = 0; o < order.size(); ++o) {
+        const int64_t i = order[o].second;
+        if (count) count[o] = cnt[i];
+        if (tris)
+            for (int k = 0; k < K; ++k)
+                tris[o * K + k] = k < cnt[i] ? seq[size_t(i) * K + k] : -1;
     }
     return FETD_OK;
 }

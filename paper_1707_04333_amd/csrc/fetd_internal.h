@@ -76,6 +76,9 @@ struct StepArgs {
     const int32_t *pid;            // load ids (for error reports)
     int ppt;                       // particles per thread: a tile is ppt * kBlock particles
     int scan;                      // lanes per group of the first-piece current scan (8, 16, 64)
+    int32_t *xcount;               // crossing record, or null: pieces of each particle's move
+    int32_t *xtris;                // [n * xcap]: the triangle of each of the first xcap pieces
+    int xcap;
 };
 
 // One (run, species) segment of a batched particle launch.

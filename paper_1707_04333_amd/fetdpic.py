@@ -47,7 +47,8 @@ class Opts(ctypes.Structure):
                 ("spai_level", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_user", ctypes.c_void_p), ("crossing_cap", ctypes.c_int32),
-                ("resort_every", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
+                ("resort_every", ctypes.c_int32), ("deterministic", ctypes.c_int32),
+                ("record_crossings", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -102,6 +103,7 @@ def lib():
                     "fetd_set_tile": [P, ctypes.c_int32],
                     "fetd_get_tile": [P, P],
                     "fetd_set_scan": [P, ctypes.c_int32],
+                    "fetd_crossings_get": [P, ctypes.c_int32, ctypes.c_int64, P, P, P],
                     "fetd_get_scan": [P, P],
                     "fetd_set_resort": [P, ctypes.c_int32],
                     "fetd_batch_create": [P, ctypes.c_int32, ctypes.c_int32, P],
@@ -175,7 +177,8 @@ class _TorchMemory:
 # ---------------------------------------------------------------------------
 
 def mesh_create(mesh, dt, eps0, mu0, c, precision="fp64", spai_level=1, device=0,
-                crossing_cap=64, resort_every=20, deterministic=False, use_torch=True):
+                crossing_cap=64, resort_every=20, deterministic=False, record_crossings=0,
+                use_torch=True):
     """fetd_mesh_create.  ``mesh`` has node_xy, tri_nodes, tri_shift, period."""
     node_xy = np.ascontiguousarray(mesh.node_xy, dtype=np.float64)
     tri = np.ascontiguousarray(mesh.tri_nodes, dtype=np.int32)
@@ -195,7 +198,8 @@ def mesh_create(mesh, dt, eps0, mu0, c, precision="fp64", spai_level=1, device=0
     opts = Opts(PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                 float(dt), float(eps0), float(mu0), float(c), int(spai_level), int(device),
                 stream, mem._alloc if mem else ALLOC_FN(), mem._free if mem else FREE_FN(), None,
-                int(crossing_cap), int(resort_every), 1 if deterministic else 0)
+                int(crossing_cap), int(resort_every), 1 if deterministic else 0,
+                int(record_crossings))
     h = ctypes.c_void_p()
     _check(lib().fetd_mesh_create(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h)))
     return h, mem
@@ -300,6 +304,21 @@ def particles_get(h, species):
     _check(lib().fetd_particles_get(h, int(species), cnt, _p(tri), _p(slot), _p(lam), _p(u),
                                     _p(ids), ctypes.byref(n)), h)
     return dict(tri=tri, slot=slot, lam=lam, u=u, id=ids)
+
+
+def crossings_get(h, species, record):
+    """fetd_crossings_get: (count [n], tris [n, record]) of the last step, in
+    the order of particles_get."""
+    n = ctypes.c_int64()
+    st = lib().fetd_crossings_get(h, int(species), 0, None, None, ctypes.byref(n))
+    if st not in (FETD_OK, FETD_E_ARG):
+        _check(st, h)
+    cnt = n.value
+    count = np.empty(cnt, dtype=np.int32)
+    tris = np.empty((cnt, int(record)), dtype=np.int32)
+    _check(lib().fetd_crossings_get(h, int(species), cnt, _p(count), _p(tris), ctypes.byref(n)),
+           h)
+    return count, tris
 
 
 def diagnostics(h):
@@ -408,6 +427,7 @@ class Sim:
     needs kept alive."""
 
     def __init__(self, mesh, dt, eps0, mu0, c, **kw):
+        self.record = int(kw.get("record_crossings", 0))
         self.h, self._mem = mesh_create(mesh, dt, eps0, mu0, c, **kw)
 
     def close(self):
@@ -463,6 +483,9 @@ class Sim:
 
     def particles(self, species):
         return particles_get(self.h, species)
+
+    def crossings(self, species):
+        return crossings_get(self.h, species, self.record)
 
     def diagnostics(self):
         return diagnostics(self.h)

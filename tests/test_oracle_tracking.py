@@ -200,3 +200,40 @@ def test_wall_loss(oracle_lib):
         last_f, Ls, Lf = segs[-1]
         assert np.min(np.abs(Lf)) == 0.0
     assert n_lost == 20
+
+
+def test_step_records_each_particles_pieces(oracle_lib):
+    """The oracle's per-particle piece record of a step (the triangle of each
+    straight piece, Sec. II.D): it starts in the particle's triangle before
+    the step, walks through edge neighbours, ends in its triangle after the
+    step (unless lost at a wall), and the piece counts sum to the step's
+    segment count."""
+    w = I.pair_plasma(n_side=12, length=0.02, n_pairs=1500, theta=1.0, steps=5,
+                      precision="fp64")
+    sp = [(s.q, s.m, s.w, s.tri, s.lam, s.u) for s in w.species]
+    osim = oracle_lib.OracleSim(w.mesh, w.dt * 3.0, sp, I.EPS0, I.MU0, I.C_LIGHT,
+                                spai_level=1, bz_ext=w.bz_ext)
+    T = osim.T
+    K = 6
+    crossed = 0
+    for _ in range(4):
+        before = [s.tri.copy() for s in osim.species]
+        seg0 = osim.segments
+        osim.step(1, "hc", record=K)
+        total = 0
+        for s, b in zip(osim.species, before):
+            alive = b >= 0
+            assert np.all(s.nseq[~alive] == 0)
+            assert np.all(s.nseq[alive] >= 1)
+            assert np.array_equal(s.seq[alive, 0], b[alive])
+            total += int(s.nseq.sum())
+            for p in np.nonzero(alive)[0]:
+                m = min(int(s.nseq[p]), K)
+                for k in range(1, m):
+                    assert s.seq[p, k] in T.tri_nbr[s.seq[p, k - 1]]
+                assert np.all(s.seq[p, m:] == -1)
+                if s.nseq[p] <= K and s.tri[p] >= 0:
+                    assert s.seq[p, m - 1] == s.tri[p]
+            crossed += int((s.nseq[alive] > 1).sum())
+        assert total == osim.segments - seg0
+    assert crossed > 1000
