@@ -283,9 +283,9 @@ fetd_status fetd_particles_get(fetd_sim *sim, int32_t species, int64_t capacity,
  * else FETD_E_STATE), for the species' particles alive after it, in the
  * order and count of fetd_particles_get: count[n] = the number of straight
  * pieces of each particle's move (1 = it stayed in its triangle), tris[n*K]
- * = the triangle of each of the first K pieces, -1 past count.  Valid until
- * the next step or sort.  Either array may be NULL; capacity counts
- * particles. */
+ * = the triangle of each of the first K pieces, -1 past count.  Kept by
+ * fetd_pic_step; steps taken in a batch do not update it.  Valid until the
+ * next step or sort.  Either array may be NULL; capacity counts particles. */
 fetd_status fetd_crossings_get(fetd_sim *sim, int32_t species, int64_t capacity, int32_t *count,
                                int32_t *tris, int64_t *n_out);
 
