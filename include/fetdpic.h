@@ -107,7 +107,8 @@ typedef struct {
 typedef struct {
     int32_t precision;    /* fetd_precision */
     double dt;            /* time step [s] */
-    double eps0, mu0, c;  /* vacuum constants [SI]; c enters the pushers */
+    double eps0, mu0, c;  /* vacuum constants [SI]; c enters the pushers
+                             (c^2 must lie in [1e-250, 1e250]) */
     int32_t spai_level;   /* >= 0: SPAI of [*eps] on the level-th power of its
                              sparsity graph (0 = diagonal); -1: exact inverse
                              (meshes with at most 4096 edges) */

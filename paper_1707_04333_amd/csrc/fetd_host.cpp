@@ -1097,7 +1097,10 @@ fetd_status fetd_mesh_create(const fetd_mesh_desc *mesh, const fetd_opts *opts, 
         g_last_error = "mesh has more than FETD_MAX_TRIS triangles";
         return FETD_E_ARG;
     }
+    // c^2 within [1e-250, 1e250]: the FP64 pushers' division by c^2 is
+    // correctly rounded on that range.
     if (!(opts->dt > 0) || !(opts->eps0 > 0) || !(opts->mu0 > 0) || !(opts->c > 0) ||
+        !(opts->c * opts->c >= 1e-250 && opts->c * opts->c <= 1e250) ||
         (opts->precision != FETD_FP64 && opts->precision != FETD_MIXED &&
          opts->precision != FETD_MIXED_F64FIELD) ||
         opts->spai_level < -1 || opts->spai_level > 4) {

@@ -66,6 +66,24 @@ def test_mesh_size_limit_without_device():
     assert b"FETD_MAX_TRIS" in L.fetd_last_error(None)
 
 
+def test_speed_of_light_range_without_device():
+    """c^2 outside [1e-250, 1e250] (the range on which the FP64 pushers'
+    division by c^2 is correctly rounded) is refused before device work."""
+    import numpy as np
+    from paper_1707_04333_amd import fetdpic
+    L = fetdpic.lib()
+    xy = np.array([0.0, 0.0, 1.0, 0.0, 0.0, 1.0])
+    tri = np.array([0, 1, 2], np.int32)
+    desc = fetdpic.MeshDesc(3, fetdpic._p(xy), 1, fetdpic._p(tri), None, None)
+    for c in (1e-126, 1e126, float("inf")):
+        opts = fetdpic.Opts(0, 1e-12, 8.8e-12, 1.26e-6, c, 1, 0, None, fetdpic.ALLOC_FN(),
+                            fetdpic.FREE_FN(), None, 64, 20, 0)
+        out = ctypes.c_void_p()
+        st = L.fetd_mesh_create(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(out))
+        assert st == fetdpic.FETD_E_ARG and not out.value, c
+        assert b"invalid options" in L.fetd_last_error(None)
+
+
 def test_tet_argument_errors_without_device():
     from paper_1707_04333_amd import fetd3
     L = fetd3.lib()
