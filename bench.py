@@ -83,30 +83,40 @@ def kernel_hash(src=KERNEL_SRC):
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(precision, traffic_file=TRAFFIC_FILE, src=KERNEL_SRC):
+def _same_launch(leg, tile, scan):
+    """A counter record applies to a leg run at the same tile and scan width
+    (when the record states them)."""
+    return ((tile is None or leg.get("tile") in (None, tile)) and
+            (scan is None or leg.get("scan") in (None, scan)))
+
+
+def measured_traffic(precision, traffic_file=TRAFFIC_FILE, src=KERNEL_SRC, tile=None, scan=None):
     """HBM bytes per particle launch from the committed rocprofv3 counter
     runs (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when
-    the kernel source changed since they were taken."""
+    the kernel source changed since they were taken or they were taken at
+    another tile or scan width."""
     try:
         rec = json.load(open(traffic_file))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_sha256_16") != kernel_hash(src):
         return None
-    return rec.get(precision, {}).get("hbm_bytes_per_launch")
+    leg = rec.get(precision, {})
+    return leg.get("hbm_bytes_per_launch") if _same_launch(leg, tile, scan) else None
 
 
-def measured_valu(precision, issue_file=ISSUE_FILE, src=KERNEL_SRC):
+def measured_valu(precision, issue_file=ISSUE_FILE, src=KERNEL_SRC, tile=None, scan=None):
     """VALU instructions (wavefront instructions) per particle launch from
     the committed SQ counter runs, or None when the kernel source changed
-    since they were taken."""
+    since they were taken or they were taken at another tile or scan."""
     try:
         rec = json.load(open(issue_file))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_sha256_16") != kernel_hash(src):
         return None
-    return rec.get(precision, {}).get("valu_per_launch")
+    leg = rec.get(precision, {})
+    return leg.get("valu_per_launch") if _same_launch(leg, tile, scan) else None
 
 
 def host_info():
@@ -143,11 +153,11 @@ def copy_ceiling_gbs(nbytes=1 << 30, reps=5):
     return fp.copy_ceiling(0, nbytes, reps)
 
 
-def run_gpu(w, precision, steps, warmup, pusher, resort=None):
+def run_gpu(w, precision, steps, warmup, pusher, resort=None, pin=(None, None)):
     """One workload in one precision.  The autotuner chooses the particle
-    tile and scan width, and the re-sort interval unless `resort` fixes it.
-    The timed window starts at a sorting step and covers `steps` steps
-    (inputs already on the device)."""
+    tile and scan width (unless `pin` fixes them), and the re-sort interval
+    unless `resort` fixes it.  The timed window starts at a sorting step
+    and covers `steps` steps (inputs already on the device)."""
     from paper_1707_04333_amd import fetdpic as fp
     log(f"{precision}: creating simulation ({w.n_particles} particles)")
     t0 = time.perf_counter()
@@ -161,7 +171,14 @@ def run_gpu(w, precision, steps, warmup, pusher, resort=None):
         resort = tuned["resort_every"]
     else:
         sim.set_resort(resort)
-    log(f"{precision}: tile {tuned['tile']}, scan {tuned['scan']} lanes, re-sort every {resort}")
+    if pin[0]:
+        sim.set_tile(pin[0])
+        tuned["tile"] = pin[0]
+    if pin[1]:
+        sim.set_scan(pin[1])
+        tuned["scan"] = pin[1]
+    log(f"{precision}: tile {tuned['tile']}, scan {tuned['scan']} lanes, re-sort every {resort}"
+        + (" (pinned)" if pin[0] or pin[1] else ""))
     # the autotuner leaves the order decayed: the next step sorts
     align = 0
     # warm-up: at least `warmup` steps, ending where the next step sorts
@@ -267,8 +284,16 @@ def run_batched(pusher, min_steps=100):
     wls = I.batched_sweep()
     n_p = sum(w.n_particles for w in wls)
     n_f = sum(w.mesh.n_tris for w in wls)
+    species_n = [[sp.n for sp in w.species] for w in wls]
     sims = [fp.from_workload(w, precision="mixed", spai_level=1, device=0) for w in wls]
     del wls
+    # the persistent particle launch of a step covers every (run, species)
+    # segment: its algorithmic bytes are the sum of the segments' launches
+    launch_bytes = 0
+    for s, ns in zip(sims, species_n):
+        inf = s.info()
+        launch_bytes += sum(particle_launch_bytes(n, inf["n_tris"], inf["n_edges"], True)
+                            for n in ns)
     ks = []
     for s in sims:
         s.diagnostics()
@@ -308,7 +333,9 @@ def run_batched(pusher, min_steps=100):
             "n_tris": n_f, "precision": "mixed", "value": n_p * steps / t_b,
             "ms_per_step": t_b / steps * 1e3, "steps": steps, "graph_replays": replays,
             "eager_steps_timed": eager, "separate_value": n_p * steps / t_s,
-            "batched_vs_separate": t_s / t_b, "resort_every": K, "gauss_rel": gauss}
+            "batched_vs_separate": t_s / t_b, "resort_every": K, "gauss_rel": gauss,
+            "particle_launch_algorithmic_bytes": launch_bytes,
+            "particle_bytes_gbs_step": launch_bytes / (t_b / steps) / 1e9}
 
 
 def cpu_baseline(w, pusher, steps=2, absorber=True):
@@ -569,17 +596,22 @@ def run_workload(name, args, pusher=None, resort=None):
     counted = (name == "large" and args.large_particles == 128_000_000) or \
         (name == "pair" and args.pairs == DEFAULT_PAIRS)
     tfile = TRAFFIC_FILE if name == "large" else PAIR_TRAFFIC_FILE
-    r64 = run_gpu(w, "fp64", args.steps, args.warmup, pusher, resort)
+    pin = (args.tile, args.scan)
+    r64 = run_gpu(w, "fp64", args.steps, args.warmup, pusher, resort, pin)
     issue = counted and name == "large"
     rec = {"fp64": leg_record(r64, n_p, args.steps, species_n, False,
-                              measured_traffic("fp64", tfile) if counted else None,
-                              measured_valu("fp64") if issue else None)}
+                              measured_traffic("fp64", tfile, tile=r64["tile"], scan=r64["scan"])
+                              if counted else None,
+                              measured_valu("fp64", tile=r64["tile"], scan=r64["scan"])
+                              if issue else None)}
     if not args.no_mixed:
         for prec in ("mixed", "mixed_f64field"):
-            r = run_gpu(w, prec, args.steps, args.warmup, pusher, resort or r64["resort"])
+            r = run_gpu(w, prec, args.steps, args.warmup, pusher, resort or r64["resort"], pin)
             rec[prec] = leg_record(r, n_p, args.steps, species_n, True,
-                                   measured_traffic(prec, tfile) if counted else None,
-                                   measured_valu(prec) if issue else None)
+                                   measured_traffic(prec, tfile, tile=r["tile"], scan=r["scan"])
+                                   if counted else None,
+                                   measured_valu(prec, tile=r["tile"], scan=r["scan"])
+                                   if issue else None)
             rec[prec]["vs_fp64"] = rec[prec]["value"] / rec["fp64"]["value"]
     cfg = workload_config(name, w, r64["info"], pusher, r64["resort"], args)
     return w, cfg, rec, r64
@@ -601,6 +633,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="pin the particle tile (a multiple of 256 in 512..2048) after the "
+                         "autotuner, e.g. to take counters at a fixed launch shape")
+    ap.add_argument("--scan", type=int, default=None, help="pin the scan width (8, 16, 64)")
     ap.add_argument("--timing-overhead", action="store_true",
                     help="step time of the pair plasma with each stage-timing mode, in "
                          "windows separated by idle (for a kernel trace)")

@@ -323,10 +323,13 @@ fetd_status fetd_stage_times(fetd_sim *sim, double *ms, int64_t *launches);
  * particles a block of the particle kernel takes, over how many lanes the
  * first-piece currents are summed before their LDS add, and how often the
  * triangle order is restored).  With T = min(trial_steps, 20):
- * 1. Tile: for each tile size (512, 1024, 2048 particles per block of 256
- *    threads; the current one first) sort, run T steps timing the particle
- *    stage with HIP events; keep the tile of least mean particle-stage time
- *    (ties keep the earlier candidate).
+ * 1. Tile: for each tile size (512 to 2048 particles per block of 256
+ *    threads in steps of 256; the current one first) sort, run T steps
+ *    timing the particle stage with HIP events; keep the tile of least mean
+ *    particle-stage time (ties keep the earlier candidate).  The tile sets
+ *    how many rounds of blocks a launch takes on the device's block slots:
+ *    on a launch of a few rounds the last, partly filled round is a
+ *    sizeable share of the time.
  * 2. Scan: the same for the scan group widths 64, 16 and 8 lanes, with that
  *    tile (the current width first).
  * 3. Cadence: sort once (timed), advance trial_steps steps timing the
@@ -334,7 +337,7 @@ fetd_status fetd_stage_times(fetd_sim *sim, double *ms, int64_t *launches);
  *    minimising (T_sort + sum_{j<K} T_particles(j)) / K over the candidates
  *    5, 10, 20, 40, 80, 160 (up to trial_steps).
  * out (or NULL) receives the three choices and the measured costs.  Every
- * trial step is an ordinary step: the simulation advances by 6 T +
+ * trial step is an ordinary step: the simulation advances by 10 T +
  * trial_steps steps, and its results do not depend on the choices beyond
  * FP64 summation order (not at all in deterministic mode). */
 typedef struct {
@@ -342,13 +345,13 @@ typedef struct {
     int32_t tile_particles;     /* chosen tile */
     int32_t scan_lanes;         /* chosen scan group width */
     double resort_cost_ms[6];   /* cost per step of K = 5, 10, 20, 40, 80, 160; -1 if untried */
-    double tile_cost_ms[3];     /* mean particle-stage ms per step, tiles 512, 1024, 2048 */
+    double tile_cost_ms[7];     /* mean particle-stage ms per step, tiles 512, 768, ..., 2048 */
     double scan_cost_ms[3];     /* the same for scan widths 64, 16, 8 */
 } fetd_tuning;
 fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps, fetd_tuning *out);
 
-/* Particles per block of the particle kernel for this run: 512, 1024 (the
- * default) or 2048, else FETD_E_ARG.  Takes effect at the next step (the
+/* Particles per block of the particle kernel for this run: a multiple of
+ * 256 from 512 to 2048 (default 1024), else FETD_E_ARG.  Takes effect at the next step (the
  * tiles' current-window homes are recomputed from the current order); a run
  * stepped in a batch keeps its own tile there (a batch rebuilds its tile
  * list when a member's tile changes). */

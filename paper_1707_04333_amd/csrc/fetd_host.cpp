@@ -2009,15 +2009,15 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, fetd
 
     // 1. Tile (the current one first, so a tie keeps it).
     {
-        int order[3] = {s->ppt, 0, 0};
-        for (int k = 0, j = 1; k < 3; ++k)
+        int order[kNumPPT] = {s->ppt};
+        for (int k = 0, j = 1; k < kNumPPT; ++k)
             if (kPPTChoices[k] != s->ppt) order[j++] = kPPTChoices[k];
         int best = s->ppt;
         double best_cost = std::numeric_limits<double>::max();
         for (int c : order) {
             double cost = 0.0;
             if ((st = set_ppt(s, c)) || (st = trial(cost))) return st;
-            for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < kNumPPT; ++k)
                 if (kPPTChoices[k] == c && out) out->tile_cost_ms[k] = cost;
             if (cost < best_cost) {
                 best_cost = cost;

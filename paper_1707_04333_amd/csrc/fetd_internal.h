@@ -16,11 +16,12 @@ constexpr int kBlock = 256;                // threads per block of the particle 
 #endif
 constexpr int kPPT = FETD_PPT;             // default particles per thread of the particle kernel
 // Particles per thread a run may use (its tile is ppt * kBlock particles,
-// a run-time value of the step arguments); per-tile slots are sized for the
-// smallest.
-constexpr int kPPTChoices[3] = {2, 4, 8};
+// 512 to 2048 in steps of 256, a run-time value of the step arguments);
+// per-tile slots are sized for the smallest.
+constexpr int kNumPPT = 7;
+constexpr int kPPTChoices[kNumPPT] = {2, 3, 4, 5, 6, 7, 8};
 constexpr int kMinPPT = 2;
-inline bool valid_ppt(int p) { return p == 2 || p == 4 || p == 8; }
+inline bool valid_ppt(int p) { return p >= kMinPPT && p <= 8; }
 // Lanes per group of the first-piece current scan (a run-time value).
 constexpr int kScanChoices[3] = {64, 16, 8};
 inline bool valid_scan(int w) { return w == 8 || w == 16 || w == 64; }

@@ -337,14 +337,14 @@ STAGES = ("faraday", "particles", "ampere", "spmv", "sort")
 
 
 AUTOTUNE_CANDIDATES = (5, 10, 20, 40, 80, 160)
-TILE_CANDIDATES = (512, 1024, 2048)
+TILE_CANDIDATES = (512, 768, 1024, 1280, 1536, 1792, 2048)
 SCAN_CANDIDATES = (64, 16, 8)
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("resort_every", ctypes.c_int32), ("tile_particles", ctypes.c_int32),
                 ("scan_lanes", ctypes.c_int32), ("resort_cost_ms", ctypes.c_double * 6),
-                ("tile_cost_ms", ctypes.c_double * 3), ("scan_cost_ms", ctypes.c_double * 3)]
+                ("tile_cost_ms", ctypes.c_double * 7), ("scan_cost_ms", ctypes.c_double * 3)]
 
 
 def autotune(h, pusher="boris", trial_steps=160, with_costs=False):

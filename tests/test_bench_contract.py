@@ -46,6 +46,22 @@ def test_traffic_is_null_for_another_source(tmp_path):
     assert bench.measured_traffic("mixed", bench.TRAFFIC_FILE, str(other)) is None
 
 
+def test_counter_records_apply_only_at_their_launch_shape():
+    """The committed counter records state the tile and scan width they were
+    taken at; a leg run at another shape gets no traffic or VALU figure."""
+    for precs, rec in ((("fp64", "mixed"), bench.TRAFFIC_FILE), (("fp64", "mixed"), bench.PAIR_TRAFFIC_FILE)):
+        for prec in precs:
+            leg = json.load(open(rec))[prec]
+            t, s = leg["tile"], leg["scan"]
+            assert bench.measured_traffic(prec, rec, tile=t, scan=s) == leg["hbm_bytes_per_launch"]
+            other = 512 if t != 512 else 768
+            assert bench.measured_traffic(prec, rec, tile=other, scan=s) is None
+            assert bench.measured_traffic(prec, rec, tile=t, scan=64 if s != 64 else 8) is None
+    leg = json.load(open(bench.ISSUE_FILE))["fp64"]
+    assert bench.measured_valu("fp64", tile=leg["tile"], scan=leg["scan"]) == leg["valu_per_launch"]
+    assert bench.measured_valu("fp64", tile=leg["tile"] - 256, scan=leg["scan"]) is None
+
+
 def test_cpu_baseline_record(oracle_lib):
     from paper_1707_04333_amd import inputs as I
     w = I.large_run(n_side=40, n_particles=5000, precision="fp64")

@@ -111,7 +111,7 @@ def test_batched_members_keep_their_tiles():
     member's tile as it was set."""
     fp = _fp()
     specs = [(12, 0.02, 3001, 0.3), (20, 0.03, 9000, 0.1), (9, 0.015, 1500, 1.0)]
-    tiles = (512, 2048, 1024)
+    tiles = (512, 2048, 1280)
     wls = [_wl(n, L, p, t, "fp64") for n, L, p, t in specs]
     batched = [fp.from_workload(w, spai_level=1, deterministic=True, resort_every=4)
                for w in wls]
@@ -162,7 +162,7 @@ def test_autotune_returns_argmin_and_keeps_the_run():
     """fetd_autotune picks the tile, the scan width and then the re-sort
     interval of least measured cost, and its trial steps are ordinary steps
     of the run: in deterministic mode the state equals, bit for bit, that of
-    a plain run of as many steps (3 x 20 tile trials, 3 x 20 scan trials, 40
+    a plain run of as many steps (7 x 20 tile trials, 3 x 20 scan trials, 40
     cadence trials)."""
     fp = _fp()
     w = _wl(n_side=24, length=0.038, n_pairs=40_000)
@@ -174,12 +174,12 @@ def test_autotune_returns_argmin_and_keeps_the_run():
     assert all(v > 0 for v in r["costs"].values())
     assert r["resort_every"] == min(cands, key=lambda c: r["costs"][c])
     tc = r["tile_costs"]
-    assert set(tc) == {512, 1024, 2048} and all(v > 0 for v in tc.values())
+    assert set(tc) == set(range(512, 2049, 256)) and all(v > 0 for v in tc.values())
     assert r["tile"] == min(tc, key=lambda c: tc[c]) and tuned.get_tile() == r["tile"]
     sc = r["scan_costs"]
     assert set(sc) == {64, 16, 8} and all(v > 0 for v in sc.values())
     assert r["scan"] == min(sc, key=lambda c: sc[c]) and tuned.get_scan() == r["scan"]
-    plain.step(6 * 20 + 40, "boris")
+    plain.step(10 * 20 + 40, "boris")
     _assert_bitwise(_state(tuned), _state(plain))
     tuned.step(7, "boris")
     plain.step(7, "boris")
@@ -188,7 +188,7 @@ def test_autotune_returns_argmin_and_keeps_the_run():
     plain.close()
 
 
-@pytest.mark.parametrize("tile,scan", [(512, 64), (2048, 8), (1024, 16)])
+@pytest.mark.parametrize("tile,scan", [(512, 64), (2048, 8), (1024, 16), (1280, 8), (1792, 16)])
 def test_every_tile_gives_the_same_run(tile, scan):
     """Deterministic mode: a run at each tile size and scan width equals the
     run at the defaults bit for bit (hot plasma, re-sorts, crossings)."""
@@ -203,8 +203,9 @@ def test_every_tile_gives_the_same_run(tile, scan):
     a.step(30, "hc")
     b.step(30, "hc")
     _assert_bitwise(_state(a), _state(b))
-    with pytest.raises(Exception):
-        b.set_tile(768)
+    for bad in (640, 256, 2304):
+        with pytest.raises(Exception):
+            b.set_tile(bad)
     with pytest.raises(Exception):
         b.set_scan(32)
     a.close()

@@ -57,10 +57,10 @@ def _compare_fields(osim, g, tol=1e-12):
         assert err <= tol, (name, err)
 
 
-@pytest.mark.parametrize("tile,scan", [(512, 64), (2048, 8), (1024, 16)])
+@pytest.mark.parametrize("tile,scan", [(512, 64), (2048, 8), (1024, 16), (1280, 8), (1792, 64)])
 def test_pair_plasma_fp64_parity_other_tiles(oracle_lib, tile, scan):
-    """The particle kernel at the other tile sizes (2 and 8 particles per
-    thread) and scan widths against the oracle: 20,011 particles (ragged
+    """The particle kernel at other tile sizes (2, 4, 5, 7 and 8 particles
+    per thread) and scan widths against the oracle: 20,011 particles (ragged
     last tile), re-sorts every 20 steps, 60 steps of Vay."""
     w = I.pair_plasma(n_side=24, length=0.038, n_pairs=20_011, theta=0.3, steps=60,
                       precision="fp64")
