@@ -274,25 +274,26 @@ def run_timing_overhead(args, window=160, reps=2):
             "overhead_vs_untimed": {k: min(v) / base - 1.0 for k, v in out.items()}}
 
 
-def run_batched(pusher, min_steps=100):
-    """64 uneven pair-plasma runs (mixed): batched with graph replay, timed
-    over whole replayed cycles of two re-sort intervals, against the same
-    runs stepped one by one for the same number of steps."""
+def run_batched(pusher, min_steps=100, precision="mixed"):
+    """64 uneven pair-plasma runs: batched with graph replay, timed over
+    whole replayed cycles of two re-sort intervals, against the same runs
+    stepped one by one for the same number of steps."""
     from paper_1707_04333_amd import fetdpic as fp
     from paper_1707_04333_amd import inputs as I
-    log("batched: generating 64 runs")
-    wls = I.batched_sweep()
+    log(f"batched ({precision}): generating 64 runs")
+    wls = I.batched_sweep(precision="fp64" if precision == "fp64" else "mixed")
     n_p = sum(w.n_particles for w in wls)
     n_f = sum(w.mesh.n_tris for w in wls)
     species_n = [[sp.n for sp in w.species] for w in wls]
-    sims = [fp.from_workload(w, precision="mixed", spai_level=1, device=0) for w in wls]
+    sims = [fp.from_workload(w, precision=precision, spai_level=1, device=0) for w in wls]
     del wls
     # the persistent particle launch of a step covers every (run, species)
     # segment: its algorithmic bytes are the sum of the segments' launches
     launch_bytes = 0
     for s, ns in zip(sims, species_n):
         inf = s.info()
-        launch_bytes += sum(particle_launch_bytes(n, inf["n_tris"], inf["n_edges"], True)
+        launch_bytes += sum(particle_launch_bytes(n, inf["n_tris"], inf["n_edges"],
+                                                  precision != "fp64")
                             for n in ns)
     ks = []
     for s in sims:
@@ -330,7 +331,7 @@ def run_batched(pusher, min_steps=100):
     log(f"batched: {steps} steps in {t_b:.3f} s ({replays} graph replays, {eager} eager steps), "
         f"separate {t_s:.3f} s")
     return {"workload": "batched_sweep_64", "n_runs": 64, "n_particles": n_p,
-            "n_tris": n_f, "precision": "mixed", "value": n_p * steps / t_b,
+            "n_tris": n_f, "precision": precision, "value": n_p * steps / t_b,
             "ms_per_step": t_b / steps * 1e3, "steps": steps, "graph_replays": replays,
             "eager_steps_timed": eager, "separate_value": n_p * steps / t_s,
             "batched_vs_separate": t_s / t_b, "resort_every": K, "gauss_rel": gauss,
@@ -637,6 +638,8 @@ def main():
                     help="pin the particle tile (a multiple of 256 in 512..2048) after the "
                          "autotuner, e.g. to take counters at a fixed launch shape")
     ap.add_argument("--scan", type=int, default=None, help="pin the scan width (8, 16, 64)")
+    ap.add_argument("--batched-precision", default="mixed", choices=("mixed", "fp64"),
+                    help="precision of --workload batched")
     ap.add_argument("--timing-overhead", action="store_true",
                     help="step time of the pair plasma with each stage-timing mode, in "
                          "windows separated by idle (for a kernel trace)")
@@ -670,7 +673,7 @@ def main():
         print(json.dumps(run_tet(args)))
         return
     if args.workload == "batched":
-        print(json.dumps(run_batched("boris")))
+        print(json.dumps(run_batched("boris", precision=args.batched_precision)))
         return
     name = args.workload
     log(f"generating workload {name}")
@@ -723,6 +726,8 @@ def main():
         out["pair_plasma"] = {"config": pcfg, **prec_rec}
     if not args.no_batched and name in ("large", "pair"):
         out["batched"] = run_batched("boris")
+        out["batched_fp64"] = run_batched("boris", precision="fp64")
+        out["batched"]["vs_fp64"] = out["batched"]["value"] / out["batched_fp64"]["value"]
     if not args.no_cpu and name in ("large", "pair"):
         log("timing the CPU oracle on the headline workload")
         out["cpu_baseline"] = cpu_baseline(w, cfg["pusher"])
