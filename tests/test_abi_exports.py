@@ -94,3 +94,41 @@ def test_tet_argument_errors_without_device():
     assert L.fetd3_pic_step(None, 1, 0) == -1
     assert L.fetd3_profile_mask(None, 2, 1) == -1
     L.fetd3_destroy(None)
+
+
+def _c_layout(header, structs, tmp_path):
+    """sizeof and offsetof of each struct's fields, from the C header as gcc
+    lays them out."""
+    import subprocess
+    lines = [f'#include "{header}"', "#include <stddef.h>", "#include <stdio.h>", "int main(void) {"]
+    for cname, fields in structs:
+        lines.append(f'    printf("%s %zu\\n", "{cname}", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'    printf("%s.%s %zu\\n", "{cname}", "{f}", offsetof({cname}, {f}));')
+    lines.append("    return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {k: int(v) for k, v in (ln.split() for ln in out.splitlines())}
+
+
+def test_binding_structs_match_the_headers(tmp_path):
+    """Every struct the Python bindings pass through the C-ABI has the size
+    and field offsets the public headers give it."""
+    from paper_1707_04333_amd import fetd3, fetdpic
+    pairs = [("fetdpic.h", [("fetd_mesh_desc", fetdpic.MeshDesc), ("fetd_opts", fetdpic.Opts),
+                            ("fetd_info", fetdpic.Info), ("fetd_diag", fetdpic.Diag),
+                            ("fetd_tuning", fetdpic.Tuning)]),
+             ("fetd3.h", [("fetd3_mesh_desc", fetd3.MeshDesc3), ("fetd3_opts", fetd3.Opts3),
+                          ("fetd3_diag", fetd3.Diag3)])]
+    renamed = {("fetd3_opts", "stream"): "hip_stream"}  # binding name -> C name
+    for header, structs in pairs:
+        spec = [(cname, [renamed.get((cname, f), f) for f, _ in py._fields_]) for cname, py in structs]
+        got = _c_layout(header, spec, tmp_path)
+        for cname, py in structs:
+            assert got[cname] == ctypes.sizeof(py), cname
+            for f, _ in py._fields_:
+                assert got[f"{cname}.{renamed.get((cname, f), f)}"] == getattr(py, f).offset, (cname, f)
