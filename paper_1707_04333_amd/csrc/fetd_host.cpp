@@ -2102,7 +2102,7 @@ fetd_status fetd_set_tile(fetd_sim *s, int32_t tile_particles)
 {
     if (!s) return FETD_E_ARG;
     if (tile_particles % kBlock != 0 || !valid_ppt(tile_particles / kBlock))
-        return s->fail(FETD_E_ARG, "tile_particles must be 512, 1024 or 2048");
+        return s->fail(FETD_E_ARG, "tile_particles must be a multiple of 256 from 512 to 2048");
     DeviceGuard g(s->device);
     return set_ppt(s, tile_particles / kBlock);
 }
