@@ -372,8 +372,12 @@ fetd_status fetd_set_resort(fetd_sim *sim, int32_t every);
 /* Batched stepping of many independent simulations (parameter sweeps):
  * every phase of a step (Faraday, particle stage, Ampere, SpMV) is one
  * persistent launch over the flattened work of all runs; with use_graph
- * the launch sequence of a full re-sort cycle is captured once in a HIP
- * graph and replayed.  All simulations must live on the same device and
+ * the launch sequence of a cycle of two re-sort intervals (2K steps) is
+ * captured in a HIP graph and replayed: once per pusher, phase in the
+ * re-sort interval and sort parity (the graph's sorts read and write fixed
+ * buffers), after one eager sorting step per pusher; a call whose steps
+ * cover a cycle from the next sort starts its graph there, a shorter one at
+ * its current phase, so calls of 2K steps replay from the third on.  All simulations must live on the same device and
  * stream and have the same precision; they stay individually usable
  * (fields_get, particles_get, diagnostics) between batch steps.  The batch
  * keeps pointers to the simulations: destroy it before them.  Re-sorting

@@ -2203,6 +2203,9 @@ struct fetd_batch {
     int resort_every = 20;
     hipGraphExec_t graph = nullptr;
     int graph_pusher = -1;
+    int graph_phase = -1;  // steps since the last sort (at most K) where the captured cycle starts
+    int graph_parity = -1; // sort parity where it starts (its sorts read and write fixed buffers)
+    unsigned warm = 0;  // pushers that have run an eager sorting step (all their kernels loaded)
     int64_t graph_captures = 0, graph_replays = 0, eager_steps = 0;
     std::string err;
 };
@@ -2306,11 +2309,13 @@ void batch_release(fetd_batch *b)
 fetd_status batch_enqueue(fetd_batch *b, int n, int pusher)
 {
     for (int it = 0; it < n; ++it) {
+        bool sorted = false;
         if (b->steps_since_sort >= b->resort_every) {
             for (fetd_sim *s : b->sims)
                 if (fetd_status st = sort_all(s, b->stream)) return batch_fail(b, st, s->err);
             b->parity ^= 1;
             b->steps_since_sort = 0;
+            sorted = true;
         }
         hipError_t e = launch_faraday_batched(b->stream, b->d_fields, b->d_tri_prefix, b->nrun,
                                               b->tri_blocks);
@@ -2331,31 +2336,53 @@ fetd_status batch_enqueue(fetd_batch *b, int n, int pusher)
             ++s->step;
             s->steps_since_sort = b->steps_since_sort;
         }
+        // a sorting step launches every kernel of a cycle; outside a
+        // capture that loads them, so later calls may capture at once
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (sorted && hipStreamIsCapturing(b->stream, &cs) == hipSuccess &&
+            cs == hipStreamCaptureStatusNone)
+            b->warm |= 1u << pusher;
     }
     return FETD_OK;
 }
 
-// Steps of a batch call in graph mode: eager steps up to the next sort; a
-// first full cycle eagerly (every kernel of the cycle is then loaded, which
-// a capture forbids doing); then whole cycles of 2 re-sort intervals
-// starting right before a sort (the particle buffers and the sort parity
-// return to their state), captured once and replayed; the rest eagerly.
+// Steps of a batch call in graph mode.  A cycle of 2K steps (K the re-sort
+// interval) from any phase (steps since the last sort) holds two sorts and
+// returns the particle buffers, the sort parity and the phase to where they
+// were, so it is captured once per pusher and phase and replayed.  Before a
+// pusher's first capture the batch runs eagerly up to and including a
+// sorting step (every kernel of a cycle is then loaded, which a capture
+// forbids doing).  A call that replays the existing graph at the current
+// phase does so at once; otherwise a call long enough first runs eagerly up
+// to the next sort (so graphs start right before a sort) and a shorter one
+// captures at the current phase, so a batch stepped in calls of 2K steps
+// replays from its third call at the latest.  The rest runs eagerly.
 fetd_status batch_graph_steps(fetd_batch *b, int left, int pusher)
 {
     const int K = b->resort_every;
-    const int lead = std::min(left, std::max(0, K - b->steps_since_sort));
-    if (fetd_status st = batch_enqueue(b, lead, pusher)) return st;
-    b->eager_steps += lead;
-    left -= lead;
     const int cycle = 2 * K;
-    if (left >= cycle && (!b->graph || b->graph_pusher != pusher)) {
-        if (b->graph) (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-        if (fetd_status st = batch_enqueue(b, cycle, pusher)) return st;
-        b->eager_steps += cycle;
-        left -= cycle;
+    if (left >= cycle && !((b->warm >> pusher) & 1u)) {
+        const int n = std::min(left, std::max(1, K - b->steps_since_sort + 1));
+        if (fetd_status st = batch_enqueue(b, n, pusher)) return st;
+        b->eager_steps += n;
+        left -= n;
     }
-    if (left >= cycle) {
+    if (left >= cycle && ((b->warm >> pusher) & 1u)) {
+        int phase = std::min(b->steps_since_sort, K);
+        const bool same = b->graph && b->graph_pusher == pusher && b->graph_phase == phase &&
+                          b->graph_parity == b->parity;
+        const int lead = K - phase;
+        if (!same && lead > 0 && left >= lead + cycle) {
+            if (fetd_status st = batch_enqueue(b, lead, pusher)) return st;
+            b->eager_steps += lead;
+            left -= lead;
+            phase = K;
+        }
+        if (b->graph && (b->graph_pusher != pusher || b->graph_phase != phase ||
+                         b->graph_parity != b->parity)) {
+            (void)hipGraphExecDestroy(b->graph);
+            b->graph = nullptr;
+        }
         if (!b->graph) {
             // capture with the host counters advanced as during replay
             const int save_parity = b->parity, save_since = b->steps_since_sort;
@@ -2387,6 +2414,8 @@ fetd_status batch_graph_steps(fetd_batch *b, int left, int pusher)
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
             b->graph_pusher = pusher;
+            b->graph_phase = phase;
+            b->graph_parity = b->parity;
             ++b->graph_captures;
         }
         while (left >= cycle) {
@@ -2394,9 +2423,9 @@ fetd_status batch_graph_steps(fetd_batch *b, int left, int pusher)
             if (e != hipSuccess) return batch_fail(b, FETD_E_HIP, hipGetErrorString(e));
             for (fetd_sim *s : b->sims) {
                 s->step += cycle;
-                s->steps_since_sort = K;
+                s->steps_since_sort = phase;
             }
-            b->steps_since_sort = K;
+            b->steps_since_sort = phase;
             ++b->graph_replays;
             left -= cycle;
         }

@@ -134,6 +134,37 @@ def test_batched_members_keep_their_tiles():
         s.close()
 
 
+def test_batch_stepped_in_short_calls_captures_a_graph():
+    """A batch stepped in calls of two re-sort intervals (2K steps, too few
+    for a lead, an eager cycle and a captured cycle in one call) captures
+    its graph on a later call and replays it; a call of K steps between
+    replays (one sort: the buffers' parity flips) and a change of pusher
+    each make it capture again; the runs stay bit for bit the runs stepped
+    one by one."""
+    fp = _fp()
+    specs = [(12, 0.02, 3001, 0.3), (16, 0.025, 6000, 0.1)]
+    wls = [_wl(n, L, p, t, "fp64") for n, L, p, t in specs]
+    K = 6
+    batched = [fp.from_workload(w, spai_level=1, deterministic=True, resort_every=K)
+               for w in wls]
+    single = [fp.from_workload(w, spai_level=1, deterministic=True, resort_every=K)
+              for w in wls]
+    b = fp.Batch(batched, use_graph=True)
+    plan = [("hc", 3), ("hc", 2 * K), ("hc", 2 * K), ("hc", 2 * K), ("hc", K), ("hc", 2 * K),
+            ("vay", 2 * K), ("vay", 2 * K), ("vay", 2 * K + 5)]
+    for pusher, n in plan:
+        b.step(n, pusher)
+        for s in single:
+            s.step(n, pusher)
+    st = b.stats()
+    assert st["graph_captures"] >= 3 and st["graph_replays"] >= 4, st
+    for gb, gs in zip(batched, single):
+        _assert_bitwise(_state(gb), _state(gs))
+    b.close()
+    for s in batched + single:
+        s.close()
+
+
 def test_deterministic_save_and_resume():
     fp = _fp()
     w = _wl()
