@@ -381,7 +381,8 @@ fetd_status fetd_set_resort(fetd_sim *sim, int32_t every);
  * stream and have the same precision; they stay individually usable
  * (fields_get, particles_get, diagnostics) between batch steps.  The batch
  * keeps pointers to the simulations: destroy it before them.  Re-sorting
- * follows resort_every of the first simulation.  Members must also agree
+ * follows resort_every of the first simulation as it was when the batch was
+ * created.  Members must also agree
  * on the deterministic option.  The batch runs on a non-blocking stream
  * of its own and orders itself after the members' earlier work and before
  * their later work with events, so a graph can be captured also when the
