@@ -377,8 +377,9 @@ fetd_status fetd_set_resort(fetd_sim *sim, int32_t every);
  * re-sort interval and sort parity (the graph's sorts read and write fixed
  * buffers), after one eager sorting step per pusher; a call whose steps
  * cover a cycle from the next sort starts its graph there, a shorter one at
- * its current phase, so calls of 2K steps replay from the third on.  All simulations must live on the same device and
- * stream and have the same precision; they stay individually usable
+ * its current phase, so calls of 2K steps replay from the third on.  All
+ * simulations must live on the same device and stream, have the same
+ * precision and appear once each (else FETD_E_ARG); they stay individually usable
  * (fields_get, particles_get, diagnostics) between batch steps.  The batch
  * keeps pointers to the simulations: destroy it before them.  Re-sorting
  * follows resort_every of the first simulation as it was when the batch was

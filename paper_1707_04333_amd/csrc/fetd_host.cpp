@@ -2452,6 +2452,14 @@ fetd_status fetd_batch_create(fetd_sim *const *sims, int32_t n, int32_t use_grap
             g_last_error = "invalid batch arguments";
             return FETD_E_ARG;
         }
+    {
+        std::vector<fetd_sim *> seen(sims, sims + n);
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) {
+            g_last_error = "a simulation appears twice in the batch";
+            return FETD_E_ARG;
+        }
+    }
     fetd_batch *b = new (std::nothrow) fetd_batch();
     if (!b) return FETD_E_OOM;
     b->sims.assign(sims, sims + n);

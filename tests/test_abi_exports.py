@@ -49,6 +49,20 @@ def test_argument_errors_without_device():
     L.fetd_destroy(None)
 
 
+def test_batch_arguments_without_device():
+    """fetd_batch_create refuses an empty list, a null member and a member
+    listed twice before it touches any simulation or device."""
+    from paper_1707_04333_amd import fetdpic
+    L = fetdpic.lib()
+    out = ctypes.c_void_p()
+    two = (ctypes.c_void_p * 2)(0x1000, 0x1000)  # never dereferenced
+    assert L.fetd_batch_create(two, 2, 1, ctypes.byref(out)) == fetdpic.FETD_E_ARG
+    assert b"twice" in L.fetd_last_error(None) and not out.value
+    null = (ctypes.c_void_p * 2)(0x1000, None)
+    assert L.fetd_batch_create(null, 2, 1, ctypes.byref(out)) == fetdpic.FETD_E_ARG
+    assert L.fetd_batch_create(two, 0, 1, ctypes.byref(out)) == fetdpic.FETD_E_ARG
+
+
 def test_mesh_size_limit_without_device():
     """A mesh beyond FETD_MAX_TRIS (the particle kernel's 32-bit table
     offsets) is refused before any array is read or a device is queried."""
