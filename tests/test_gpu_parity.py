@@ -114,6 +114,40 @@ def test_cyclotron_fp64_parity(oracle_lib, pusher):
     g.close()
 
 
+@pytest.mark.parametrize("pusher", ["boris", "boris_tan", "vay", "hc"])
+def test_fp64_particle_update_bitwise_over_momentum_range(oracle_lib, pusher):
+    """With the fields equal on both sides (no self-field: weight 0; uniform
+    Bz = 1 T, E = 0), the FP64 particle update is the oracle's bit for bit
+    over the whole range of momenta the pushers' reduced square roots and
+    divisions by c^2 are claimed for: |u| from exactly 0 and 1e-160 m/s (u.u
+    below the smallest normal) to 1e15 m/s (gamma 3.3e6), 100 steps."""
+    import dataclasses
+    w = I.cyclotron()
+    sp = w.species[0]
+    rng = np.random.default_rng(4242)
+    n = sp.tri.shape[0]
+    mags = np.concatenate([[0.0, 0.0, 1e-160, 1e-155, 1e-150, 1e-120, 1e-60, 1e-10, 1.0, 1e3],
+                           10.0 ** rng.uniform(-150.0, 15.0, n - 10)])
+    ang = rng.uniform(0.0, 2.0 * np.pi, n)
+    u = np.stack([mags * np.cos(ang), mags * np.sin(ang)], axis=1)
+    u[1] = [0.0, -0.0]
+    w = dataclasses.replace(w, species=[dataclasses.replace(sp, w=0.0, u=u)])
+    osim = _oracle_sim(oracle_lib, w, 2)
+    g = _gpu_sim(w, 2)
+    for _ in range(4):
+        osim.step(25, pusher)
+        g.step(25, pusher)
+        s = osim.species[0]
+        gp = g.particles(0)
+        alive = np.nonzero(s.tri >= 0)[0]
+        assert np.array_equal(gp["id"], alive)
+        assert np.array_equal(gp["tri"], s.tri[alive]) and np.array_equal(gp["slot"], s.slot[alive])
+        assert np.array_equal(gp["lam"], s.lam[alive])
+        assert np.array_equal(gp["u"], s.u[alive])
+    assert g.diagnostics()["n_segments"] == osim.segments
+    g.close()
+
+
 @pytest.mark.parametrize("pusher", ["boris", "hc"])
 def test_pair_plasma_fp64_parity(oracle_lib, pusher):
     """Self-consistent pair plasma on a torus spanning many tiles and a
