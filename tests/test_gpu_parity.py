@@ -148,6 +148,31 @@ def test_fp64_particle_update_bitwise_over_momentum_range(oracle_lib, pusher):
     g.close()
 
 
+@pytest.mark.parametrize("pusher", ["boris", "vay", "hc"])
+def test_fp64_particle_update_bitwise_with_applied_field(oracle_lib, pusher):
+    """The same with an electric field: the boosted oscillator's affine
+    restoring E_y and uniform B_z (weight 0, so the fields are the applied
+    ones on both sides), 3,000 positrons drifting at gamma 2, 5 and 10 across
+    a periodic seam: gather, push, move and crossings bit for bit, 200 steps."""
+    import dataclasses
+    w = I.boosted_oscillator(n_particles=3000)
+    w = dataclasses.replace(w, species=[dataclasses.replace(sp, w=0.0) for sp in w.species])
+    osim = _oracle_sim(oracle_lib, w, 1)
+    g = _gpu_sim(w, 1)
+    for _ in range(4):
+        osim.step(50, pusher)
+        g.step(50, pusher)
+        s = osim.species[0]
+        gp = g.particles(0)
+        alive = np.nonzero(s.tri >= 0)[0]
+        assert np.array_equal(gp["id"], alive)
+        assert np.array_equal(gp["tri"], s.tri[alive]) and np.array_equal(gp["slot"], s.slot[alive])
+        assert np.array_equal(gp["lam"], s.lam[alive])
+        assert np.array_equal(gp["u"], s.u[alive])
+    assert g.diagnostics()["n_segments"] == osim.segments
+    g.close()
+
+
 @pytest.mark.parametrize("pusher", ["boris", "hc"])
 def test_pair_plasma_fp64_parity(oracle_lib, pusher):
     """Self-consistent pair plasma on a torus spanning many tiles and a
