@@ -83,14 +83,16 @@ def kernel_hash(src=KERNEL_SRC):
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def _same_launch(leg, tile, scan):
-    """A counter record applies to a leg run at the same tile and scan width
-    (when the record states them)."""
+def _same_launch(leg, tile, scan, defer=None):
+    """A counter record applies to a leg run at the same tile, scan width
+    and exit mode (when the record states them)."""
     return ((tile is None or leg.get("tile") in (None, tile)) and
-            (scan is None or leg.get("scan") in (None, scan)))
+            (scan is None or leg.get("scan") in (None, scan)) and
+            (defer is None or leg.get("defer_exits") in (None, defer)))
 
 
-def measured_traffic(precision, traffic_file=TRAFFIC_FILE, src=KERNEL_SRC, tile=None, scan=None):
+def measured_traffic(precision, traffic_file=TRAFFIC_FILE, src=KERNEL_SRC, tile=None, scan=None,
+                     defer=None):
     """HBM bytes per particle launch from the committed rocprofv3 counter
     runs (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when
     the kernel source changed since they were taken or they were taken at
@@ -102,10 +104,11 @@ def measured_traffic(precision, traffic_file=TRAFFIC_FILE, src=KERNEL_SRC, tile=
     if rec.get("kernel_sha256_16") != kernel_hash(src):
         return None
     leg = rec.get(precision, {})
-    return leg.get("hbm_bytes_per_launch") if _same_launch(leg, tile, scan) else None
+    return leg.get("hbm_bytes_per_launch") if _same_launch(leg, tile, scan, defer) else None
 
 
-def measured_valu(precision, issue_file=ISSUE_FILE, src=KERNEL_SRC, tile=None, scan=None):
+def measured_valu(precision, issue_file=ISSUE_FILE, src=KERNEL_SRC, tile=None, scan=None,
+                  defer=None):
     """VALU instructions (wavefront instructions) per particle launch from
     the committed SQ counter runs, or None when the kernel source changed
     since they were taken or they were taken at another tile or scan."""
@@ -116,7 +119,7 @@ def measured_valu(precision, issue_file=ISSUE_FILE, src=KERNEL_SRC, tile=None, s
     if rec.get("kernel_sha256_16") != kernel_hash(src):
         return None
     leg = rec.get(precision, {})
-    return leg.get("valu_per_launch") if _same_launch(leg, tile, scan) else None
+    return leg.get("valu_per_launch") if _same_launch(leg, tile, scan, defer) else None
 
 
 def host_info():
@@ -153,7 +156,7 @@ def copy_ceiling_gbs(nbytes=1 << 30, reps=5):
     return fp.copy_ceiling(0, nbytes, reps)
 
 
-def run_gpu(w, precision, steps, warmup, pusher, resort=None, pin=(None, None)):
+def run_gpu(w, precision, steps, warmup, pusher, resort=None, pin=(None, None, None)):
     """One workload in one precision.  The autotuner chooses the particle
     tile and scan width (unless `pin` fixes them), and the re-sort interval
     unless `resort` fixes it.  The timed window starts at a sorting step
@@ -177,8 +180,13 @@ def run_gpu(w, precision, steps, warmup, pusher, resort=None, pin=(None, None)):
     if pin[1]:
         sim.set_scan(pin[1])
         tuned["scan"] = pin[1]
-    log(f"{precision}: tile {tuned['tile']}, scan {tuned['scan']} lanes, re-sort every {resort}"
-        + (" (pinned)" if pin[0] or pin[1] else ""))
+    if pin[2] is not None and precision != "fp64":
+        sim.set_defer_exits(pin[2])
+        tuned["defer_exits"] = pin[2]
+    log(f"{precision}: tile {tuned['tile']}, scan {tuned['scan']} lanes, exits "
+        f"{'deferred' if tuned['defer_exits'] or precision == 'fp64' else 'traced'}, "
+        f"re-sort every {resort}" + (" (pinned)" if pin[0] or pin[1] or pin[2] is not None
+                                     else ""))
     # the autotuner leaves the order decayed: the next step sorts
     align = 0
     # warm-up: at least `warmup` steps, ending where the next step sorts
@@ -209,7 +217,7 @@ def run_gpu(w, precision, steps, warmup, pusher, resort=None, pin=(None, None)):
     return dict(elapsed=t1 - t0, particles=particles, stages=stages, stage_steps=stage_steps,
                 diag=diag, info=info, resort=resort, warmup_steps=w_steps,
                 sorts_timed=int(math.ceil(steps / resort)), tile=tuned["tile"],
-                scan=tuned["scan"])
+                scan=tuned["scan"], defer=int(tuned["defer_exits"] or precision == "fp64"))
 
 
 def leg_record(r, n_p, steps, species_n, fp32, traffic=None, valu=None):
@@ -222,7 +230,7 @@ def leg_record(r, n_p, steps, species_n, fp32, traffic=None, valu=None):
     achieved = per_launch / avg_s / 1e9
     return {"value": n_p * steps / r["elapsed"], "ms_per_step": r["elapsed"] / steps * 1e3,
             "gauss_rel": r["diag"]["gauss_rel"], "resort_every": r["resort"],
-            "tile": r["tile"], "scan_lanes": r["scan"],
+            "tile": r["tile"], "scan_lanes": r["scan"], "defer_exits": r["defer"],
             "sorts_in_timed_steps": r["sorts_timed"],
             "roofline": {"bound": "hbm", "kernel": "k_particle_step", "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -597,22 +605,22 @@ def run_workload(name, args, pusher=None, resort=None):
     counted = (name == "large" and args.large_particles == 128_000_000) or \
         (name == "pair" and args.pairs == DEFAULT_PAIRS)
     tfile = TRAFFIC_FILE if name == "large" else PAIR_TRAFFIC_FILE
-    pin = (args.tile, args.scan)
+    pin = (args.tile, args.scan, args.defer_exits)
     r64 = run_gpu(w, "fp64", args.steps, args.warmup, pusher, resort, pin)
     issue = counted and name == "large"
     rec = {"fp64": leg_record(r64, n_p, args.steps, species_n, False,
-                              measured_traffic("fp64", tfile, tile=r64["tile"], scan=r64["scan"])
-                              if counted else None,
-                              measured_valu("fp64", tile=r64["tile"], scan=r64["scan"])
-                              if issue else None)}
+                              measured_traffic("fp64", tfile, tile=r64["tile"], scan=r64["scan"],
+                                               defer=r64["defer"]) if counted else None,
+                              measured_valu("fp64", tile=r64["tile"], scan=r64["scan"],
+                                            defer=r64["defer"]) if issue else None)}
     if not args.no_mixed:
         for prec in ("mixed", "mixed_f64field"):
             r = run_gpu(w, prec, args.steps, args.warmup, pusher, resort or r64["resort"], pin)
             rec[prec] = leg_record(r, n_p, args.steps, species_n, True,
-                                   measured_traffic(prec, tfile, tile=r["tile"], scan=r["scan"])
-                                   if counted else None,
-                                   measured_valu(prec, tile=r["tile"], scan=r["scan"])
-                                   if issue else None)
+                                   measured_traffic(prec, tfile, tile=r["tile"], scan=r["scan"],
+                                                    defer=r["defer"]) if counted else None,
+                                   measured_valu(prec, tile=r["tile"], scan=r["scan"],
+                                                 defer=r["defer"]) if issue else None)
             rec[prec]["vs_fp64"] = rec[prec]["value"] / rec["fp64"]["value"]
     cfg = workload_config(name, w, r64["info"], pusher, r64["resort"], args)
     return w, cfg, rec, r64
@@ -638,6 +646,8 @@ def main():
                     help="pin the particle tile (a multiple of 256 in 512..2048) after the "
                          "autotuner, e.g. to take counters at a fixed launch shape")
     ap.add_argument("--scan", type=int, default=None, help="pin the scan width (8, 16, 64)")
+    ap.add_argument("--defer-exits", type=int, default=None, choices=(0, 1),
+                    help="pin the FP32 legs' exit mode (FP64 always defers)")
     ap.add_argument("--batched-precision", default="mixed", choices=("mixed", "fp64"),
                     help="precision of --workload batched")
     ap.add_argument("--timing-overhead", action="store_true",
@@ -701,7 +711,7 @@ def main():
         "roofline": f64["roofline"],
         "valu_issue": f64["valu_issue"],
         "tuning": {"tile": f64["tile"], "scan_lanes": f64["scan_lanes"],
-                   "resort_every": f64["resort_every"]},
+                   "defer_exits": f64["defer_exits"], "resort_every": f64["resort_every"]},
         "stage_ms_per_step": f64["stage_ms_per_step"],
         "gauss_rel": f64["gauss_rel"],
         "hbm_gbs_step": f64["hbm_gbs_step"],

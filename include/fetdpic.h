@@ -332,21 +332,26 @@ fetd_status fetd_stage_times(fetd_sim *sim, double *ms, int64_t *launches);
  *    sizeable share of the time.
  * 2. Scan: the same for the scan group widths 64, 16 and 8 lanes, with that
  *    tile (the current width first).
- * 3. Cadence: sort once (timed), advance trial_steps steps timing the
+ * 3. Deferred exits (FP32 particles only): the same for off and on (the
+ *    current setting first); see fetd_set_defer_exits.
+ * 4. Cadence: sort once (timed), advance trial_steps steps timing the
  *    particle stage of every step, and set the re-sort interval K
  *    minimising (T_sort + sum_{j<K} T_particles(j)) / K over the candidates
  *    5, 10, 20, 40, 80, 160 (up to trial_steps).
  * out (or NULL) receives the three choices and the measured costs.  Every
- * trial step is an ordinary step: the simulation advances by 10 T +
+ * trial step is an ordinary step: the simulation advances by 10 T (FP32
+ * particles: 12 T) +
  * trial_steps steps, and its results do not depend on the choices beyond
  * FP64 summation order (not at all in deterministic mode). */
 typedef struct {
     int32_t resort_every;       /* chosen re-sort interval K */
     int32_t tile_particles;     /* chosen tile */
     int32_t scan_lanes;         /* chosen scan group width */
+    int32_t defer_exits;        /* chosen exit mode (FP32 particles; 1 in FP64) */
     double resort_cost_ms[6];   /* cost per step of K = 5, 10, 20, 40, 80, 160; -1 if untried */
     double tile_cost_ms[7];     /* mean particle-stage ms per step, tiles 512, 768, ..., 2048 */
     double scan_cost_ms[3];     /* the same for scan widths 64, 16, 8 */
+    double defer_cost_ms[2];    /* the same for deferred exits off, on; -1 if untried (FP64) */
 } fetd_tuning;
 fetd_status fetd_autotune(fetd_sim *sim, int32_t pusher, int32_t trial_steps, fetd_tuning *out);
 
@@ -365,6 +370,18 @@ fetd_status fetd_get_tile(fetd_sim *sim, int32_t *tile_particles);
  * mode). */
 fetd_status fetd_set_scan(fetd_sim *sim, int32_t scan_lanes);
 fetd_status fetd_get_scan(fetd_sim *sim, int32_t *scan_lanes);
+
+/* Deferred exits (FP32 particles; FP64 always defers, and a batched step
+ * never does in FP32): the particle kernel's first pass decides by
+ * comparison which moves stay inside their triangle, with a margin of
+ * 2^-20 above the error of the FP32 reciprocal, so the stays are exactly
+ * the moves the full first piece would end inside, and traces the others
+ * from their start after the pass; off, it traces every particle's first
+ * piece in the pass.  On pays where few particles cross an edge per step.
+ * The results are the same either way up to FP64 summation order (bit for
+ * bit in deterministic mode).  on: 0 or 1, else FETD_E_ARG. */
+fetd_status fetd_set_defer_exits(fetd_sim *sim, int32_t on);
+fetd_status fetd_get_defer_exits(fetd_sim *sim, int32_t *on);
 
 /* Set the re-sort interval directly (k >= 1). */
 fetd_status fetd_set_resort(fetd_sim *sim, int32_t every);

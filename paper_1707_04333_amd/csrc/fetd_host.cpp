@@ -131,6 +131,7 @@ struct fetd_sim {
     int xcap = 0;                     // crossing record: pieces kept per particle (0 = off)
     int32_t *d_xcount = nullptr, *d_xtris = nullptr;  // [p_cap], [p_cap * xcap]
     int scan = 64;                    // lanes per group of the first-piece current scan
+    int defer = 0;                    // FP32 particles: deferred exits
     int64_t block_count_cap = 0;  // blocks covered by d_block_counts
     double *d_q = nullptr, *d_divd = nullptr, *d_partial = nullptr;
     // field probes
@@ -816,6 +817,13 @@ fetd_status sort_all(fetd_sim *s, hipStream_t stream)
 }
 
 // Lanes per group of the particle kernel's first-piece current scan.
+fetd_status set_defer(fetd_sim *s, int on)
+{
+    if (on != 0 && on != 1) return s->fail(FETD_E_ARG, "defer_exits must be 0 or 1");
+    s->defer = on;
+    return FETD_OK;
+}
+
 fetd_status set_scan(fetd_sim *s, int lanes)
 {
     if (!valid_scan(lanes)) return s->fail(FETD_E_ARG, "scan_lanes must be 8, 16 or 64");
@@ -984,6 +992,7 @@ StepArgs step_args(const fetd_sim *s, const Species &sp, int pbuf)
     a.tile_home = s->d_tile_home + sp.bc_offset;
     a.ppt = s->ppt;
     a.scan = s->scan;
+    a.defer = s->defer;
     a.xcap = s->xcap;
     a.xcount = s->d_xcount ? s->d_xcount + sp.offset : nullptr;
     a.xtris = s->d_xtris ? s->d_xtris + sp.offset * s->xcap : nullptr;
@@ -1995,6 +2004,7 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, fetd
         for (double &c : out->resort_cost_ms) c = -1.0;
         for (double &c : out->tile_cost_ms) c = -1.0;
         for (double &c : out->scan_cost_ms) c = -1.0;
+        for (double &c : out->defer_cost_ms) c = -1.0;
     }
     // Mean particle-stage ms per step over short_steps steps from a fresh sort.
     auto trial = [&](double &cost) -> fetd_status {
@@ -2045,8 +2055,26 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, fetd
         }
         if ((st = set_scan(s, best))) return st;
     }
+    // 3. Deferred exits (FP32 particles; FP64 always defers), with that tile
+    //    and width.
+    if (s->fp32()) {
+        const int first = s->defer;
+        int best = first;
+        double best_cost = std::numeric_limits<double>::max();
+        for (int c : {first, 1 - first}) {
+            double cost = 0.0;
+            if ((st = set_defer(s, c)) || (st = trial(cost))) return st;
+            if (out) out->defer_cost_ms[c] = cost;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = c;
+            }
+        }
+        if ((st = set_defer(s, best))) return st;
+    }
 
-    // 3. Re-sort cadence: one timed sort, then the particle stage of every
+
+    // 4. Re-sort cadence: one timed sort, then the particle stage of every
     //    step as the order decays.
     if ((st = fetd_profile_mask(s, (1 << 1) | (1 << 4), 1))) return st;
     {
@@ -2081,6 +2109,7 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, fetd
         out->resort_every = best;
         out->tile_particles = s->ppt * kBlock;
         out->scan_lanes = s->scan;
+        out->defer_exits = s->defer;
     }
     return FETD_OK;
 }
@@ -2095,6 +2124,19 @@ fetd_status fetd_get_scan(fetd_sim *s, int32_t *scan_lanes)
 {
     if (!s || !scan_lanes) return FETD_E_ARG;
     *scan_lanes = s->scan;
+    return FETD_OK;
+}
+
+fetd_status fetd_set_defer_exits(fetd_sim *s, int32_t on)
+{
+    if (!s) return FETD_E_ARG;
+    return set_defer(s, on);
+}
+
+fetd_status fetd_get_defer_exits(fetd_sim *s, int32_t *on)
+{
+    if (!s || !on) return FETD_E_ARG;
+    *on = s->defer;
     return FETD_OK;
 }
 

@@ -77,6 +77,7 @@ struct StepArgs {
     const int32_t *pid;            // load ids (for error reports)
     int ppt;                       // particles per thread: a tile is ppt * kBlock particles
     int scan;                      // lanes per group of the first-piece current scan (8, 16, 64)
+    int defer;                     // FP32: deferred exits (FP64 always defers; batched: never)
     int32_t *xcount;               // crossing record, or null: pieces of each particle's move
     int32_t *xtris;                // [n * xcap]: the triangle of each of the first xcap pieces
     int xcap;

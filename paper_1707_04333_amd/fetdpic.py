@@ -103,6 +103,8 @@ def lib():
                     "fetd_set_tile": [P, ctypes.c_int32],
                     "fetd_get_tile": [P, P],
                     "fetd_set_scan": [P, ctypes.c_int32],
+                    "fetd_set_defer_exits": [P, ctypes.c_int32],
+                    "fetd_get_defer_exits": [P, P],
                     "fetd_crossings_get": [P, ctypes.c_int32, ctypes.c_int64, P, P, P],
                     "fetd_get_scan": [P, P],
                     "fetd_set_resort": [P, ctypes.c_int32],
@@ -343,26 +345,40 @@ SCAN_CANDIDATES = (64, 16, 8)
 
 class Tuning(ctypes.Structure):
     _fields_ = [("resort_every", ctypes.c_int32), ("tile_particles", ctypes.c_int32),
-                ("scan_lanes", ctypes.c_int32), ("resort_cost_ms", ctypes.c_double * 6),
-                ("tile_cost_ms", ctypes.c_double * 7), ("scan_cost_ms", ctypes.c_double * 3)]
+                ("scan_lanes", ctypes.c_int32), ("defer_exits", ctypes.c_int32),
+                ("resort_cost_ms", ctypes.c_double * 6),
+                ("tile_cost_ms", ctypes.c_double * 7), ("scan_cost_ms", ctypes.c_double * 3),
+                ("defer_cost_ms", ctypes.c_double * 2)]
 
 
 def autotune(h, pusher="boris", trial_steps=160, with_costs=False):
-    """fetd_autotune: tunes the tile, the scan group width, then the
-    re-sort interval.  Returns the chosen re-sort interval; with_costs, a
-    dict with the three choices ("resort_every", "tile", "scan") and the
-    measured cost in ms per step of every candidate tried ("costs",
-    "tile_costs", "scan_costs")."""
+    """fetd_autotune: tunes the tile, the scan group width, the exit mode
+    (FP32 particles), then the re-sort interval.  Returns the chosen re-sort
+    interval; with_costs, a dict with the choices ("resort_every", "tile",
+    "scan", "defer_exits") and the measured cost in ms per step of every
+    candidate tried ("costs", "tile_costs", "scan_costs", "defer_costs")."""
     pid = PUSHERS[pusher] if isinstance(pusher, str) else int(pusher)
     t = Tuning()
     _check(lib().fetd_autotune(h, pid, int(trial_steps), ctypes.byref(t)), h)
     if not with_costs:
         return t.resort_every
     return {"resort_every": t.resort_every, "tile": t.tile_particles, "scan": t.scan_lanes,
+            "defer_exits": t.defer_exits,
             "costs": {c: float(v) for c, v in zip(AUTOTUNE_CANDIDATES, t.resort_cost_ms)
                       if v >= 0},
             "tile_costs": {c: float(v) for c, v in zip(TILE_CANDIDATES, t.tile_cost_ms)},
-            "scan_costs": {c: float(v) for c, v in zip(SCAN_CANDIDATES, t.scan_cost_ms)}}
+            "scan_costs": {c: float(v) for c, v in zip(SCAN_CANDIDATES, t.scan_cost_ms)},
+            "defer_costs": {c: float(v) for c, v in enumerate(t.defer_cost_ms) if v >= 0}}
+
+
+def set_defer_exits(h, on):
+    _check(lib().fetd_set_defer_exits(h, int(on)), h)
+
+
+def get_defer_exits(h):
+    out = ctypes.c_int32()
+    _check(lib().fetd_get_defer_exits(h, ctypes.byref(out)), h)
+    return out.value
 
 
 def set_tile(h, tile_particles):
@@ -501,6 +517,12 @@ class Sim:
 
     def set_resort(self, every):
         set_resort(self.h, every)
+
+    def set_defer_exits(self, on):
+        set_defer_exits(self.h, on)
+
+    def get_defer_exits(self):
+        return get_defer_exits(self.h)
 
     def set_tile(self, tile_particles):
         set_tile(self.h, tile_particles)

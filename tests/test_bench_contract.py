@@ -47,8 +47,9 @@ def test_traffic_is_null_for_another_source(tmp_path):
 
 
 def test_counter_records_apply_only_at_their_launch_shape():
-    """The committed counter records state the tile and scan width they were
-    taken at; a leg run at another shape gets no traffic or VALU figure."""
+    """The committed counter records state the tile, scan width and exit
+    mode they were taken at; a leg run at another shape gets no traffic or
+    VALU figure."""
     for precs, rec in ((("fp64", "mixed"), bench.TRAFFIC_FILE), (("fp64", "mixed"), bench.PAIR_TRAFFIC_FILE)):
         for prec in precs:
             leg = json.load(open(rec))[prec]
@@ -57,6 +58,9 @@ def test_counter_records_apply_only_at_their_launch_shape():
             other = 512 if t != 512 else 768
             assert bench.measured_traffic(prec, rec, tile=other, scan=s) is None
             assert bench.measured_traffic(prec, rec, tile=t, scan=64 if s != 64 else 8) is None
+    leg = json.load(open(bench.TRAFFIC_FILE))["mixed"]
+    assert bench.measured_traffic("mixed", bench.TRAFFIC_FILE, tile=leg["tile"], scan=leg["scan"],
+                                  defer=1 - leg["defer_exits"]) is None
     leg = json.load(open(bench.ISSUE_FILE))["fp64"]
     assert bench.measured_valu("fp64", tile=leg["tile"], scan=leg["scan"]) == leg["valu_per_launch"]
     assert bench.measured_valu("fp64", tile=leg["tile"] - 256, scan=leg["scan"]) is None

@@ -189,16 +189,18 @@ def test_deterministic_save_and_resume():
     sim.close()
 
 
-def test_autotune_returns_argmin_and_keeps_the_run():
-    """fetd_autotune picks the tile, the scan width and then the re-sort
-    interval of least measured cost, and its trial steps are ordinary steps
-    of the run: in deterministic mode the state equals, bit for bit, that of
-    a plain run of as many steps (7 x 20 tile trials, 3 x 20 scan trials, 40
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotune_returns_argmin_and_keeps_the_run(precision):
+    """fetd_autotune picks the tile, the scan width, the exit mode (FP32
+    particles) and then the re-sort interval of least measured cost, and its
+    trial steps are ordinary steps of the run: in deterministic mode the
+    state equals, bit for bit, that of a plain run of as many steps (7 x 20
+    tile trials, 3 x 20 scan trials, FP32: 2 x 20 exit-mode trials, 40
     cadence trials)."""
     fp = _fp()
-    w = _wl(n_side=24, length=0.038, n_pairs=40_000)
-    tuned = fp.from_workload(w, spai_level=1, deterministic=True)
-    plain = fp.from_workload(w, spai_level=1, deterministic=True)
+    w = _wl(n_side=24, length=0.038, n_pairs=40_000, precision=precision)
+    tuned = fp.from_workload(w, precision=precision, spai_level=1, deterministic=True)
+    plain = fp.from_workload(w, precision=precision, spai_level=1, deterministic=True)
     r = tuned.autotune("boris", trial_steps=40, with_costs=True)
     cands = [c for c in (5, 10, 20, 40, 80, 160) if c <= 40]
     assert set(r["costs"]) == set(cands)
@@ -210,13 +212,44 @@ def test_autotune_returns_argmin_and_keeps_the_run():
     sc = r["scan_costs"]
     assert set(sc) == {64, 16, 8} and all(v > 0 for v in sc.values())
     assert r["scan"] == min(sc, key=lambda c: sc[c]) and tuned.get_scan() == r["scan"]
-    plain.step(10 * 20 + 40, "boris")
+    dc = r["defer_costs"]
+    if precision == "fp64":
+        assert dc == {}
+    else:
+        assert set(dc) == {0, 1} and all(v > 0 for v in dc.values())
+        assert r["defer_exits"] == min(dc, key=lambda c: dc[c])
+        assert tuned.get_defer_exits() == r["defer_exits"]
+    plain.step((10 if precision == "fp64" else 12) * 20 + 40, "boris")
     _assert_bitwise(_state(tuned), _state(plain))
     tuned.step(7, "boris")
     plain.step(7, "boris")
     _assert_bitwise(_state(tuned), _state(plain))
     tuned.close()
     plain.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed_f64field"])
+def test_deferred_exits_give_the_same_run(precision):
+    """Deterministic mode, FP32 particles: deferred exits (stays decided by
+    comparison with a margin, the others traced from the start after the
+    pass) give bit for bit the run with every first piece traced in the
+    pass: the same stays, the same arithmetic (hot plasma, re-sorts,
+    crossings, 40 steps); FP64 always defers and ignores the switch."""
+    fp = _fp()
+    w = _wl(n_side=24, length=0.038, n_pairs=40_000, precision="mixed")
+    a = fp.from_workload(w, precision=precision, spai_level=1, deterministic=True, resort_every=7)
+    b = fp.from_workload(w, precision=precision, spai_level=1, deterministic=True, resort_every=7)
+    assert a.get_defer_exits() == 0
+    b.set_defer_exits(1)
+    assert b.get_defer_exits() == 1
+    a.step(40, "hc")
+    b.step(40, "hc")
+    _assert_bitwise(_state(a), _state(b))
+    assert a.diagnostics()["n_segments"] == b.diagnostics()["n_segments"]
+    with pytest.raises(Exception):
+        b.set_defer_exits(2)
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("tile,scan", [(512, 64), (2048, 8), (1024, 16), (1280, 8), (1792, 16)])
