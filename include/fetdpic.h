@@ -338,11 +338,11 @@ fetd_status fetd_stage_times(fetd_sim *sim, double *ms, int64_t *launches);
  *    particle stage of every step, and set the re-sort interval K
  *    minimising (T_sort + sum_{j<K} T_particles(j)) / K over the candidates
  *    5, 10, 20, 40, 80, 160 (up to trial_steps).
- * out (or NULL) receives the three choices and the measured costs.  Every
- * trial step is an ordinary step: the simulation advances by 10 T (FP32
- * particles: 12 T) +
- * trial_steps steps, and its results do not depend on the choices beyond
- * FP64 summation order (not at all in deterministic mode). */
+ * out (or NULL) receives the choices and the measured costs.  Every trial
+ * step is an ordinary step: the simulation advances by 10 T (FP32
+ * particles: 12 T) + trial_steps steps, and its results do not depend on
+ * the choices beyond FP64 summation order (not at all in deterministic
+ * mode). */
 typedef struct {
     int32_t resort_every;       /* chosen re-sort interval K */
     int32_t tile_particles;     /* chosen tile */
@@ -379,7 +379,8 @@ fetd_status fetd_get_scan(fetd_sim *sim, int32_t *scan_lanes);
  * from their start after the pass; off, it traces every particle's first
  * piece in the pass.  On pays where few particles cross an edge per step.
  * The results are the same either way up to FP64 summation order (bit for
- * bit in deterministic mode).  on: 0 or 1, else FETD_E_ARG. */
+ * bit in deterministic mode).  on: 0 or 1, else FETD_E_ARG; an FP64 run
+ * accepts it, keeps deferring and reports 1. */
 fetd_status fetd_set_defer_exits(fetd_sim *sim, int32_t on);
 fetd_status fetd_get_defer_exits(fetd_sim *sim, int32_t *on);
 

@@ -2109,7 +2109,7 @@ fetd_status fetd_autotune(fetd_sim *s, int32_t pusher, int32_t trial_steps, fetd
         out->resort_every = best;
         out->tile_particles = s->ppt * kBlock;
         out->scan_lanes = s->scan;
-        out->defer_exits = s->defer;
+        out->defer_exits = s->fp32() ? s->defer : 1;
     }
     return FETD_OK;
 }
@@ -2136,7 +2136,7 @@ fetd_status fetd_set_defer_exits(fetd_sim *s, int32_t on)
 fetd_status fetd_get_defer_exits(fetd_sim *s, int32_t *on)
 {
     if (!s || !on) return FETD_E_ARG;
-    *on = s->defer;
+    *on = s->fp32() ? s->defer : 1;  // FP64 always defers
     return FETD_OK;
 }
 

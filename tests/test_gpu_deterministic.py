@@ -214,7 +214,7 @@ def test_autotune_returns_argmin_and_keeps_the_run(precision):
     assert r["scan"] == min(sc, key=lambda c: sc[c]) and tuned.get_scan() == r["scan"]
     dc = r["defer_costs"]
     if precision == "fp64":
-        assert dc == {}
+        assert dc == {} and r["defer_exits"] == 1 and tuned.get_defer_exits() == 1
     else:
         assert set(dc) == {0, 1} and all(v > 0 for v in dc.values())
         assert r["defer_exits"] == min(dc, key=lambda c: dc[c])
