@@ -374,10 +374,10 @@ fetd_status fetd_get_scan(fetd_sim *sim, int32_t *scan_lanes);
 /* Deferred exits (FP32 particles; FP64 always defers, and a batched step
  * never does in FP32): the particle kernel's first pass decides by
  * comparison which moves stay inside their triangle, with a margin of
- * 2^-20 above the error of the FP32 reciprocal, so the stays are exactly
- * the moves the full first piece would end inside, and traces the others
- * from their start after the pass; off, it traces every particle's first
- * piece in the pass.  On pays where few particles cross an edge per step.
+ * 2^-20 above the error of the FP32 reciprocal (every move kept is one the
+ * full first piece ends inside), and traces the others from their start
+ * after the pass, with the full first piece, so each move ends as it would
+ * otherwise; off, it traces every particle's first piece in the pass.  On pays where few particles cross an edge per step.
  * The results are the same either way up to FP64 summation order (bit for
  * bit in deterministic mode).  on: 0 or 1, else FETD_E_ARG; an FP64 run
  * accepts it, keeps deferring and reports 1. */
