@@ -807,7 +807,7 @@ fetd_status sort_all(fetd_sim *s, hipStream_t stream)
         a.elem_bytes = int(2 * rb);
         a.tile_home = s->d_tile_home + sp.bc_offset;
         a.tile = int64_t(s->ppt) * kBlock;
-        // launch_sort fills key_out with the lost key first (slots past the alive count)
+        // launch_sort writes the lost key into the slots past the live count
         hipError_t e = launch_sort(stream, a);
         if (e != hipSuccess) return s->hip_fail(e, "sort");
     }

@@ -310,21 +310,57 @@ __device__ __forceinline__ uint32_t sort_window(const SortArgs &a, int64_t blk)
     return h > kSortBack ? h - kSortBack : 0u;
 }
 
+// Runs of equal in-window bins along a wavefront.  The particles are nearly
+// sorted, so most of a wavefront's lanes share one or two bins; LDS atomics
+// to one address from many lanes are serialised, so one lane per run (its
+// head) adds the run's length.  Lanes outside the window or lost take a
+// class of their own and form runs of one.  Returns the head mask; `len` is
+// the run length on head lanes.
+__device__ __forceinline__ uint64_t bin_runs(bool in, uint32_t bin, int lane, int &len)
+{
+    const uint32_t cls = in ? bin : 0x10000u + uint32_t(lane);
+    const uint32_t prev = __shfl_up(cls, 1, 64);
+    const bool head = lane == 0 || cls != prev;
+    const uint64_t heads = __ballot(head);
+    const uint64_t after = heads & ~((2ull << lane) - 1ull);
+    len = (after ? __builtin_ctzll(after) : 64) - lane;
+    return heads;
+}
+
+// The block's kSortPer keys per thread, all loads in flight at once (past
+// the end: the lost key; the loads themselves stay in bounds).
+__device__ __forceinline__ void load_block_keys(const SortArgs &a, int64_t b0,
+                                                uint32_t (&key)[kSortPer])
+{
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+        const int64_t i = b0 + j * 256 + int(threadIdx.x);
+        key[j] = a.key_in[i < a.n ? i : a.n - 1];
+    }
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j)
+        if (b0 + j * 256 + int(threadIdx.x) >= a.n) key[j] = kLost;
+}
+
 __global__ __launch_bounds__(256) void k_sort_hist(SortArgs a)
 {
     __shared__ int32_t h[kSortBins];
     for (int t = threadIdx.x; t < kSortBins; t += 256) h[t] = 0;
     const uint32_t wb = sort_window(a, blockIdx.x);
+    const int lane = threadIdx.x & 63;
     __syncthreads();
     const int64_t b0 = int64_t(blockIdx.x) * kSortB;
+    uint32_t key[kSortPer];
+    load_block_keys(a, b0, key);
 #pragma unroll
     for (int j = 0; j < kSortPer; ++j) {
-        const int64_t i = b0 + j * 256 + int(threadIdx.x);
-        const uint32_t k = i < a.n ? a.key_in[i] : kLost;
-        if (k == kLost) continue;
+        const uint32_t k = key[j];
         const uint32_t f = k & kTriMask, bin = f - wb;
-        if (bin < uint32_t(kSortBins)) atomicAdd(&h[bin], 1);
-        else atomicAdd(a.counts + f, 1);
+        const bool in = k != kLost && bin < uint32_t(kSortBins);
+        int len;
+        const uint64_t heads = bin_runs(in, bin, lane, len);
+        if (in && ((heads >> lane) & 1ull)) atomicAdd(&h[bin], len);
+        else if (k != kLost && !in) atomicAdd(a.counts + f, 1);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < kSortBins; t += 256)
@@ -407,17 +443,27 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs a)
     const int64_t b0 = int64_t(blockIdx.x) * kSortB;
     // ranks within the block's bins (outside the window: a direct global slot)
     int32_t bin[kSortPer], rank[kSortPer];
+    uint32_t key[kSortPer];
+    load_block_keys(a, b0, key);
 #pragma unroll
     for (int j = 0; j < kSortPer; ++j) {
-        const int64_t i = b0 + j * 256 + tid;
-        const uint32_t k = i < a.n ? a.key_in[i] : kLost;
+        const uint32_t k = key[j];
+        const uint32_t f = k & kTriMask, b = f - wb;
+        const bool in = k != kLost && b < uint32_t(kSortBins);
+        // one LDS atomic per run of equal bins; the run's lanes take
+        // consecutive ranks after the head's
+        int len;
+        const uint64_t heads = bin_runs(in, b, lane, len);
+        const int head = 63 - __builtin_clzll(heads & ((2ull << lane) - 1ull));
+        int base = 0;
+        if (in && head == lane) base = atomicAdd(&cnt[b], len);
+        base = __shfl(base, head, 64);
         bin[j] = -1;
         rank[j] = -1;
         if (k == kLost) continue;
-        const uint32_t f = k & kTriMask, b = f - wb;
-        if (b < uint32_t(kSortBins)) {
+        if (in) {
             bin[j] = int32_t(b);
-            rank[j] = atomicAdd(&cnt[b], 1);
+            rank[j] = base + (lane - head);
         } else {
             bin[j] = -2;
             rank[j] = atomicAdd(&n_out, 1);
@@ -444,14 +490,20 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs a)
     __syncthreads();
     int32_t before = incl - run;
     for (int w = 0; w < wv; ++w) before += wsum[w];
+    // (the four reservations are all in flight before their results are used)
+    int32_t off4[4] = {0, 0, 0, 0}, at4[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int b = 4 * tid + q;
         loc[b] = before;
         before += c4[q];
-        cnt[b] = c4[q] ? a.offsets[wb + uint32_t(b)] + atomicAdd(a.counts + wb + uint32_t(b), c4[q])
-                       : 0;
+        if (c4[q]) {
+            off4[q] = a.offsets[wb + uint32_t(b)];
+            at4[q] = atomicAdd(a.counts + wb + uint32_t(b), c4[q]);
+        }
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cnt[4 * tid + q] = off4[q] + at4[q];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kSortPer; ++j) {
@@ -462,17 +514,63 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs a)
     }
     __syncthreads();
     // copy out in slot order: in-window slots [0, n_in), outside ones at the top
+    // (every slot's loads are in flight before the stores, which might
+    // alias the inputs for all the compiler knows)
     const int n_in = wsum[0] + wsum[1] + wsum[2] + wsum[3];
     const int nout = n_out;
-    for (int s = tid; s < kSortB; s += 256) {
-        if (s >= n_in && s < kSortB - nout) continue;
-        const int64_t src = b0 + s_src[s];
-        const int64_t dst = s_dst[s];
-        a.key_out[dst] = a.key_in[src];
-        reinterpret_cast<E *>(a.lam_out)[dst] = reinterpret_cast<const E *>(a.lam_in)[src];
-        reinterpret_cast<E *>(a.u_out)[dst] = reinterpret_cast<const E *>(a.u_in)[src];
-        a.pid_out[dst] = a.pid_in[src];
+    const E *lam_in = reinterpret_cast<const E *>(a.lam_in);
+    const E *u_in = reinterpret_cast<const E *>(a.u_in);
+    E *lam_out = reinterpret_cast<E *>(a.lam_out);
+    E *u_out = reinterpret_cast<E *>(a.u_out);
+    constexpr int kGroup = 8;
+    static_assert(kSortPer % kGroup == 0, "copy groups");
+#pragma unroll
+    for (int g = 0; g < kSortPer; g += kGroup) {
+        bool on[kGroup];
+        int32_t dst[kGroup];
+        uint32_t kv[kGroup], pv[kGroup];
+        E lv[kGroup], uv[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            // loads without a branch (an empty slot reads the block's first
+            // particle and stores nothing), so the group's loads stay in flight
+            const int s = (g + q) * 256 + tid;
+            on[q] = s < n_in || s >= kSortB - nout;
+            const int64_t src = b0 + (on[q] ? s_src[s] : 0);
+            dst[q] = s_dst[s];
+            kv[q] = a.key_in[src];
+            lv[q] = lam_in[src];
+            uv[q] = u_in[src];
+            pv[q] = a.pid_in[src];
+        }
+        // every loaded value counts as used here, so the compiler cannot sink
+        // the loads into the conditional stores below, one slot at a time
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q)
+            asm volatile("" ::"v"(kv[q]), "v"(pv[q]), "v"(lv[q].x), "v"(lv[q].y), "v"(uv[q].x),
+                         "v"(uv[q].y));
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            if (!on[q]) continue;
+            a.key_out[dst[q]] = kv[q];
+            lam_out[dst[q]] = lv[q];
+            u_out[dst[q]] = uv[q];
+            a.pid_out[dst[q]] = pv[q];
+        }
     }
+}
+
+// p[i] = v for offsets start[0] <= i < n (a grid-stride loop over a fixed
+// grid: the start is known only on the device).
+constexpr int kTailBlocks = 1024;
+__global__ __launch_bounds__(256) void k_fill_tail(uint32_t *__restrict__ p,
+                                                   const int32_t *__restrict__ start, int64_t n,
+                                                   uint32_t v)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(*start) + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += stride)
+        p[i] = v;
 }
 
 // Home triangle of every tile of the sorted segment (its first particle).
@@ -671,8 +769,6 @@ hipError_t launch_sort(hipStream_t s, const SortArgs &a)
     // fill kernels rather than memsets, so the sort can sit in a captured graph
     hipError_t err = launch_fill_u32(s, reinterpret_cast<uint32_t *>(a.counts), 0u, a.nf + 1);
     if (err != hipSuccess) return err;
-    err = launch_fill_u32(s, a.key_out, kLost, a.n);
-    if (err != hipSuccess) return err;
     if (a.n > 0)
         hipLaunchKernelGGL(k_sort_hist, dim3(grid_for(a.n, kSortB)), dim3(256), 0, s, a);
     const int nb = int((a.nf + 1023) / 1024);
@@ -680,6 +776,10 @@ hipError_t launch_sort(hipStream_t s, const SortArgs &a)
                        a.block_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, nb, a.block_sums);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, s, a.nf, a.offsets, a.block_sums, nb);
+    // slots past the live count (offsets[nf]) hold the lost key
+    if (a.n > 0)
+        hipLaunchKernelGGL(k_fill_tail, dim3(kTailBlocks), dim3(256), 0, s, a.key_out,
+                           a.offsets + a.nf, a.n, kLost);
     err = launch_fill_u32(s, reinterpret_cast<uint32_t *>(a.counts), 0u, a.nf + 1);
     if (err != hipSuccess) return err;
     if (a.n > 0) {
